@@ -1,0 +1,218 @@
+/*
+ * lgs_lbm.h -- C ABI of the MI355X liquid-gas-solid lattice Boltzmann library.
+ *
+ * One call of lbm_step advances every lattice instance of a context by one
+ * time step of the method of Bogner & Ruede, "Liquid-gas-solid flows with
+ * lattice Boltzmann: Simulation of floating bodies":
+ *
+ *   1. body remap          (Sec. 2.3 cell-centre mapping; Sec. 2.4 conversions
+ *                           into / out of obstacle on B(x))       -- if a body moved
+ *   2. stream + collide    (Sec. 2.1 Eq. stream and the collide step with the
+ *                           force term of Eq. forceterm; Sec. 2.2 mass exchange
+ *                           and Eq. reconstruct; Sec. 2.3 Eq. noslip), fused with
+ *      momentum exchange   (Eqs. momentumexchange, momentuminterface, netforce,
+ *                           torque) on the same pass
+ *   3. interface conversions (Sec. 2.2, thresholds -eps / 1+eps)
+ *
+ * Units are lattice units (cell size 1, time step 1).  Cell (x, y, z) spans
+ * [x, x+1] x [y, y+1] x [z, z+1]; its centre is (x+.5, y+.5, z+.5) (Sec. 2.1).
+ * Faces that are not periodic are static no-slip walls just outside the
+ * lattice (halfway bounce-back).
+ *
+ * Host arrays exchanged through lbm_read_fields / lbm_write_fields are laid
+ * out x fastest: scalars [nz][ny][nx], populations [19][nz][ny][nx] in the
+ * D3Q19 order of the paper's Fig. d3q19 caption: C, W, E, N, S, T, B, TW, TE,
+ * TN, TS, NW, NE, SW, SE, BW, BE, BN, BS (E = +x, N = +y, T = +z).  Flags are
+ * one byte per cell: bits 0-1 type (0 gas, 1 liquid, 2 interface,
+ * 3 obstacle), bits 2-5 owning body of an obstacle cell.
+ *
+ * Every function returns an int32 status (LBM_OK = 0, negative on error) and
+ * leaves its outputs untouched on error; lbm_last_error() gives a
+ * thread-local message.  No exception crosses the ABI.  A context is used by
+ * one host thread; all its device work is ordered on one HIP stream.
+ */
+#ifndef LGS_LBM_H
+#define LGS_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LBM_OK = 0,
+    LBM_ERR_INVALID = -1,  /* bad argument (message says which)              */
+    LBM_ERR_NOMEM = -2,    /* workspace too small or allocation failed       */
+    LBM_ERR_DEVICE = -3,   /* a HIP call failed                              */
+    LBM_ERR_UNSTABLE = -4, /* non-finite values or a list overflow detected  */
+    LBM_ERR_STATE = -5     /* call not valid in the context's current state  */
+};
+
+/* Storage of the populations.  All variants store the deviation f_i - w_i
+ * from the rest weights (w_i of the caption of Fig. d3q19) and collide in
+ * FP32: FP32 stores it as float, FP16 as binary16 scaled by fp16_scale (a
+ * power of two), BF16 as bfloat16 unscaled. */
+enum { LBM_FP32 = 0, LBM_FP16_DEV = 1, LBM_BF16_DEV = 2 };
+
+enum { LBM_PERIODIC_X = 1, LBM_PERIODIC_Y = 2, LBM_PERIODIC_Z = 4 };
+
+enum {
+    LBM_FIELD_POP = 1,   /* f_i (absolute, not the stored deviation), 19 per cell */
+    LBM_FIELD_FLAGS = 2, /* one byte per cell (write: bits 0-5 as above)         */
+    LBM_FIELD_PHI = 3,   /* fill level phi (Sec. 2.2)                             */
+    LBM_FIELD_MASS = 4,  /* liquid mass m of interface cells (Sec. 2.2)           */
+    LBM_FIELD_RHO = 5,   /* density sum_i f_i (read only)                         */
+    LBM_FIELD_VEL = 6    /* velocity sum_i c_i f_i / rho, 3 per cell [3][z][y][x] (read only) */
+};
+enum { LBM_F64 = 0, LBM_F32 = 1, LBM_U8 = 2 };
+
+/* Parts of one step, for phase-isolated testing with lbm_step_phases. */
+enum { LBM_PHASE_REMAP = 1, LBM_PHASE_SWEEP = 2, LBM_PHASE_CONVERT = 4, LBM_PHASE_ALL = 7 };
+
+/* Gas-side reconstruction set in interface cells (Sec. 2.2, Eq. reconstruct).
+ * The normal n = -grad(phi) (central differences over the 6 axis
+ * neighbours; liquid 1, gas 0, interface phi, obstacle / wall: own phi)
+ * points into the gas; a link i >= 1 counts as "from the gas side" when
+ * c_i.n < -1e-3 |n|_1.
+ *   0: links with a gas source, plus links from the gas side      (default)
+ *   1: links with a gas source only
+ *   2: links with a gas source, plus links with c_i.n <= +1e-3 |n|_1
+ *      (the printed "c_i^T n <= 0", tangential links included)            */
+enum { LBM_RECON_GAS_SIDE = 0, LBM_RECON_GAS_ONLY = 1, LBM_RECON_PAPER_LE = 2 };
+
+#define LBM_MAX_BODIES 16
+
+typedef struct lbm_config {
+    int32_t nx, ny, nz;        /* lattice cells                                      */
+    int32_t storage;           /* LBM_FP32 / LBM_FP16_DEV / LBM_BF16_DEV              */
+    double tau;                /* BGK relaxation time, > 0.5 (Sec. 2.1)                */
+    double accel[3];           /* body acceleration a (gravity = {0, 0, -g}) (Eq. forceterm) */
+    double rho_gas;            /* gas density rho_G, p_G = rho_G / 3 (Sec. 2.2)        */
+    double eps;                /* conversion threshold epsilon (Sec. 2.2), >= 0        */
+    double fill_height;        /* H: initial liquid below z = H (cells of fill
+                                  clamp(H - z, 0, 1)), hydrostatic density
+                                  rho = rho_G - 3 a_z (H - z_c) + noise             */
+    double init_ux_surface;    /* u_s: initial u_x = u_s z_c (2H - z_c) / H^2 (0 = rest) */
+    uint32_t periodic;         /* LBM_PERIODIC_* bits; other faces are walls          */
+    int32_t recon_mode;        /* LBM_RECON_*                                         */
+    uint64_t seed;             /* initial density noise: SplitMix64(seed ^ cell index) */
+    double noise_amp;          /* noise amplitude A: rho += A (2U - 1)                 */
+    double fp16_scale;         /* power of two (FP16 storage); 0 = default 4096        */
+    int32_t max_bodies;        /* bodies per instance, 0 .. LBM_MAX_BODIES             */
+    int32_t reserved;
+} lbm_config;
+
+/* A cuboid rigid body (Sec. 2.3).  A cell is an obstacle cell of the body iff
+ * its centre c satisfies |R^T (c - pos)|_k <= half_ext[k] for k = 0..2, with R
+ * the rotation of `quat` and the minimum image of c - pos on periodic axes
+ * (evaluated in FP64 without fused multiply-add).  Moving-wall velocity at a
+ * point p: vel + omega x (p - pos). */
+typedef struct lbm_body {
+    double half_ext[3]; /* half extents in the body frame (cells)                  */
+    double pos[3];      /* centre of gravity o, lattice coordinates               */
+    double quat[4];     /* orientation w, x, y, z (unit)                          */
+    double vel[3];      /* world frame, cells per step                            */
+    double omega[3];    /* world frame, radians per step                          */
+    double density;     /* rho_s relative to the liquid's 1                       */
+    uint32_t fixed;     /* 1: the caller holds the pose (moves it only through
+                           lbm_set_body); 0: free -- after every full step the
+                           library advances it with lbm_integrate_body, fed with
+                           the mean of this and the previous step's fluid force
+                           and torque, on the DOFs of dof_mask                   */
+    uint32_t dof_mask;  /* free bodies: bits 0-2 translation x,y,z, 3-5 rotation */
+} lbm_body;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Device bytes needed for n_inst instances described by cfgs[0..n_inst-1]. */
+int32_t lbm_workspace_size(const lbm_config* cfgs, int32_t n_inst, size_t* bytes);
+
+/* Create a context and initialise every instance (basin of lbm_config, no
+ * body yet).  d_workspace: device memory of at least lbm_workspace_size bytes
+ * owned by the caller (e.g. a torch uint8 tensor kept alive for the context's
+ * lifetime), or NULL to let the library allocate and own it.  hip_stream: the
+ * hipStream_t all work is ordered on (NULL = null stream).  Checks: tau > 0.5,
+ * max_k n_k |a_k| < 0.1 c_s^2 (the incompressibility bound of Sec. 2.1),
+ * storage, sizes, eps >= 0, rho_gas > 0. */
+int32_t lbm_create(const lbm_config* cfgs, int32_t n_inst, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                   lbm_ctx** out);
+int32_t lbm_destroy(lbm_ctx* ctx);
+
+/* Set (add or move) body `body` of instance `inst`.  The pose takes effect at
+ * the next step's remap phase; the first set of a body maps it (covered liquid
+ * mass goes to the ledger).  Checks: body inside the non-periodic extent with
+ * one free cell of margin, surface speed < 1 cell per step (Sec. 2.4 assumes
+ * obstacles move less than a cell per step), moves by less than one cell
+ * since its last mapping, and no overlap (with margin) with another body. */
+int32_t lbm_set_body(lbm_ctx* ctx, int32_t inst, int32_t body, const lbm_body* b);
+int32_t lbm_get_body(lbm_ctx* ctx, int32_t inst, int32_t body, lbm_body* b);
+
+/* Advance all instances by nsteps full steps (remap if needed, sweep,
+ * conversions, then the host update of free bodies).  Asynchronous on the
+ * context's stream unless a free body exists: then every step ends with a
+ * stream synchronisation and one small device-to-host copy of the forces. */
+int32_t lbm_step(lbm_ctx* ctx, int32_t nsteps);
+
+/* One step restricted to the phases in phase_mask (LBM_PHASE_*), for tests.
+ * LBM_PHASE_CONVERT without LBM_PHASE_SWEEP first scans for the interface
+ * cells past the thresholds. */
+int32_t lbm_step_phases(lbm_ctx* ctx, int32_t phase_mask);
+
+/* Fluid-on-body force and torque about the body's centre, world frame, of the
+ * last completed sweep (FP64 sums).  Synchronises the stream. */
+int32_t lbm_body_forces(lbm_ctx* ctx, int32_t inst, int32_t body, double force[3], double torque[3]);
+
+/* Copy a field of one instance to / from host memory (synchronous).
+ * bytes must equal cells * components * sizeof(dtype).  POP is the absolute
+ * f_i; gas and obstacle cells hold unspecified populations. */
+int32_t lbm_read_fields(lbm_ctx* ctx, int32_t inst, int32_t field, int32_t dtype, void* host_dst, size_t bytes);
+int32_t lbm_write_fields(lbm_ctx* ctx, int32_t inst, int32_t field, int32_t dtype, const void* host_src,
+                         size_t bytes);
+
+/* Liquid mass sum_LIQ rho + sum_IF m (FP64 reduction on the device) and the
+ * ledger: mass added to the fluid minus mass removed by remaps and
+ * undistributable conversion excess.  total - ledger is conserved up to
+ * round-off and moving-wall mass fluxes.  Synchronises. */
+int32_t lbm_mass_total(lbm_ctx* ctx, int32_t inst, double* total, double* ledger);
+int32_t lbm_set_ledger(lbm_ctx* ctx, int32_t inst, double ledger);
+
+/* Counts of the last conversion phase: filled, emptied, gas->interface,
+ * liquid->interface.  Synchronises. */
+int32_t lbm_conversion_counts(lbm_ctx* ctx, int32_t inst, int64_t counts[4]);
+
+/* Number of liquid cells with a gas neighbour (0 for a closed interface
+ * layer, Sec. 2.2).  Synchronises. */
+int32_t lbm_liq_gas_contacts(lbm_ctx* ctx, int32_t inst, int64_t* contacts);
+
+/* Wait for all work of the context. */
+int32_t lbm_sync(lbm_ctx* ctx);
+
+/* Kernel timing: while enabled, HIP events bracket the two sweep kernels of
+ * every step (on the context's stream).  lbm_kernel_time returns the summed
+ * duration in milliseconds and the number of timed steps since the last
+ * enable (synchronises).  Kernel ids: 0 = bulk sweep (liquid cells whose
+ * sources are fluid or static wall), 1 = boundary sweep (interface cells and
+ * liquid cells next to gas or a body), 2 = both. */
+int32_t lbm_enable_kernel_timing(lbm_ctx* ctx, int32_t enable);
+int32_t lbm_kernel_time(lbm_ctx* ctx, int32_t kernel, double* total_ms, int64_t* launches);
+
+/* Number of cells the last sweep of an instance handled in the boundary
+ * kernel (synchronises). */
+int32_t lbm_boundary_cells(lbm_ctx* ctx, int32_t inst, int64_t* n);
+
+/* Host rigid-body update (the paper couples to a rigid-body engine; this is
+ * a plain semi-implicit Euler step, dt = 1): mass M = density * 8 hx hy hz,
+ * V += (F + M a) / M on translational DOFs (dof_mask bits 0-2),
+ * Omega += I_SS^-1 T_S on rotational DOFs S (bits 3-5; I the world-frame
+ * cuboid inertia about the centre), pos += V, quat rotated by Omega. */
+int32_t lbm_integrate_body(const lbm_body* in, const double force[3], const double torque[3],
+                           const double accel[3], uint32_t dof_mask, lbm_body* out);
+
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LGS_LBM_H */

@@ -100,6 +100,8 @@ typedef struct {
     int fixed;
     double R[9]; /* body -> world rotation, row major */
     double force[3], torque[3];
+    double fprev[3], tprev[3]; /* previous step's force / torque (coupled steps) */
+    int have_prev;
 } ob_body;
 
 typedef struct {
@@ -381,6 +383,7 @@ int ob_set_body(ob_state *s, int k, const double *half, const double *pos, const
     quat_to_R(b->quat, b->R);
     b->active = 1;
     b->moved = 1;
+    b->have_prev = 0;
     if (k + 1 > s->nb) s->nb = k + 1;
     return 0;
 }
@@ -904,6 +907,45 @@ int ob_step(ob_state *s, int nsteps, int phase_mask) {
             sweep(s);
         }
         if (phase_mask & 4) convert(s);
+    }
+    return 0;
+}
+
+/* Steps with free bodies: after every full step each body with a non-zero
+ * DOF mask is advanced by the host update below, fed with the mean of this
+ * and the previous step's fluid force and torque (the first step uses its own
+ * force), and set again for the next step's remap. */
+int ob_integrate_body(const double *half, const double *pos, const double *quat, const double *vel,
+                      const double *omega, double density, const double *F, const double *T,
+                      const double *a, int dof_mask, double *pos_out, double *quat_out, double *vel_out,
+                      double *omega_out);
+
+int ob_step_coupled(ob_state *s, int nsteps, const int *dof_masks) {
+    for (int n = 0; n < nsteps; ++n) {
+        ob_step(s, 1, 7);
+        for (int k = 0; k < s->nb; ++k) {
+            ob_body *b = &s->b[k];
+            if (!b->active || !dof_masks[k]) continue;
+            double F[3], T[3];
+            for (int j = 0; j < 3; ++j) {
+                F[j] = b->have_prev ? 0.5 * (b->force[j] + b->fprev[j]) : b->force[j];
+                T[j] = b->have_prev ? 0.5 * (b->torque[j] + b->tprev[j]) : b->torque[j];
+                b->fprev[j] = b->force[j];
+                b->tprev[j] = b->torque[j];
+            }
+            b->have_prev = 1;
+            double p[3], q[4], v[3], w[3];
+            if (ob_integrate_body(b->half, b->pos, b->quat, b->vel, b->omega, b->density, F, T, s->a, dof_masks[k], p,
+                                  q, v, w))
+                return -1;
+            double fp[3] = {b->fprev[0], b->fprev[1], b->fprev[2]}, tp[3] = {b->tprev[0], b->tprev[1], b->tprev[2]};
+            ob_set_body(s, k, b->half, p, q, v, w, b->density, b->fixed);
+            for (int j = 0; j < 3; ++j) {
+                b->fprev[j] = fp[j];
+                b->tprev[j] = tp[j];
+            }
+            b->have_prev = 1;
+        }
     }
     return 0;
 }

@@ -51,6 +51,8 @@ def lib():
         L.ob_liq_gas_contacts.restype = C.c_long
         L.ob_liq_gas_contacts.argtypes = [C.c_void_p]
         L.ob_last_conversions.argtypes = [C.c_void_p, C.POINTER(C.c_long)]
+        L.ob_step_coupled.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int)]
+        L.ob_step_coupled.restype = C.c_int
         for nm in ("ob_get_f", "ob_set_f", "ob_get_mass", "ob_set_mass", "ob_get_phi", "ob_set_phi"):
             getattr(L, nm).argtypes = [C.c_void_p, _dp]
         L.ob_get_flags.argtypes = [C.c_void_p, _u8p]
@@ -156,6 +158,14 @@ class Oracle:
 
     def step(self, n=1, phases=PH_ALL):
         lib().ob_step(self._h, int(n), int(phases))
+
+    def step_coupled(self, n, dof_masks):
+        """n full steps; bodies with a non-zero DOF mask are advanced after
+        every step by the host update fed with the mean of the current and the
+        previous step's force and torque."""
+        m = (C.c_int * 16)(*([int(v) for v in dof_masks] + [0] * (16 - len(dof_masks))))
+        if lib().ob_step_coupled(self._h, int(n), m) != 0:
+            raise ValueError("step_coupled: invalid body")
 
     def body_forces(self, k=0):
         F, T = np.zeros(3), np.zeros(3)

@@ -1,0 +1,846 @@
+// lgs_api.hip -- host side of the C ABI declared in include/lgs_lbm.h.
+//
+// A context owns n instances laid out back to back in one device workspace
+// (caller-provided, e.g. a torch tensor, or allocated here).  Kernels receive
+// an Inst descriptor by value.  Steps alternate between two population
+// lattices ("parity"); per-step counters and force accumulators are kept per
+// parity so that no memset is ever needed inside a step.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lgs_internal.h"
+
+using namespace lgs;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_OK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return fail(LBM_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t storage_bytes(int storage) { return storage == LBM_FP32 ? 4 : 2; }
+
+struct InstHost {
+    lbm_config cfg;
+    Inst dev;
+    DevBody bodies[MAXB];
+    lbm_body desc[MAXB];  // caller's description (free bodies are integrated from it)
+    double fprev[MAXB][6];
+    bool have_prev[MAXB];
+    bool mapped[MAXB];
+    double mapped_pos[MAXB][3];
+    int region_side;
+    bool need_remap;
+    size_t offset, bytes;
+};
+
+// Byte layout of one instance inside the workspace.
+size_t layout(const lbm_config& c, Inst* I, char* base) {
+    const size_t N = (size_t)c.nx * c.ny * c.nz;
+    const size_t sb = storage_bytes(c.storage);
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        char* p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    char* p0 = take(Q * N * sb);
+    char* p1 = take(Q * N * sb);
+    char* fl = take(N);
+    char* ph0 = take(4 * N);
+    char* ph1 = take(4 * N);
+    char* mh = take(4 * N);
+    char* ml = take(4 * N);
+    char* sh = take(4 * N);
+    char* ax = take(4 * N);
+    char* ru = take(N);
+    char* cl = take(4 * (N / 32 + 1));
+    char* cl2 = take(4 * (N / 32 + 1));
+    char* l0 = take(4 * N);
+    char* l1 = take(4 * N);
+    char* l2 = take(4 * N);
+    char* l3 = take(4 * N);
+    char* l4 = take(4 * N);
+    char* ct = take(sizeof(Ctl));
+    char* bd = take(sizeof(DevBody) * MAXB);
+    if (I) {
+        I->pop[0] = p0;
+        I->pop[1] = p1;
+        I->flags = (uint8_t*)fl;
+        I->phi[0] = (float*)ph0;
+        I->phi[1] = (float*)ph1;
+        I->m_hi = (float*)mh;
+        I->m_lo = (float*)ml;
+        I->share = (float*)sh;
+        I->aux = (float*)ax;
+        I->rule = (uint8_t*)ru;
+        I->claim = (uint32_t*)cl;
+        I->claim2 = (uint32_t*)cl2;
+        I->cand = (int*)l0;
+        I->newg = (int*)l1;
+        I->newl = (int*)l2;
+        I->recv = (int*)l3;
+        I->bnd = (int*)l4;
+        I->ctl = (Ctl*)ct;
+        I->bodies = (DevBody*)bd;
+        I->list_cap = (int)N;
+    }
+    return off;
+}
+
+int validate(const lbm_config& c, int k) {
+    char buf[256];
+    auto bad = [&](const char* what) {
+        snprintf(buf, sizeof buf, "instance %d: %s", k, what);
+        return fail(LBM_ERR_INVALID, buf);
+    };
+    if (c.nx <= 0 || c.ny <= 0 || c.nz <= 0) return bad("lattice sizes must be positive");
+    if ((double)c.nx * c.ny * c.nz > 2.0e9 / Q) return bad("lattice too large for 32-bit indexing");
+    if (!(c.tau > 0.5)) return bad("tau must exceed 1/2 (positive viscosity)");
+    if (c.storage != LBM_FP32 && c.storage != LBM_FP16_DEV && c.storage != LBM_BF16_DEV) return bad("unknown storage");
+    if (!(c.rho_gas > 0.0)) return bad("rho_gas must be positive");
+    if (!(c.eps >= 0.0)) return bad("eps must be >= 0");
+    if (c.recon_mode < 0 || c.recon_mode > 2) return bad("unknown recon_mode");
+    if (c.max_bodies < 0 || c.max_bodies > MAXB) return bad("max_bodies out of range");
+    const double n[3] = {(double)c.nx, (double)c.ny, (double)c.nz};
+    for (int a = 0; a < 3; ++a)
+        if (!(n[a] * std::fabs(c.accel[a]) < 0.1 / 3.0))
+            return bad("acceleration too large for the lattice (l_k |a_k| must be << c_s^2)");
+    if (c.storage == LBM_FP16_DEV) {
+        double s = c.fp16_scale == 0.0 ? 4096.0 : c.fp16_scale;
+        int e;
+        if (!(s > 0.0) || std::frexp(s, &e) != 0.5) return bad("fp16_scale must be a power of two");
+    }
+    return LBM_OK;
+}
+
+void quat_to_R(const double q[4], double R[9]) {
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1.0 - 2.0 * (y * y + z * z);
+    R[1] = 2.0 * (x * y - w * z);
+    R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);
+    R[4] = 1.0 - 2.0 * (x * x + z * z);
+    R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);
+    R[7] = 2.0 * (y * z + w * x);
+    R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+}  // namespace
+
+struct lbm_ctx {
+    int n_inst = 0;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool own_ws = false;
+    int parity = 0;
+    int last_parity = 0;
+    bool have_forces = false;
+    std::vector<InstHost> inst;
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;  // begin/end pairs of timed sweeps
+    size_t ev_used = 0;
+    double* pinned = nullptr;  // per instance: MAXB x 6 forces of the last step
+};
+
+static hipEvent_t next_event(lbm_ctx* c) {
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->ev_pool.push_back(e);
+    }
+    return c->ev_pool[c->ev_used++];
+}
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+int32_t lbm_workspace_size(const lbm_config* cfgs, int32_t n_inst, size_t* bytes) {
+    if (!cfgs || n_inst <= 0 || !bytes) return fail(LBM_ERR_INVALID, "workspace_size: bad arguments");
+    size_t tot = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        int rc = validate(cfgs[k], k);
+        if (rc) return rc;
+        tot += layout(cfgs[k], nullptr, nullptr);
+    }
+    *bytes = tot;
+    return LBM_OK;
+}
+
+int32_t lbm_create(const lbm_config* cfgs, int32_t n_inst, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                   lbm_ctx** out) {
+    if (!out) return fail(LBM_ERR_INVALID, "create: out is NULL");
+    size_t need = 0;
+    int rc = lbm_workspace_size(cfgs, n_inst, &need);
+    if (rc) return rc;
+    lbm_ctx* c = new lbm_ctx();
+    c->n_inst = n_inst;
+    c->stream = (hipStream_t)hip_stream;
+    if (d_workspace) {
+        if (ws_bytes < need) {
+            delete c;
+            return fail(LBM_ERR_NOMEM, "create: workspace smaller than lbm_workspace_size");
+        }
+        if (((uintptr_t)d_workspace) & 255) {
+            delete c;
+            return fail(LBM_ERR_INVALID, "create: workspace must be 256-byte aligned");
+        }
+        c->ws = (char*)d_workspace;
+        c->ws_bytes = ws_bytes;
+    } else {
+        void* p = nullptr;
+        if (hipMalloc(&p, need) != hipSuccess) {
+            delete c;
+            return fail(LBM_ERR_NOMEM, "create: hipMalloc of the workspace failed");
+        }
+        c->ws = (char*)p;
+        c->ws_bytes = need;
+        c->own_ws = true;
+    }
+    c->inst.resize(n_inst);
+    if (hipHostMalloc((void**)&c->pinned, sizeof(double) * MAXB * 6 * n_inst) != hipSuccess) {
+        if (c->own_ws) (void)hipFree(c->ws);
+        delete c;
+        return fail(LBM_ERR_NOMEM, "create: pinned host buffer");
+    }
+    size_t off = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        InstHost& h = c->inst[k];
+        memset(&h, 0, sizeof(InstHost));
+        h.cfg = cfgs[k];
+        if (h.cfg.storage == LBM_FP16_DEV && h.cfg.fp16_scale == 0.0) h.cfg.fp16_scale = 4096.0;
+        Inst& I = h.dev;
+        h.offset = off;
+        h.bytes = layout(h.cfg, &I, c->ws + off);
+        off += h.bytes;
+        I.nx = h.cfg.nx;
+        I.ny = h.cfg.ny;
+        I.nz = h.cfg.nz;
+        I.N = h.cfg.nx * h.cfg.ny * h.cfg.nz;
+        I.periodic = h.cfg.periodic & 7;
+        I.recon_mode = h.cfg.recon_mode;
+        I.storage = h.cfg.storage;
+        I.nbodies = 0;
+        I.omega = (float)(1.0 / h.cfg.tau);
+        I.ax = (float)h.cfg.accel[0];
+        I.ay = (float)h.cfg.accel[1];
+        I.az = (float)h.cfg.accel[2];
+        I.rho_g = (float)h.cfg.rho_gas;
+        I.scale = h.cfg.storage == LBM_FP16_DEV ? (float)h.cfg.fp16_scale : 1.f;
+        I.inv_scale = 1.f / I.scale;
+        I.eps = h.cfg.eps;
+        const size_t N = (size_t)I.N;
+        HIP_OK(hipMemsetAsync(I.ctl, 0, sizeof(Ctl), c->stream));
+        HIP_OK(hipMemsetAsync(I.bodies, 0, sizeof(DevBody) * MAXB, c->stream));
+        HIP_OK(hipMemsetAsync(I.claim, 0, 4 * (N / 32 + 1), c->stream));
+        HIP_OK(hipMemsetAsync(I.claim2, 0, 4 * (N / 32 + 1), c->stream));
+        HIP_OK(hipMemsetAsync(I.rule, 0, N, c->stream));
+        launch_init(I, h.cfg, c->stream);
+        HIP_OK(hipGetLastError());
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+int32_t lbm_destroy(lbm_ctx* c) {
+    if (!c) return LBM_OK;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    if (c->own_ws) (void)hipFree(c->ws);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    delete c;
+    return LBM_OK;
+}
+
+static int check_inst(lbm_ctx* c, int inst) {
+    if (!c) return fail(LBM_ERR_INVALID, "context is NULL");
+    if (inst < 0 || inst >= c->n_inst) return fail(LBM_ERR_INVALID, "instance index out of range");
+    return LBM_OK;
+}
+
+static int set_body_impl(lbm_ctx* c, int inst, int k, const lbm_body* b, bool keep_prev);
+
+int32_t lbm_set_body(lbm_ctx* c, int32_t inst, int32_t k, const lbm_body* b) {
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    return set_body_impl(c, inst, k, b, false);
+}
+
+static int set_body_impl(lbm_ctx* c, int inst, int k, const lbm_body* b, bool keep_prev) {
+    InstHost& h = c->inst[inst];
+    if (!b || k < 0 || k >= MAXB || k >= std::max(1, h.cfg.max_bodies))
+        return fail(LBM_ERR_INVALID, "set_body: body index out of range (raise max_bodies)");
+    const double n[3] = {(double)h.cfg.nx, (double)h.cfg.ny, (double)h.cfg.nz};
+    DevBody d;
+    memset(&d, 0, sizeof d);
+    for (int a = 0; a < 3; ++a) {
+        if (!(b->half_ext[a] > 0.0)) return fail(LBM_ERR_INVALID, "set_body: half extents must be positive");
+        double p = b->pos[a];
+        if (h.cfg.periodic & (1 << a)) p = p - n[a] * std::floor(p / n[a]);
+        d.pos[a] = p;
+        d.half[a] = b->half_ext[a];
+        d.vel[a] = b->vel[a];
+        d.omega[a] = b->omega[a];
+    }
+    const double qn = std::sqrt(b->quat[0] * b->quat[0] + b->quat[1] * b->quat[1] + b->quat[2] * b->quat[2] +
+                                b->quat[3] * b->quat[3]);
+    if (!(std::fabs(qn - 1.0) < 1e-6)) return fail(LBM_ERR_INVALID, "set_body: quaternion must be unit");
+    quat_to_R(b->quat, d.R);
+    for (int a = 0; a < 3; ++a)
+        d.ext[a] = std::fabs(d.R[a * 3 + 0]) * d.half[0] + std::fabs(d.R[a * 3 + 1]) * d.half[1] +
+                   std::fabs(d.R[a * 3 + 2]) * d.half[2];
+    const double Rc = std::sqrt(d.half[0] * d.half[0] + d.half[1] * d.half[1] + d.half[2] * d.half[2]);
+    // inside the non-periodic extent with a free cell of margin
+    for (int a = 0; a < 3; ++a) {
+        if (h.cfg.periodic & (1 << a)) {
+            if (2.0 * d.ext[a] >= n[a] && !(d.half[a] >= 0.5 * n[a] && d.ext[a] == d.half[a]))
+                return fail(LBM_ERR_INVALID, "set_body: body wider than a periodic axis");
+            continue;
+        }
+        if (d.pos[a] - d.ext[a] < 1.0 || d.pos[a] + d.ext[a] > n[a] - 1.0)
+            return fail(LBM_ERR_INVALID, "set_body: body must stay one cell inside the walls");
+    }
+    const double speed = std::sqrt(d.vel[0] * d.vel[0] + d.vel[1] * d.vel[1] + d.vel[2] * d.vel[2]) +
+                         std::sqrt(d.omega[0] * d.omega[0] + d.omega[1] * d.omega[1] + d.omega[2] * d.omega[2]) * Rc;
+    if (!(speed < 1.0)) return fail(LBM_ERR_INVALID, "set_body: surface speed must be below one cell per step");
+    if (h.mapped[k]) {
+        for (int a = 0; a < 3; ++a) {
+            const double dd = wrap_rel(d.pos[a] - h.mapped_pos[k][a], n[a], h.cfg.periodic & (1 << a));
+            if (!(std::fabs(dd) < 1.0))
+                return fail(LBM_ERR_INVALID, "set_body: body moved a cell or more since its last mapping");
+        }
+    }
+    for (int j = 0; j < h.dev.nbodies; ++j) {
+        if (j == k || !h.bodies[j].active) continue;
+        bool sep = false;
+        for (int a = 0; a < 3; ++a) {
+            const double dd = wrap_rel(d.pos[a] - h.bodies[j].pos[a], n[a], h.cfg.periodic & (1 << a));
+            if (std::fabs(dd) >= d.ext[a] + h.bodies[j].ext[a] + 3.0) sep = true;
+        }
+        if (!sep) return fail(LBM_ERR_INVALID, "set_body: bodies must stay three cells apart");
+    }
+    if (b->fixed == 0 && (b->dof_mask & ~0x3Fu)) return fail(LBM_ERR_INVALID, "set_body: dof_mask has unknown bits");
+    if (b->fixed == 0 && !(b->density > 0.0)) return fail(LBM_ERR_INVALID, "set_body: free body needs a density > 0");
+    d.active = 1;
+    d.moved = 1;
+    h.desc[k] = *b;
+    for (int a = 0; a < 3; ++a) h.desc[k].pos[a] = d.pos[a];
+    if (!keep_prev) h.have_prev[k] = false;
+    for (int a = 0; a < 3; ++a) d.prev_pos[a] = h.mapped[k] ? h.mapped_pos[k][a] : d.pos[a];
+    h.bodies[k] = d;
+    if (k + 1 > h.dev.nbodies) h.dev.nbodies = k + 1;
+    int side = 2 * (int)std::ceil(Rc) + 6;
+    if (side > h.region_side) h.region_side = side;
+    h.need_remap = true;
+    launch_set_body(h.dev, k, h.bodies[k], c->stream);
+    return LBM_OK;
+}
+
+int32_t lbm_get_body(lbm_ctx* c, int32_t inst, int32_t k, lbm_body* b) {
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    InstHost& h = c->inst[inst];
+    if (!b || k < 0 || k >= h.dev.nbodies || !h.bodies[k].active) return fail(LBM_ERR_INVALID, "get_body: no such body");
+    *b = h.desc[k];
+    return LBM_OK;
+}
+
+static void after_remap(InstHost& h) {
+    for (int k = 0; k < h.dev.nbodies; ++k) {
+        DevBody& d = h.bodies[k];
+        if (!d.active || !d.moved) continue;
+        d.moved = 0;
+        for (int a = 0; a < 3; ++a) d.prev_pos[a] = d.pos[a], h.mapped_pos[k][a] = d.pos[a];
+        h.mapped[k] = true;
+    }
+    h.need_remap = false;
+}
+
+__global__ void k_copy_state(Inst I, int from);
+
+// Host update of free bodies after a full step (parity p): mean of this and
+// the previous step's force / torque -> lbm_integrate_body -> next pose.
+static int couple_free_bodies(lbm_ctx* c, int p) {
+    bool any = false;
+    for (int k = 0; k < c->n_inst; ++k) {
+        InstHost& h = c->inst[k];
+        bool has = false;
+        for (int b = 0; b < h.dev.nbodies; ++b)
+            if (h.bodies[b].active && h.desc[b].fixed == 0 && h.desc[b].dof_mask) has = true;
+        if (!has) continue;
+        any = true;
+        HIP_OK(hipMemcpyAsync(c->pinned + (size_t)k * MAXB * 6, &h.dev.ctl->cnt[p].acc[0][0], sizeof(double) * MAXB * 6,
+                              hipMemcpyDeviceToHost, c->stream));
+    }
+    if (!any) return LBM_OK;
+    HIP_OK(hipStreamSynchronize(c->stream));
+    for (int k = 0; k < c->n_inst; ++k) {
+        InstHost& h = c->inst[k];
+        for (int b = 0; b < h.dev.nbodies; ++b) {
+            if (!h.bodies[b].active || h.desc[b].fixed != 0 || !h.desc[b].dof_mask) continue;
+            const double* fnow = c->pinned + ((size_t)k * MAXB + b) * 6;
+            double F[3], T[3];
+            for (int a = 0; a < 3; ++a) {
+                F[a] = h.have_prev[b] ? 0.5 * (fnow[a] + h.fprev[b][a]) : fnow[a];
+                T[a] = h.have_prev[b] ? 0.5 * (fnow[3 + a] + h.fprev[b][3 + a]) : fnow[3 + a];
+            }
+            for (int a = 0; a < 6; ++a) h.fprev[b][a] = fnow[a];
+            h.have_prev[b] = true;
+            lbm_body nb;
+            int rc = lbm_integrate_body(&h.desc[b], F, T, h.cfg.accel, h.desc[b].dof_mask, &nb);
+            if (rc) return rc;
+            rc = set_body_impl(c, k, b, &nb, true);
+            if (rc) return rc;
+        }
+    }
+    return LBM_OK;
+}
+
+static int run_step(lbm_ctx* c, int mask) {
+    const int p = c->parity;
+    const bool advances = (mask & (LBM_PHASE_SWEEP | LBM_PHASE_CONVERT)) != 0;
+    for (int k = 0; k < c->n_inst; ++k) {
+        InstHost& h = c->inst[k];
+        bool remapped = false;
+        if ((mask & LBM_PHASE_REMAP) && h.need_remap) {
+            launch_remap(h.dev, p, h.region_side, c->stream);
+            after_remap(h);
+            remapped = true;
+        }
+        if (mask & LBM_PHASE_SWEEP) {
+            hipEvent_t e0 = c->timing ? next_event(c) : nullptr;
+            hipEvent_t e1 = c->timing ? next_event(c) : nullptr;
+            hipEvent_t e2 = c->timing ? next_event(c) : nullptr;
+            if (e0) HIP_OK(hipEventRecord(e0, c->stream));
+            launch_sweep_bulk(h.dev, p, c->stream);
+            if (e1) HIP_OK(hipEventRecord(e1, c->stream));
+            launch_sweep_boundary(h.dev, p, c->stream);
+            if (e2) HIP_OK(hipEventRecord(e2, c->stream));
+        } else if (mask & LBM_PHASE_CONVERT) {
+            hipLaunchKernelGGL(k_copy_state, dim3((h.dev.N + 255) / 256), dim3(256), 0, c->stream, h.dev, p);
+            launch_mark(h.dev, p, c->stream);
+        }
+        if (mask & LBM_PHASE_CONVERT) launch_convert(h.dev, p, remapped, c->stream);
+        else if (advances || remapped) launch_finish(h.dev, p, advances, remapped, c->stream);
+    }
+    HIP_OK(hipGetLastError());
+    if (advances) {
+        c->last_parity = p;
+        c->have_forces = (mask & LBM_PHASE_SWEEP) != 0;
+        c->parity ^= 1;
+    }
+    if (mask == LBM_PHASE_ALL) return couple_free_bodies(c, p);
+    return LBM_OK;
+}
+
+int32_t lbm_step(lbm_ctx* c, int32_t nsteps) {
+    if (!c) return fail(LBM_ERR_INVALID, "context is NULL");
+    if (nsteps < 0) return fail(LBM_ERR_INVALID, "step: nsteps < 0");
+    for (int s = 0; s < nsteps; ++s) {
+        int rc = run_step(c, LBM_PHASE_ALL);
+        if (rc) return rc;
+    }
+    return LBM_OK;
+}
+
+int32_t lbm_step_phases(lbm_ctx* c, int32_t mask) {
+    if (!c) return fail(LBM_ERR_INVALID, "context is NULL");
+    if (mask <= 0 || mask > LBM_PHASE_ALL) return fail(LBM_ERR_INVALID, "step_phases: bad mask");
+    return run_step(c, mask);
+}
+
+static int sync_and_check(lbm_ctx* c) {
+    HIP_OK(hipStreamSynchronize(c->stream));
+    for (int k = 0; k < c->n_inst; ++k) {
+        int flags[2] = {0, 0};
+        Ctl* ctl = c->inst[k].dev.ctl;
+        HIP_OK(hipMemcpy(&flags[0], &ctl->nonfinite, sizeof(int), hipMemcpyDeviceToHost));
+        int ov[2];
+        HIP_OK(hipMemcpy(&ov[0], &ctl->cnt[0].overflow, sizeof(int), hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(&ov[1], &ctl->cnt[1].overflow, sizeof(int), hipMemcpyDeviceToHost));
+        if (flags[0]) return fail(LBM_ERR_UNSTABLE, "non-finite or non-positive density detected");
+        if (ov[0] || ov[1]) return fail(LBM_ERR_UNSTABLE, "conversion list overflow");
+    }
+    return LBM_OK;
+}
+
+int32_t lbm_sync(lbm_ctx* c) {
+    if (!c) return fail(LBM_ERR_INVALID, "context is NULL");
+    return sync_and_check(c);
+}
+
+int32_t lbm_enable_kernel_timing(lbm_ctx* c, int32_t enable) {
+    if (!c) return fail(LBM_ERR_INVALID, "context is NULL");
+    HIP_OK(hipStreamSynchronize(c->stream));
+    c->timing = enable != 0;
+    c->ev_used = 0;
+    return LBM_OK;
+}
+
+int32_t lbm_kernel_time(lbm_ctx* c, int32_t kernel, double* total_ms, int64_t* launches) {
+    if (!c || !total_ms || !launches) return fail(LBM_ERR_INVALID, "kernel_time: bad arguments");
+    if (kernel < 0 || kernel > 2) return fail(LBM_ERR_INVALID, "kernel_time: unknown kernel id");
+    HIP_OK(hipStreamSynchronize(c->stream));
+    double tot = 0.0;
+    const int a = kernel == 1 ? 1 : 0, b = kernel == 0 ? 1 : 2;
+    for (size_t k = 0; k + 2 < c->ev_used; k += 3) {
+        float ms = 0.f;
+        HIP_OK(hipEventElapsedTime(&ms, c->ev_pool[k + a], c->ev_pool[k + b]));
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = (int64_t)(c->ev_used / 3);
+    return LBM_OK;
+}
+
+int32_t lbm_boundary_cells(lbm_ctx* c, int32_t inst, int64_t* n) {
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    if (!n) return fail(LBM_ERR_INVALID, "boundary_cells: NULL output");
+    HIP_OK(hipStreamSynchronize(c->stream));
+    int v = 0;
+    HIP_OK(hipMemcpy(&v, &c->inst[inst].dev.ctl->cnt[c->last_parity].n_bnd, sizeof(int), hipMemcpyDeviceToHost));
+    *n = v;
+    return LBM_OK;
+}
+
+int32_t lbm_body_forces(lbm_ctx* c, int32_t inst, int32_t k, double force[3], double torque[3]) {
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    InstHost& h = c->inst[inst];
+    if (k < 0 || k >= h.dev.nbodies || !h.bodies[k].active) return fail(LBM_ERR_INVALID, "body_forces: no such body");
+    if (!force || !torque) return fail(LBM_ERR_INVALID, "body_forces: NULL output");
+    HIP_OK(hipStreamSynchronize(c->stream));
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    if (c->have_forces)
+        HIP_OK(hipMemcpy(v, &h.dev.ctl->cnt[c->last_parity].acc[k][0], sizeof v, hipMemcpyDeviceToHost));
+    for (int a = 0; a < 3; ++a) {
+        force[a] = v[a];
+        torque[a] = v[3 + a];
+    }
+    return LBM_OK;
+}
+
+int32_t lbm_conversion_counts(lbm_ctx* c, int32_t inst, int64_t counts[4]) {
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    HIP_OK(hipStreamSynchronize(c->stream));
+    StepCounters sc;
+    HIP_OK(hipMemcpy(&sc, &c->inst[inst].dev.ctl->cnt[c->last_parity], sizeof sc, hipMemcpyDeviceToHost));
+    counts[0] = sc.filled;
+    counts[1] = sc.emptied;
+    counts[2] = sc.newg;
+    counts[3] = sc.newl;
+    return LBM_OK;
+}
+
+int32_t lbm_mass_total(lbm_ctx* c, int32_t inst, double* total, double* ledger) {
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    const Inst& I = c->inst[inst].dev;
+    launch_mass_total(I, c->parity, c->stream);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(c->stream));
+    double v[2];
+    HIP_OK(hipMemcpy(&v[0], &I.ctl->mass_total, sizeof(double), hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(&v[1], &I.ctl->ledger, sizeof(double), hipMemcpyDeviceToHost));
+    if (total) *total = v[0];
+    if (ledger) *ledger = v[1];
+    return LBM_OK;
+}
+
+int32_t lbm_set_ledger(lbm_ctx* c, int32_t inst, double ledger) {
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    HIP_OK(hipStreamSynchronize(c->stream));
+    HIP_OK(hipMemcpy(&c->inst[inst].dev.ctl->ledger, &ledger, sizeof(double), hipMemcpyHostToDevice));
+    return LBM_OK;
+}
+
+int32_t lbm_liq_gas_contacts(lbm_ctx* c, int32_t inst, int64_t* contacts) {
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    const Inst& I = c->inst[inst].dev;
+    launch_contacts(I, c->stream);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(c->stream));
+    unsigned long long v = 0;
+    HIP_OK(hipMemcpy(&v, &I.ctl->contacts, sizeof v, hipMemcpyDeviceToHost));
+    *contacts = (int64_t)v;
+    return LBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// field I/O (host side conversion; not on the hot path)
+// ---------------------------------------------------------------------------
+static double wq(int i) { return wgtd(i); }
+
+static float half_to_float(uint16_t h) {
+    __half v;
+    memcpy(&v, &h, 2);
+    return __half2float(v);
+}
+static uint16_t float_to_half(float f) {
+    __half v = __float2half(f);
+    uint16_t h;
+    memcpy(&h, &v, 2);
+    return h;
+}
+static float bf16_to_float(uint16_t h) {
+    uint32_t u = (uint32_t)h << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+static uint16_t float_to_bf16(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+int32_t lbm_read_fields(lbm_ctx* c, int32_t inst, int32_t field, int32_t dtype, void* dst, size_t bytes) {
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    const InstHost& h = c->inst[inst];
+    const Inst& I = h.dev;
+    const size_t N = (size_t)I.N;
+    const int p = c->parity;
+    size_t comps = field == LBM_FIELD_POP ? Q : (field == LBM_FIELD_VEL ? 3 : 1);
+    size_t esz = dtype == LBM_F64 ? 8 : (dtype == LBM_F32 ? 4 : 1);
+    if (field == LBM_FIELD_FLAGS ? dtype != LBM_U8 : dtype == LBM_U8)
+        return fail(LBM_ERR_INVALID, "read_fields: dtype does not fit the field");
+    if (!dst || bytes != N * comps * esz) return fail(LBM_ERR_INVALID, "read_fields: wrong byte count");
+    HIP_OK(hipStreamSynchronize(c->stream));
+    auto put = [&](size_t k, double v) {
+        if (dtype == LBM_F64) ((double*)dst)[k] = v;
+        else ((float*)dst)[k] = (float)v;
+    };
+    if (field == LBM_FIELD_FLAGS) {
+        HIP_OK(hipMemcpy(dst, I.flags, N, hipMemcpyDeviceToHost));
+        for (size_t k = 0; k < N; ++k) ((uint8_t*)dst)[k] &= KEEP_MASK;
+        return LBM_OK;
+    }
+    if (field == LBM_FIELD_PHI || field == LBM_FIELD_MASS) {
+        std::vector<float> a(N), b(N);
+        if (field == LBM_FIELD_PHI) {
+            HIP_OK(hipMemcpy(a.data(), I.phi[p], 4 * N, hipMemcpyDeviceToHost));
+            for (size_t k = 0; k < N; ++k) put(k, a[k]);
+        } else {
+            HIP_OK(hipMemcpy(a.data(), I.m_hi, 4 * N, hipMemcpyDeviceToHost));
+            HIP_OK(hipMemcpy(b.data(), I.m_lo, 4 * N, hipMemcpyDeviceToHost));
+            for (size_t k = 0; k < N; ++k) put(k, (double)a[k] + (double)b[k]);
+        }
+        return LBM_OK;
+    }
+    if (field != LBM_FIELD_POP && field != LBM_FIELD_RHO && field != LBM_FIELD_VEL)
+        return fail(LBM_ERR_INVALID, "read_fields: unknown field");
+    const size_t sb = storage_bytes(I.storage);
+    std::vector<char> raw(Q * N * sb);
+    HIP_OK(hipMemcpy(raw.data(), I.pop[p], raw.size(), hipMemcpyDeviceToHost));
+    auto dev = [&](int i, size_t k) -> double {
+        const size_t j = (size_t)i * N + k;
+        if (I.storage == LBM_FP32) return (double)((const float*)raw.data())[j];
+        if (I.storage == LBM_FP16_DEV) return (double)half_to_float(((const uint16_t*)raw.data())[j]) / I.scale;
+        return (double)bf16_to_float(((const uint16_t*)raw.data())[j]);
+    };
+    if (field == LBM_FIELD_POP) {
+        for (int i = 0; i < Q; ++i)
+            for (size_t k = 0; k < N; ++k) put((size_t)i * N + k, wq(i) + dev(i, k));
+        return LBM_OK;
+    }
+    for (size_t k = 0; k < N; ++k) {
+        double r = 0, j0 = 0, j1 = 0, j2 = 0;
+        for (int i = 0; i < Q; ++i) {
+            const double f = wq(i) + dev(i, k);
+            r += f;
+            j0 += cx(i) * f;
+            j1 += cy(i) * f;
+            j2 += cz(i) * f;
+        }
+        if (field == LBM_FIELD_RHO) {
+            put(k, r);
+        } else {
+            const double ir = r != 0 ? 1.0 / r : 0.0;
+            put(k, j0 * ir);
+            put(N + k, j1 * ir);
+            put(2 * N + k, j2 * ir);
+        }
+    }
+    return LBM_OK;
+}
+
+int32_t lbm_write_fields(lbm_ctx* c, int32_t inst, int32_t field, int32_t dtype, const void* src, size_t bytes) {
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    InstHost& h = c->inst[inst];
+    const Inst& I = h.dev;
+    const size_t N = (size_t)I.N;
+    const int p = c->parity;
+    size_t comps = field == LBM_FIELD_POP ? Q : 1;
+    size_t esz = dtype == LBM_F64 ? 8 : (dtype == LBM_F32 ? 4 : 1);
+    if (field == LBM_FIELD_FLAGS ? dtype != LBM_U8 : dtype == LBM_U8)
+        return fail(LBM_ERR_INVALID, "write_fields: dtype does not fit the field");
+    if (!src || bytes != N * comps * esz) return fail(LBM_ERR_INVALID, "write_fields: wrong byte count");
+    auto get = [&](size_t k) -> double {
+        return dtype == LBM_F64 ? ((const double*)src)[k] : (double)((const float*)src)[k];
+    };
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if (field == LBM_FIELD_FLAGS) {
+        std::vector<uint8_t> a((const uint8_t*)src, (const uint8_t*)src + N);
+        for (size_t k = 0; k < N; ++k) {
+            a[k] &= KEEP_MASK;
+            if ((a[k] & TYPE_MASK) == OBS) {
+                const int b = (a[k] >> 2) & 15;
+                if (b >= h.dev.nbodies || !h.bodies[b].active)
+                    return fail(LBM_ERR_INVALID, "write_fields: obstacle cell of an unknown body");
+            } else {
+                a[k] &= TYPE_MASK;
+            }
+        }
+        HIP_OK(hipMemcpy(I.flags, a.data(), N, hipMemcpyHostToDevice));
+        // the written obstacle cells are the bodies' mappings
+        for (int k = 0; k < h.dev.nbodies; ++k) {
+            if (!h.bodies[k].active) continue;
+            h.bodies[k].moved = 1;
+        }
+        after_remap(h);
+        for (int k = 0; k < h.dev.nbodies; ++k)
+            if (h.bodies[k].active) launch_set_body(I, k, h.bodies[k], c->stream);
+        HIP_OK(hipStreamSynchronize(c->stream));
+        return LBM_OK;
+    }
+    if (field == LBM_FIELD_PHI) {
+        std::vector<float> a(N);
+        for (size_t k = 0; k < N; ++k) a[k] = (float)get(k);
+        HIP_OK(hipMemcpy(I.phi[p], a.data(), 4 * N, hipMemcpyHostToDevice));
+        return LBM_OK;
+    }
+    if (field == LBM_FIELD_MASS) {
+        std::vector<float> a(N), b(N);
+        for (size_t k = 0; k < N; ++k) {
+            const double m = get(k);
+            a[k] = (float)m;
+            b[k] = (float)(m - (double)a[k]);
+        }
+        HIP_OK(hipMemcpy(I.m_hi, a.data(), 4 * N, hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(I.m_lo, b.data(), 4 * N, hipMemcpyHostToDevice));
+        return LBM_OK;
+    }
+    if (field != LBM_FIELD_POP) return fail(LBM_ERR_INVALID, "write_fields: field is read-only or unknown");
+    const size_t sb = storage_bytes(I.storage);
+    std::vector<char> raw(Q * N * sb);
+    for (int i = 0; i < Q; ++i)
+        for (size_t k = 0; k < N; ++k) {
+            const size_t j = (size_t)i * N + k;
+            const double d = get(j) - wq(i);
+            if (I.storage == LBM_FP32) ((float*)raw.data())[j] = (float)d;
+            else if (I.storage == LBM_FP16_DEV) ((uint16_t*)raw.data())[j] = float_to_half((float)(d * I.scale));
+            else ((uint16_t*)raw.data())[j] = float_to_bf16((float)d);
+        }
+    HIP_OK(hipMemcpy(I.pop[p], raw.data(), raw.size(), hipMemcpyHostToDevice));
+    return LBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// host rigid-body update
+// ---------------------------------------------------------------------------
+int32_t lbm_integrate_body(const lbm_body* in, const double F[3], const double T[3], const double accel[3],
+                           uint32_t dof, lbm_body* out) {
+    if (!in || !F || !T || !accel || !out) return fail(LBM_ERR_INVALID, "integrate_body: NULL argument");
+    const double* h = in->half_ext;
+    const double M = in->density * 8.0 * h[0] * h[1] * h[2];
+    if (!(M > 0.0)) return fail(LBM_ERR_INVALID, "integrate_body: body mass must be positive");
+    lbm_body o = *in;
+    for (int a = 0; a < 3; ++a)
+        if (dof & (1u << a)) o.vel[a] = in->vel[a] + (F[a] + M * accel[a]) / M;
+    double R[9];
+    quat_to_R(in->quat, R);
+    const double Ib[3] = {M / 3.0 * (h[1] * h[1] + h[2] * h[2]), M / 3.0 * (h[0] * h[0] + h[2] * h[2]),
+                          M / 3.0 * (h[0] * h[0] + h[1] * h[1])};
+    double Iw[9];
+    for (int r = 0; r < 3; ++r)
+        for (int cc = 0; cc < 3; ++cc) {
+            double acc = 0.0;
+            for (int k = 0; k < 3; ++k) acc += R[r * 3 + k] * Ib[k] * R[cc * 3 + k];
+            Iw[r * 3 + cc] = acc;
+        }
+    int S[3], ns = 0;
+    for (int a = 0; a < 3; ++a)
+        if (dof & (8u << a)) S[ns++] = a;
+    if (ns > 0) {
+        double A[3][4];
+        for (int r = 0; r < ns; ++r) {
+            for (int cc = 0; cc < ns; ++cc) A[r][cc] = Iw[S[r] * 3 + S[cc]];
+            A[r][ns] = T[S[r]];
+        }
+        for (int pv = 0; pv < ns; ++pv) {
+            int best = pv;
+            for (int r = pv + 1; r < ns; ++r)
+                if (std::fabs(A[r][pv]) > std::fabs(A[best][pv])) best = r;
+            if (best != pv)
+                for (int cc = 0; cc <= ns; ++cc) std::swap(A[pv][cc], A[best][cc]);
+            for (int r = pv + 1; r < ns; ++r) {
+                const double f = A[r][pv] / A[pv][pv];
+                for (int cc = pv; cc <= ns; ++cc) A[r][cc] -= f * A[pv][cc];
+            }
+        }
+        double dw[3];
+        for (int r = ns - 1; r >= 0; --r) {
+            double acc = A[r][ns];
+            for (int cc = r + 1; cc < ns; ++cc) acc -= A[r][cc] * dw[cc];
+            dw[r] = acc / A[r][r];
+        }
+        for (int r = 0; r < ns; ++r) o.omega[S[r]] = in->omega[S[r]] + dw[r];
+    }
+    for (int a = 0; a < 3; ++a) o.pos[a] = in->pos[a] + o.vel[a];
+    const double* w = o.omega;
+    const double th = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    if (th > 0.0) {
+        const double s = std::sin(0.5 * th) / th;
+        const double dq[4] = {std::cos(0.5 * th), s * w[0], s * w[1], s * w[2]};
+        const double* q = in->quat;
+        double r[4] = {dq[0] * q[0] - dq[1] * q[1] - dq[2] * q[2] - dq[3] * q[3],
+                       dq[0] * q[1] + dq[1] * q[0] + dq[2] * q[3] - dq[3] * q[2],
+                       dq[0] * q[2] - dq[1] * q[3] + dq[2] * q[0] + dq[3] * q[1],
+                       dq[0] * q[3] + dq[1] * q[2] - dq[2] * q[1] + dq[3] * q[0]};
+        const double nn = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3]);
+        for (int a = 0; a < 4; ++a) o.quat[a] = r[a] / nn;
+    }
+    *out = o;
+    return LBM_OK;
+}
+
+}  // extern "C"
+
+// copy the current state into the other lattice (conversion-only phase)
+__global__ __launch_bounds__(256) void k_copy_state(Inst I, int from) {
+    const int id = blockIdx.x * 256 + threadIdx.x;
+    if (id >= I.N) return;
+    const size_t N = (size_t)I.N;
+    const size_t sb = I.storage == LBM_FP32 ? 4 : 2;
+    const char* s = (const char*)I.pop[from];
+    char* d = (char*)I.pop[from ^ 1];
+    for (int i = 0; i < Q; ++i) memcpy(d + ((size_t)i * N + id) * sb, s + ((size_t)i * N + id) * sb, sb);
+    I.phi[from ^ 1][id] = I.phi[from][id];
+}

@@ -1,0 +1,293 @@
+"""Python binding of the C ABI in include/lgs_lbm.h (ctypes, argument
+marshalling only: every step of the method runs in the HIP kernels of
+liblgs.so).  PyTorch provides the device workspace and the HIP stream.
+
+Raises if the library is not built: there is no fallback implementation.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblgs.so")
+
+Q = 19
+GAS, LIQ, IF, OBS = 0, 1, 2, 3
+FP32, FP16_DEV, BF16_DEV = 0, 1, 2
+STORAGE = {"fp32": FP32, "fp16": FP16_DEV, "bf16": BF16_DEV}
+PERIODIC_X, PERIODIC_Y, PERIODIC_Z = 1, 2, 4
+FIELD_POP, FIELD_FLAGS, FIELD_PHI, FIELD_MASS, FIELD_RHO, FIELD_VEL = 1, 2, 3, 4, 5, 6
+F64, F32, U8 = 0, 1, 2
+PH_REMAP, PH_SWEEP, PH_CONVERT, PH_ALL = 1, 2, 4, 7
+MAX_BODIES = 16
+
+
+class lbm_config(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("storage", C.c_int32),
+                ("tau", C.c_double), ("accel", C.c_double * 3), ("rho_gas", C.c_double), ("eps", C.c_double),
+                ("fill_height", C.c_double), ("init_ux_surface", C.c_double), ("periodic", C.c_uint32),
+                ("recon_mode", C.c_int32), ("seed", C.c_uint64), ("noise_amp", C.c_double),
+                ("fp16_scale", C.c_double), ("max_bodies", C.c_int32), ("reserved", C.c_int32)]
+
+
+class lbm_body(C.Structure):
+    _fields_ = [("half_ext", C.c_double * 3), ("pos", C.c_double * 3), ("quat", C.c_double * 4),
+                ("vel", C.c_double * 3), ("omega", C.c_double * 3), ("density", C.c_double),
+                ("fixed", C.c_uint32), ("dof_mask", C.c_uint32)]
+
+
+class LBMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("lbm error %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def library():
+    """Load liblgs.so (built in-tree by paper_1201_0351_amd/build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("liblgs.so is not built: run paper_1201_0351_amd/build.py (or __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, sz = C.c_void_p, C.c_int32, C.c_size_t
+    dp = C.POINTER(C.c_double)
+    sig = {
+        "lbm_workspace_size": [C.POINTER(lbm_config), i32, C.POINTER(sz)],
+        "lbm_create": [C.POINTER(lbm_config), i32, vp, sz, vp, C.POINTER(vp)],
+        "lbm_destroy": [vp],
+        "lbm_set_body": [vp, i32, i32, C.POINTER(lbm_body)],
+        "lbm_get_body": [vp, i32, i32, C.POINTER(lbm_body)],
+        "lbm_step": [vp, i32],
+        "lbm_step_phases": [vp, i32],
+        "lbm_body_forces": [vp, i32, i32, dp, dp],
+        "lbm_read_fields": [vp, i32, i32, i32, vp, sz],
+        "lbm_write_fields": [vp, i32, i32, i32, vp, sz],
+        "lbm_mass_total": [vp, i32, dp, dp],
+        "lbm_set_ledger": [vp, i32, C.c_double],
+        "lbm_conversion_counts": [vp, i32, C.POINTER(C.c_int64)],
+        "lbm_liq_gas_contacts": [vp, i32, C.POINTER(C.c_int64)],
+        "lbm_sync": [vp],
+        "lbm_enable_kernel_timing": [vp, i32],
+        "lbm_kernel_time": [vp, i32, dp, C.POINTER(C.c_int64)],
+        "lbm_boundary_cells": [vp, i32, C.POINTER(C.c_int64)],
+        "lbm_integrate_body": [C.POINTER(lbm_body), dp, dp, dp, C.c_uint32, C.POINTER(lbm_body)],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = i32
+    L.lbm_last_error.restype = C.c_char_p
+    L.lbm_last_error.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != 0:
+        raise LBMError(rc, library().lbm_last_error().decode())
+
+
+def make_config(d):
+    c = lbm_config()
+    c.nx, c.ny, c.nz = int(d["nx"]), int(d["ny"]), int(d["nz"])
+    st = d.get("storage", "fp32")
+    c.storage = STORAGE[st] if isinstance(st, str) else int(st)
+    c.tau = float(d["tau"])
+    for k, v in enumerate(d.get("accel", (0.0, 0.0, 0.0))):
+        c.accel[k] = float(v)
+    c.rho_gas = float(d.get("rho_gas", 1.0))
+    c.eps = float(d.get("eps", 1e-2))
+    c.fill_height = float(d.get("fill_height", 0.0))
+    c.init_ux_surface = float(d.get("init_ux_surface", 0.0))
+    c.periodic = int(d.get("periodic", 0))
+    c.recon_mode = int(d.get("recon_mode", 0))
+    c.seed = int(d.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF
+    c.noise_amp = float(d.get("noise_amp", 0.0))
+    c.fp16_scale = float(d.get("fp16_scale", 0.0))
+    c.max_bodies = int(d.get("max_bodies", 4))
+    return c
+
+
+def make_body(d):
+    b = lbm_body()
+    for k in range(3):
+        b.half_ext[k] = float(d["half"][k])
+        b.pos[k] = float(d["pos"][k])
+        b.vel[k] = float(d.get("vel", (0, 0, 0))[k])
+        b.omega[k] = float(d.get("omega", (0, 0, 0))[k])
+    q = d.get("quat", (1.0, 0.0, 0.0, 0.0))
+    for k in range(4):
+        b.quat[k] = float(q[k])
+    b.density = float(d.get("density", 1.0))
+    b.fixed = int(d.get("fixed", 1))
+    b.dof_mask = int(d.get("dof", 0x3F if b.fixed == 0 else 0))
+    return b
+
+
+def body_dict(b):
+    return dict(half=np.array(b.half_ext[:]), pos=np.array(b.pos[:]), quat=np.array(b.quat[:]),
+                vel=np.array(b.vel[:]), omega=np.array(b.omega[:]), density=b.density, fixed=b.fixed,
+                dof=b.dof_mask)
+
+
+def integrate_body(body, F, T, accel, dof_mask):
+    """Host rigid-body update (lbm_integrate_body)."""
+    out = lbm_body()
+    F = (C.c_double * 3)(*map(float, F))
+    T = (C.c_double * 3)(*map(float, T))
+    a = (C.c_double * 3)(*map(float, accel))
+    _check(library().lbm_integrate_body(C.byref(make_body(body)), F, T, a, int(dof_mask), C.byref(out)))
+    d = body_dict(out)
+    d["fixed"] = body.get("fixed", 0)
+    return d
+
+
+class Lattice:
+    """A context of one or more lattice instances on one GPU."""
+
+    def __init__(self, configs, device="cuda:0", own_workspace=False):
+        import torch
+
+        library()
+        if isinstance(configs, dict):
+            configs = [configs]
+        self.configs = [dict(c) for c in configs]
+        n = len(configs)
+        arr = (lbm_config * n)(*[make_config(c) for c in configs])
+        self._cfg = arr
+        need = C.c_size_t(0)
+        _check(library().lbm_workspace_size(arr, n, C.byref(need)))
+        self.workspace_bytes = need.value
+        self.device = torch.device(device)
+        self._stream = torch.cuda.current_stream(self.device)
+        ws_ptr = None
+        self._ws = None
+        if not own_workspace:
+            self._ws = torch.empty(need.value + 256, dtype=torch.uint8, device=self.device)
+            base = self._ws.data_ptr()
+            ws_ptr = (base + 255) & ~255
+        h = C.c_void_p()
+        _check(library().lbm_create(arr, n, ws_ptr, need.value, C.c_void_p(self._stream.cuda_stream), C.byref(h)))
+        self._h = h
+        self.n_inst = n
+
+    @property
+    def stream(self):
+        return self._stream
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            library().lbm_destroy(self._h)
+            self._h = C.c_void_p()
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def shape(self, inst=0):
+        c = self.configs[inst]
+        return (int(c["nz"]), int(c["ny"]), int(c["nx"]))
+
+    def ncells(self, inst=0):
+        z, y, x = self.shape(inst)
+        return x * y * z
+
+    # ---- bodies -------------------------------------------------------------
+    def set_body(self, k, body, inst=0):
+        _check(library().lbm_set_body(self._h, inst, k, C.byref(make_body(body))))
+
+    def get_body(self, k, inst=0):
+        b = lbm_body()
+        _check(library().lbm_get_body(self._h, inst, k, C.byref(b)))
+        return body_dict(b)
+
+    def body_forces(self, k=0, inst=0):
+        F, T = (C.c_double * 3)(), (C.c_double * 3)()
+        _check(library().lbm_body_forces(self._h, inst, k, F, T))
+        return np.array(F[:]), np.array(T[:])
+
+    # ---- stepping ---------------------------------------------------------
+    def step(self, n=1):
+        _check(library().lbm_step(self._h, int(n)))
+
+    def step_phases(self, mask):
+        _check(library().lbm_step_phases(self._h, int(mask)))
+
+    def sync(self):
+        _check(library().lbm_sync(self._h))
+
+    def enable_kernel_timing(self, on=True):
+        _check(library().lbm_enable_kernel_timing(self._h, 1 if on else 0))
+
+    def kernel_time(self, kernel=0):
+        ms, n = C.c_double(), C.c_int64()
+        _check(library().lbm_kernel_time(self._h, kernel, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    # ---- fields -----------------------------------------------------------
+    def read(self, field, inst=0, dtype=F64):
+        shp = self.shape(inst)
+        if field == FIELD_POP:
+            shp = (Q,) + shp
+        elif field == FIELD_VEL:
+            shp = (3,) + shp
+        npdt = np.uint8 if field == FIELD_FLAGS else (np.float64 if dtype == F64 else np.float32)
+        dt = U8 if field == FIELD_FLAGS else dtype
+        out = np.empty(shp, dtype=npdt)
+        _check(library().lbm_read_fields(self._h, inst, field, dt, out.ctypes.data_as(C.c_void_p), out.nbytes))
+        return out
+
+    def write(self, field, values, inst=0):
+        if field == FIELD_FLAGS:
+            a = np.ascontiguousarray(values, dtype=np.uint8)
+            dt = U8
+        else:
+            a = np.ascontiguousarray(values, dtype=np.float64)
+            dt = F64
+        _check(library().lbm_write_fields(self._h, inst, field, dt, a.ctypes.data_as(C.c_void_p), a.nbytes))
+
+    def pop(self, inst=0):
+        return self.read(FIELD_POP, inst)
+
+    def flags(self, inst=0):
+        return self.read(FIELD_FLAGS, inst)
+
+    def types(self, inst=0):
+        return self.flags(inst) & 3
+
+    def phi(self, inst=0):
+        return self.read(FIELD_PHI, inst)
+
+    def mass(self, inst=0):
+        return self.read(FIELD_MASS, inst)
+
+    def mass_total(self, inst=0):
+        M, L = C.c_double(), C.c_double()
+        _check(library().lbm_mass_total(self._h, inst, C.byref(M), C.byref(L)))
+        return M.value, L.value
+
+    def set_ledger(self, v, inst=0):
+        _check(library().lbm_set_ledger(self._h, inst, float(v)))
+
+    def conversion_counts(self, inst=0):
+        c = (C.c_int64 * 4)()
+        _check(library().lbm_conversion_counts(self._h, inst, c))
+        return dict(filled=c[0], emptied=c[1], new_from_gas=c[2], new_from_liquid=c[3])
+
+    def boundary_cells(self, inst=0):
+        v = C.c_int64()
+        _check(library().lbm_boundary_cells(self._h, inst, C.byref(v)))
+        return v.value
+
+    def liq_gas_contacts(self, inst=0):
+        v = C.c_int64()
+        _check(library().lbm_liq_gas_contacts(self._h, inst, C.byref(v)))
+        return v.value

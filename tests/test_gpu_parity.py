@@ -1,0 +1,385 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs.
+
+Tolerances (stated once, used below):
+  * flags / cell types and conversion decisions: bit-exact when both sides
+    are fed the same fill levels (phase-isolated runs);
+  * populations, FP32 storage: |f_gpu - f_ref|_2 / |f_ref|_2 <= 1e-5 over the
+    cells whose types agree (one step is far tighter: max |df| <= 1e-6);
+  * populations, FP16 / BF16 deviation storage: <= 2e-3;
+  * body force, torque: 1% relative (of the norm), plus an absolute floor for
+    components that vanish.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.oracle import PH_CONVERT, PH_REMAP, PH_SWEEP, Oracle
+from oracle.oracle import integrate_body as oracle_integrate
+from paper_1201_0351_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_1201_0351_amd import lbm as L
+
+    L.library()
+    return L
+
+
+def oracle_for(cfg, threads=THREADS):
+    o = Oracle(cfg["nx"], cfg["ny"], cfg["nz"], cfg["tau"], accel=cfg["accel"], rho_gas=cfg.get("rho_gas", 1.0),
+               eps=cfg.get("eps", 1e-2), periodic=cfg.get("periodic", 0), recon_mode=cfg.get("recon_mode", 0),
+               threads=threads)
+    o.init_basin(cfg["fill_height"], cfg.get("init_ux_surface", 0.0), cfg.get("seed", 0), cfg.get("noise_amp", 0.0))
+    return o
+
+
+def oracle_body(o, k, b):
+    o.set_body(k, b["half"], b["pos"], b["quat"], b.get("vel", (0, 0, 0)), b.get("omega", (0, 0, 0)),
+               b.get("density", 1.0), b.get("fixed", 1))
+
+
+def pair(lbm, cfg, bodies=()):
+    L = lbm.Lattice(dict(cfg, max_bodies=max(1, len(bodies))))
+    o = oracle_for(cfg)
+    for k, b in enumerate(bodies):
+        L.set_body(k, b)
+        oracle_body(o, k, b)
+    return L, o
+
+
+def fluid_mask(t):
+    return (t == 1) | (t == 2)
+
+
+def compare_pop(L, o, tol, inst=0, label=""):
+    tg, to = L.types(inst), o.types()
+    agree = (tg == to) & fluid_mask(to)
+    fg, fo = L.pop(inst), o.get_f()
+    d = (fg - fo)[:, agree]
+    rel = np.linalg.norm(d) / np.linalg.norm(fo[:, agree])
+    say("  %s pop rel err %.3e, max |df| %.3e, type mismatches %d" % (label, rel, np.abs(d).max(),
+                                                                     int((tg != to).sum())))
+    assert rel <= tol, (label, rel)
+    return rel, int((tg != to).sum())
+
+
+def assert_force_close(Fg, Fo, rtol=1e-2, atol=0.0):
+    Fg, Fo = np.asarray(Fg), np.asarray(Fo)
+    scale = max(np.linalg.norm(Fo), atol / rtol if rtol else 0.0)
+    assert np.linalg.norm(Fg - Fo) <= rtol * scale + atol, (Fg, Fo)
+
+
+# ---------------------------------------------------------------------------
+def test_init_matches(lbm):
+    cfg = W.config1()["lattice"]
+    say("init parity: 32^3 basin, noise 1e-4 seed 1")
+    L, o = pair(lbm, cfg)
+    assert np.array_equal(L.flags(), o.get_flags())
+    fg, fo = L.pop(), o.get_f()
+    m = fluid_mask(o.types())
+    assert np.abs(fg - fo)[:, m].max() < 1e-8
+    np.testing.assert_allclose(L.phi(), o.get_phi(), atol=1e-7)
+    np.testing.assert_allclose(L.mass()[o.types() == 2], o.get_mass()[o.types() == 2], rtol=1e-7)
+    Mg, _ = L.mass_total()
+    Mo, _ = o.mass_total()
+    assert Mg == pytest.approx(Mo, rel=1e-9)
+
+
+@pytest.mark.parametrize("storage,tol", [("fp32", 1e-5), ("fp16", 2e-3), ("bf16", 2e-3)])
+def test_basin_steps_without_body(lbm, storage, tol):
+    """Full steps (stream, collide, gravity, walls, free surface) on a ragged
+    40x36x30 basin with noise."""
+    cfg = W.basin((40, 36, 30), 15.5, 0.6, 1e-5, seed=7, noise_amp=1e-4, storage=storage)
+    say("basin steps %s" % storage)
+    L, o = pair(lbm, cfg)
+    for n in (1, 9, 40):
+        L.step(n)
+        o.step(n)
+        compare_pop(L, o, tol, label="%s after +%d" % (storage, n))
+    Mg, lg = L.mass_total()
+    Mo, lo = o.mass_total()
+    assert (Mg - lg) == pytest.approx(Mo - lo, rel=1e-6 if storage == "fp32" else 1e-3)
+
+
+def _injected(lbm, n=(40, 36, 32), H=14.3, amp=3.0, seed=3, threshold_frac=0.0, storage="fp32", periodic=0,
+              bodies=()):
+    """Both sides: a wavy liquid surface with random populations, fill levels
+    and masses written in (identical float32-representable numbers)."""
+    cfg = W.basin(n, H, 0.7, 2e-5, periodic=periodic, storage=storage)
+    L, o = pair(lbm, cfg)
+    t = W.wavy_surface_types(n, H, amp, seed, periodic=periodic)
+    f, phi, m = W.random_state(n, t, seed + 1, threshold_frac=threshold_frac)
+    for side in (L, o):
+        if side is L:
+            side.write(lbm.FIELD_FLAGS, t)
+            side.write(lbm.FIELD_POP, f)
+            side.write(lbm.FIELD_PHI, phi)
+            side.write(lbm.FIELD_MASS, m)
+        else:
+            side.set_flags(t)
+            side.set_f(f)
+            side.set_phi(phi)
+            side.set_mass(m)
+    for k, b in enumerate(bodies):
+        L.set_body(k, b)
+        oracle_body(o, k, b)
+    return L, o, t
+
+
+def test_remap_on_injected_surface(lbm):
+    """A heeled, moving box is mapped onto a wavy surface, then moved by
+    0.7 cells and turned: covered / uncovered cell types (rules R1-R3 and
+    the fix-up) bit-exact, new populations and masses within round-off."""
+    b = W.box((12, 10, 8), (20.3, 18.1, 14.2), 17.0, 0.5, vel=(0.01, 0.02, -0.01), omega=(1e-3, -2e-3, 3e-3))
+    L, o, _ = _injected(lbm, bodies=[b])
+    say("remap 1 (insert)")
+    L.step_phases(lbm.PH_REMAP)
+    o.step(1, PH_REMAP)
+    assert np.array_equal(L.flags(), o.get_flags())
+    for k in range(4):
+        b = dict(b, pos=(b["pos"][0] + 0.7, b["pos"][1] - 0.45, b["pos"][2] + 0.3),
+                 quat=W.heel_quat(17.0 + 4.0 * (k + 1)))
+        L.set_body(0, b)
+        oracle_body(o, 0, b)
+        say("remap move %d" % k)
+        L.step_phases(lbm.PH_REMAP)
+        o.step(1, PH_REMAP)
+        fg, fo = L.flags(), o.get_flags()
+        assert np.array_equal(fg, fo), int((fg != fo).sum())
+        t = fo & 3
+        fl = fluid_mask(t)
+        assert np.abs(L.pop() - o.get_f())[:, fl].max() < 2e-7
+        iface = t == 2
+        np.testing.assert_allclose(L.phi()[iface], o.get_phi()[iface], atol=1e-6)
+        np.testing.assert_allclose(L.mass()[iface], o.get_mass()[iface], atol=1e-6)
+        (_, lg), (_, lo) = L.mass_total(), o.mass_total()
+        assert lg == pytest.approx(lo, rel=1e-6, abs=1e-5)
+
+
+@pytest.mark.parametrize("periodic", [0, 3])
+def test_sweep_on_injected_state(lbm, periodic):
+    """One sweep (pull stream, wall and moving-body bounce-back, gas-side
+    reconstruction incl. the normal test, mass exchange, collide) plus the
+    fused momentum exchange on random states."""
+    b = W.box((12, 10, 8), (20.3, 18.1, 14.2), 23.0, 0.5, vel=(0.01, 0.02, -0.01), omega=(1e-3, -2e-3, 3e-3))
+    L, o, _ = _injected(lbm, periodic=periodic, bodies=[b])
+    L.step_phases(lbm.PH_REMAP)
+    o.step(1, PH_REMAP)
+    assert np.array_equal(L.flags(), o.get_flags())
+    say("sweep phase, periodic=%d" % periodic)
+    L.step_phases(lbm.PH_SWEEP)
+    o.step(1, PH_SWEEP)
+    t = o.types()
+    assert np.array_equal(L.types(), t)
+    fl = fluid_mask(t)
+    fg, fo = L.pop(), o.get_f()
+    assert np.abs(fg - fo)[:, fl].max() < 1e-6
+    iface = t == 2
+    np.testing.assert_allclose(L.mass()[iface], o.get_mass()[iface], atol=1e-6)
+    np.testing.assert_allclose(L.phi()[iface], o.get_phi()[iface], atol=2e-6)
+    Fg, Tg = L.body_forces(0)
+    Fo, To = o.body_forces(0)
+    say("  F gpu %s oracle %s" % (Fg, Fo))
+    say("  T gpu %s oracle %s" % (Tg, To))
+    assert_force_close(Fg, Fo, 1e-4)
+    assert_force_close(Tg, To, 1e-4)
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13])
+def test_conversions_bit_exact(lbm, seed):
+    """Conversion phase alone on identical injected fill levels (a fifth of
+    the interface cells past the thresholds): every resulting cell type is
+    identical; masses, fill levels and new populations agree to round-off."""
+    L, o, t0 = _injected(lbm, seed=seed, threshold_frac=0.2, periodic=2)
+    say("conversion phase seed %d" % seed)
+    L.step_phases(lbm.PH_CONVERT)
+    o.step(1, PH_CONVERT)
+    fg, fo = L.flags(), o.get_flags()
+    assert np.array_equal(fg, fo), int((fg != fo).sum())
+    cg, co = L.conversion_counts(), o.last_conversions()
+    assert cg == co, (cg, co)
+    assert co["filled"] > 0 and co["emptied"] > 0 and co["new_from_gas"] > 0 and co["new_from_liquid"] > 0
+    t = fo & 3
+    iface = t == 2
+    np.testing.assert_allclose(L.mass()[iface], o.get_mass()[iface], atol=2e-6)
+    np.testing.assert_allclose(L.phi()[iface], o.get_phi()[iface], atol=2e-6)
+    fl = fluid_mask(t)
+    assert np.abs(L.pop() - o.get_f())[:, fl].max() < 1e-6
+    (Mg, lg), (Mo, lo) = L.mass_total(), o.mass_total()
+    assert Mg - lg == pytest.approx(Mo - lo, rel=1e-6)
+    assert L.liq_gas_contacts() == 0 and o.liq_gas_contacts() == 0
+
+
+def test_dam_break_conserves_mass(lbm):
+    """Many conversions per step: mass + ledger conserved on the GPU, the
+    interface layer stays closed, and the run tracks the oracle."""
+    n = (48, 8, 32)
+    cfg = W.basin(n, 0.0, 0.6, 2e-4, periodic=2)
+    L, o = pair(lbm, cfg)
+    t = np.zeros(n[::-1], np.uint8)
+    t[:20, :, :20] = 1
+    tt = t.copy()  # close the interface layer around the liquid column
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if abs(dx) + abs(dy) + abs(dz) not in (1, 2):
+                    continue
+                g = np.roll(t == 0, (-dz, -dy, -dx), axis=(0, 1, 2))
+                if dx == 1:
+                    g[:, :, -1] = False
+                if dx == -1:
+                    g[:, :, 0] = False
+                if dz == 1:
+                    g[-1] = False
+                if dz == -1:
+                    g[0] = False
+                tt[(t == 1) & g] = 2
+    rng = np.random.default_rng(5)
+    fl = tt > 0
+    f = np.zeros((19,) + tt.shape)
+    f[:, fl] = rng.uniform(0.99, 1.01, (19, int(fl.sum()))).astype(np.float32) / 19.0
+    phi = np.where(fl, 1.0, 0.0)
+    m = np.where(tt == 2, 1.0, 0.0)
+    L.write(lbm.FIELD_FLAGS, tt)
+    L.write(lbm.FIELD_POP, f)
+    L.write(lbm.FIELD_PHI, phi)
+    L.write(lbm.FIELD_MASS, m)
+    o.set_flags(tt)
+    o.set_f(f)
+    o.set_phi(phi)
+    o.set_mass(m)
+    Mg0, _ = L.mass_total()
+    say("dam break 30 steps against the oracle")
+    L.step(30)
+    o.step(30)
+    compare_pop(L, o, 1e-5, label="dam break 30")
+    say("dam break 300 more steps")
+    conv = 0
+    for k in range(30):
+        L.step(10)
+        conv += sum(L.conversion_counts().values())
+        assert L.liq_gas_contacts() == 0
+    Mg, lg = L.mass_total()
+    assert conv > 0
+    assert abs(Mg - lg - Mg0) / Mg0 < 2e-6
+
+
+def test_config1_free_body(lbm):
+    """32^3 basin, tau 0.6, g 1e-5, depth 16, 8x8x4 box of density 0.5 free
+    in 6 DOF, noise 1e-4 seed 1, 200 coupled steps (host update fed with the
+    mean force of two steps) on both sides: flags, populations, pose and
+    forces stay together and the box floats at its draft."""
+    w = W.config1()
+    cfg = w["lattice"]
+    body = dict(w["bodies"][0], fixed=0, dof=w["dof"])
+    L, o = pair(lbm, cfg, [body])
+    say("config1 free body 200 coupled steps")
+    L.step(w["steps"])
+    o.step_coupled(w["steps"], [w["dof"]])
+    rel, mism = compare_pop(L, o, 1e-5, label="config1")
+    assert mism <= 5
+    bg, bo = L.get_body(0), o.get_body(0)
+    Fg, Tg = L.body_forces(0)
+    Fo, To = o.body_forces(0)
+    say("  Fz gpu %.6e oracle %.6e; z gpu %.9f oracle %.9f" % (Fg[2], Fo[2], bg["pos"][2], bo["pos"][2]))
+    assert_force_close(Fg, Fo, 1e-2, atol=1e-7)
+    np.testing.assert_allclose(bg["pos"], bo["pos"], atol=1e-5)
+    np.testing.assert_allclose(bg["vel"], bo["vel"], atol=1e-7)
+    # floating: buoyancy balances the weight rho_s V g = 0.5 * 256 * 1e-5
+    assert Fg[2] == pytest.approx(1.28e-3, rel=0.05)
+    assert abs(bg["pos"][2] - 16.0) < 0.05
+
+
+def test_released_heeled_box_128(lbm):
+    """The benchmark workload itself: 128^3, box released at 20 deg, roll
+    only.  30 coupled steps against the oracle (all 2M cells, pose, torque),
+    then 1500 more GPU steps: the box rolls back slowly (restoring torque,
+    |d heel| of a fraction of a degree per 100 steps)."""
+    w = W.config2(20.0, released=True)
+    cfg = w["lattice"]
+    body = dict(w["bodies"][0], fixed=0, dof=w["dof"])
+    L, o = pair(lbm, cfg, [body])
+    say("128^3 released box, 30 coupled steps")
+    L.step(30)
+    o.step_coupled(30, [w["dof"]])
+    compare_pop(L, o, 1e-5, label="128^3 released")
+    Tg, To = L.body_forces(0)[1], o.body_forces(0)[1]
+    assert_force_close(Tg, To, 1e-2)
+    np.testing.assert_allclose(L.get_body(0)["quat"], o.get_body(0)["quat"], atol=1e-9)
+    heel = lambda b: math.degrees(2 * math.atan2(b["quat"][1], b["quat"][0]))
+    h0 = heel(L.get_body(0))
+    say("  heel after 30 steps %.6f" % h0)
+    L.step(1500)
+    h1 = heel(L.get_body(0))
+    T = L.body_forces(0)[1]
+    say("  heel after 1530 steps %.4f, T_x %.4e" % (h1, T[0]))
+    assert T[0] < 0  # restoring
+    assert 15.0 < h1 < h0
+
+
+def test_full_size_heeled_box_one_step(lbm):
+    """The benchmark lattice (128^3, tau 0.55, g 5e-6, depth 64, 32x32x16
+    box heeled 20 deg): map + one full step from each side's own init, all
+    2M cells compared, and force / torque."""
+    w = W.config2(20.0, released=False)
+    cfg = w["lattice"]
+    L, o = pair(lbm, cfg, w["bodies"])
+    say("128^3 one step")
+    L.step(1)
+    o.step(1)
+    assert np.array_equal(L.flags(), o.get_flags())
+    compare_pop(L, o, 1e-6, label="128^3 step 1")
+    Fg, Tg = L.body_forces(0)
+    Fo, To = o.body_forces(0)
+    say("  F %s / %s  T %s / %s" % (Fg, Fo, Tg, To))
+    assert_force_close(Fg, Fo, 1e-3)
+    assert_force_close(Tg, To, 1e-3)
+
+
+def test_multi_instance_independent(lbm):
+    """Two instances of different sizes in one context advance exactly as
+    they would alone."""
+    c1 = W.basin((24, 20, 18), 9.5, 0.7, 1e-5, seed=2, noise_amp=1e-4)
+    c2 = W.basin((40, 16, 22), 11.0, 0.6, 2e-5, seed=3, noise_amp=1e-4)
+    L = lbm.Lattice([dict(c1, max_bodies=1), dict(c2, max_bodies=1)])
+    A = lbm.Lattice(dict(c2, max_bodies=1))
+    L.step(25)
+    A.step(25)
+    assert np.array_equal(L.pop(1), A.pop(0))
+    assert np.array_equal(L.flags(1), A.flags(0))
+    o = oracle_for(c1)
+    o.step(25)
+    compare_pop(L, o, 1e-5, inst=0, label="multi inst0")
+
+
+def test_invalid_body_rejected(lbm):
+    cfg = W.basin((32, 32, 32), 16, 0.6, 1e-5)
+    L = lbm.Lattice(dict(cfg, max_bodies=2))
+    with pytest.raises(lbm.LBMError):
+        L.set_body(0, W.box((8, 8, 4), (3, 16, 16)))  # touches the wall
+    with pytest.raises(lbm.LBMError):
+        L.set_body(0, W.box((8, 8, 4), (16, 16, 16), vel=(1.2, 0, 0)))  # too fast
+    L.set_body(0, W.box((8, 8, 4), (10, 16, 16)))
+    with pytest.raises(lbm.LBMError):
+        L.set_body(1, W.box((8, 8, 4), (15, 16, 16)))  # overlaps body 0
+    L.step(1)
+    with pytest.raises(lbm.LBMError):
+        L.set_body(0, W.box((8, 8, 4), (11.5, 16, 16)))  # jumps more than a cell
