@@ -147,26 +147,16 @@ void launch_set_body(const Inst& I, int slot, const DevBody& b, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // remap
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool region_cell(const Inst& I, const DevBody& B, int side, int local, int& x, int& y,
+__device__ __forceinline__ bool region_cell(const Inst& I, const RemapRegions& R, int k, int local, int& x, int& y,
                                             int& z) {
-    const double Rc = sqrt(B.half[0] * B.half[0] + B.half[1] * B.half[1] + B.half[2] * B.half[2]);
-    const int li = local % side, lj = (local / side) % side, lk = local / (side * side);
+    const int d0 = R.dim[k][0], d1 = R.dim[k][1];
+    const int l[3] = {local % d0, (local / d0) % d1, local / (d0 * d1)};
     const int n[3] = {I.nx, I.ny, I.nz};
     int c[3];
-    const int l[3] = {li, lj, lk};
     for (int a = 0; a < 3; ++a) {
-        const double lo = floor(fmin(B.prev_pos[a], B.pos[a]) - Rc - 2.0);
-        int v = (int)lo + l[a];
-        if (I.periodic & (1 << a)) {
-            if (side >= n[a]) {
-                if (l[a] >= n[a]) return false;
-                v = l[a];
-            } else {
-                v = ((v % n[a]) + n[a]) % n[a];
-            }
-        } else if (v < 0 || v >= n[a]) {
-            return false;
-        }
+        int v = R.lo[k][a] + l[a];
+        if (I.periodic & (1 << a)) v = ((v % n[a]) + n[a]) % n[a];
+        else if (v < 0 || v >= n[a]) return false;
         c[a] = v;
     }
     x = c[0];
@@ -176,14 +166,14 @@ __device__ __forceinline__ bool region_cell(const Inst& I, const DevBody& B, int
 }
 
 template <typename S>
-__global__ __launch_bounds__(256) void k_remap_eval(Inst I, int parity, int side) {
+__global__ __launch_bounds__(256) void k_remap_eval(Inst I, int parity, RemapRegions R) {
     const int k = blockIdx.y;
     const DevBody& B = I.bodies[k];
     if (!B.active || !B.moved) return;
     const int local = blockIdx.x * 256 + threadIdx.x;
-    if (local >= side * side * side) return;
+    if (local >= R.cells[k]) return;
     int x, y, z;
-    if (!region_cell(I, B, side, local, x, y, z)) return;
+    if (!region_cell(I, R, k, local, x, y, z)) return;
     const int id = x + I.nx * (y + I.ny * z);
     const uint8_t fl = I.flags[id];
     uint8_t r = 0;
@@ -229,14 +219,14 @@ __global__ __launch_bounds__(256) void k_remap_eval(Inst I, int parity, int side
 }
 
 template <typename S>
-__global__ __launch_bounds__(256) void k_remap_commit(Inst I, int parity, int side) {
+__global__ __launch_bounds__(256) void k_remap_commit(Inst I, int parity, RemapRegions R) {
     const int k = blockIdx.y;
     const DevBody& B = I.bodies[k];
     if (!B.active || !B.moved) return;
     const int local = blockIdx.x * 256 + threadIdx.x;
-    if (local >= side * side * side) return;
+    if (local >= R.cells[k]) return;
     int x, y, z;
-    if (!region_cell(I, B, side, local, x, y, z)) return;
+    if (!region_cell(I, R, k, local, x, y, z)) return;
     const int id = x + I.nx * (y + I.ny * z);
     const uint8_t fl = I.flags[id];
     const int t = fl & TYPE_MASK;
@@ -309,21 +299,23 @@ __global__ __launch_bounds__(256) void k_remap_commit(Inst I, int parity, int si
     atomicAdd(&I.ctl->ledger, m);
 }
 
-void launch_remap(const Inst& I, int parity, int side, hipStream_t s) {
-    const int cells = side * side * side;
+void launch_remap(const Inst& I, int parity, const RemapRegions& R, hipStream_t s) {
+    int cells = 0;
+    for (int k = 0; k < I.nbodies; ++k) cells = max(cells, R.cells[k]);
+    if (cells == 0) return;
     const dim3 g((cells + 255) / 256, I.nbodies), b(256);
     switch (I.storage) {
     case LBM_FP16_DEV:
-        hipLaunchKernelGGL(k_remap_eval<__half>, g, b, 0, s, I, parity, side);
-        hipLaunchKernelGGL(k_remap_commit<__half>, g, b, 0, s, I, parity, side);
+        hipLaunchKernelGGL(k_remap_eval<__half>, g, b, 0, s, I, parity, R);
+        hipLaunchKernelGGL(k_remap_commit<__half>, g, b, 0, s, I, parity, R);
         break;
     case LBM_BF16_DEV:
-        hipLaunchKernelGGL(k_remap_eval<__hip_bfloat16>, g, b, 0, s, I, parity, side);
-        hipLaunchKernelGGL(k_remap_commit<__hip_bfloat16>, g, b, 0, s, I, parity, side);
+        hipLaunchKernelGGL(k_remap_eval<__hip_bfloat16>, g, b, 0, s, I, parity, R);
+        hipLaunchKernelGGL(k_remap_commit<__hip_bfloat16>, g, b, 0, s, I, parity, R);
         break;
     default:
-        hipLaunchKernelGGL(k_remap_eval<float>, g, b, 0, s, I, parity, side);
-        hipLaunchKernelGGL(k_remap_commit<float>, g, b, 0, s, I, parity, side);
+        hipLaunchKernelGGL(k_remap_eval<float>, g, b, 0, s, I, parity, R);
+        hipLaunchKernelGGL(k_remap_commit<float>, g, b, 0, s, I, parity, R);
         break;
     }
 }

@@ -1,8 +1,13 @@
 // k_convert.hip -- free-surface cell conversions (Sec. 2.2) on the state at
-// t+1, driven by the candidate list the sweep built.
+// t+1, driven by the candidate list the sweep built, plus the end of a step.
 //
-// Three kernels; each is a function of the state before it, so the result
-// does not depend on the order of the (atomically appended) lists:
+// One workgroup of 1024 threads runs the phases one after the other,
+// separated by workgroup barriers (candidate lists are short: a few to a few
+// thousand cells per step).  Each phase is a function of the state before
+// it, so the result does not depend on the order of the (atomically
+// appended) lists:
+//   forces  the boundary sweep's per-wavefront momentum-exchange records are
+//           summed per body in slot order (fixed-order FP64 reduction)
 //   claim   per candidate: a filled cell (phi >= 1+eps) records its excess
 //           m - rho and claims its gas neighbours as new interface cells,
 //           initialising each with f = f_eq(mean rho, mean u) over its
@@ -18,10 +23,8 @@
 //   commit  receivers add the shares of their converted neighbours in link
 //           order i = 1..18 and recompute phi = m / rho; converted and new
 //           cells take their new types.  Converted cells keep their mark until
-//           the next sweep clears it.  The kernel also clears the other
-//           parity's counters and retires body moves (end of step).
-// The kernels loop over device-side lists with a fixed grid, so an empty
-// phase costs only its launch.
+//           the next sweep clears it.
+//   finish  clear the other parity's counters, retire body moves.
 #include <cstddef>
 
 #include "lgs_internal.h"
@@ -30,13 +33,18 @@ namespace lgs {
 
 namespace {
 
-constexpr int CONV_BLOCKS = 120;
+constexpr int CONV_THREADS = 512;
 
 __device__ __forceinline__ bool claim(uint32_t* bits, int id) {
     const uint32_t m = 1u << (id & 31);
     return (atomicOr(bits + (id >> 5), m) & m) == 0;
 }
-__device__ __forceinline__ bool claimed(const uint32_t* bits, int id) { return (bits[id >> 5] >> (id & 31)) & 1u; }
+__device__ __forceinline__ bool claimed(const uint32_t* bits, int id) {
+    return (__hip_atomic_load(bits + (id >> 5), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> (id & 31)) & 1u;
+}
+__device__ __forceinline__ int load_count(int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ void unclaim(uint32_t* bits, int id) { atomicAnd(bits + (id >> 5), ~(1u << (id & 31))); }
 
 __device__ __forceinline__ void push(int* list, int* cnt, int cap, int* overflow, int id) {
@@ -109,18 +117,18 @@ __device__ __forceinline__ int post_type(const Inst& I, int id) {
     return t;
 }
 
-#define GRID_LOOP(k, n) for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < (n); k += gridDim.x * blockDim.x)
+#define BLOCK_LOOP(k, n) for (int k = threadIdx.x; k < (n); k += blockDim.x)
 
 }  // namespace
 
 template <typename S>
-__global__ __launch_bounds__(256) void k_conv_claim(Inst I, int parity) {
+__device__ __forceinline__ void phase_claim(const Inst& I, int parity) {
     StepCounters& C = I.ctl->cnt[parity];
-    const int n = min(C.n_cand, I.list_cap);
+    const int n = min(load_count(&C.n_cand), I.list_cap);
     S* pop = (S*)I.pop[parity ^ 1];
     const size_t N = (size_t)I.N;
     float* phi = I.phi[parity ^ 1];
-    GRID_LOOP(k, n) {
+    BLOCK_LOOP(k, n) {
         const int id = I.cand[k];
         const uint8_t fl = I.flags[id];
         int x, y, z;
@@ -184,10 +192,10 @@ __global__ __launch_bounds__(256) void k_conv_claim(Inst I, int parity) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_conv_share(Inst I, int parity) {
+__device__ __forceinline__ void phase_share(const Inst& I, int parity) {
     StepCounters& C = I.ctl->cnt[parity];
-    const int nc = min(C.n_cand, I.list_cap);
-    GRID_LOOP(k, nc) {
+    const int nc = min(load_count(&C.n_cand), I.list_cap);
+    BLOCK_LOOP(k, nc) {
         const int id = I.cand[k];
         const uint8_t fl = I.flags[id];
         if (!(fl & (MARK_FILL | MARK_EMPTY))) continue;
@@ -213,13 +221,13 @@ __global__ __launch_bounds__(256) void k_conv_share(Inst I, int parity) {
 }
 
 template <typename S>
-__global__ __launch_bounds__(256) void k_conv_commit(Inst I, int parity, int retire_moves) {
+__device__ __forceinline__ void phase_commit(const Inst& I, int parity) {
     StepCounters& C = I.ctl->cnt[parity];
-    const int nc = min(C.n_cand, I.list_cap), ng = min(C.n_newg, I.list_cap), nl = min(C.n_newl, I.list_cap);
-    const int nr = min(C.n_recv, I.list_cap);
+    const int nc = min(load_count(&C.n_cand), I.list_cap), ng = min(load_count(&C.n_newg), I.list_cap);
+    const int nl = min(load_count(&C.n_newl), I.list_cap), nr = min(load_count(&C.n_recv), I.list_cap);
     S* pop = (S*)I.pop[parity ^ 1];
     float* phi = I.phi[parity ^ 1];
-    GRID_LOOP(k, nc + ng + nl + nr) {
+    BLOCK_LOOP(k, nc + ng + nl + nr) {
         if (k < nc) {
             const int id = I.cand[k];
             const uint8_t fl = I.flags[id];
@@ -258,34 +266,43 @@ __global__ __launch_bounds__(256) void k_conv_commit(Inst I, int parity, int ret
             unclaim(I.claim2, id);
         }
     }
-    // end of step: clear the other parity's counters, retire body moves
-    if (blockIdx.x == 0) {
+}
+
+// fixed-order FP64 sum of the boundary sweep's force records, per body
+__device__ __forceinline__ void phase_forces(const Inst& I, int parity) {
+    __shared__ double red[6][CONV_THREADS];
+    StepCounters& C = I.ctl->cnt[parity];
+    const int nrec = boundary_blocks(I) * 4;  // one record per wavefront of the boundary grid
+    for (int b = 0; b < I.nbodies; ++b) {
+        double v[6] = {0, 0, 0, 0, 0, 0};
+        for (int k = threadIdx.x; k < nrec; k += blockDim.x) {
+            const ForceRec& r = I.frec[k];
+            if (r.body != b) continue;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) v[q] += r.v[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) red[q][threadIdx.x] = v[q];
+        __syncthreads();
+        for (int o = blockDim.x >> 1; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o)
+#pragma unroll
+                for (int q = 0; q < 6; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x < 6) C.acc[b][threadIdx.x] += red[threadIdx.x][0];
+        __syncthreads();
+    }
+}
+
+// clear the other parity's counters and / or retire body moves
+__device__ __forceinline__ void phase_finish(const Inst& I, int parity, bool zero_other, bool retire_moves) {
+    if (zero_other) {
         StepCounters& O = I.ctl->cnt[parity ^ 1];
         int* ci = (int*)&O;
         const int nint = (int)(offsetof(StepCounters, acc) / sizeof(int));
         for (int q = threadIdx.x; q < nint; q += blockDim.x) ci[q] = 0;
         for (int q = threadIdx.x; q < MAXB * 6; q += blockDim.x) (&O.acc[0][0])[q] = 0.0;
-        if (retire_moves && (int)threadIdx.x < I.nbodies) {
-            DevBody& b = I.bodies[threadIdx.x];
-            if (b.moved) {
-                b.moved = 0;
-                b.prev_pos[0] = b.pos[0];
-                b.prev_pos[1] = b.pos[1];
-                b.prev_pos[2] = b.pos[2];
-            }
-        }
-    }
-}
-
-// End of a step without conversions (phase-isolated calls): clear the other
-// parity's counters and / or retire body moves.
-__global__ __launch_bounds__(256) void k_finish(Inst I, int parity, int zero_other, int retire_moves) {
-    if (zero_other) {
-        StepCounters& O = I.ctl->cnt[parity ^ 1];
-        int* ci = (int*)&O;
-        const int nint = (int)(offsetof(StepCounters, acc) / sizeof(int));
-        for (int k = threadIdx.x; k < nint; k += blockDim.x) ci[k] = 0;
-        for (int k = threadIdx.x; k < MAXB * 6; k += blockDim.x) (&O.acc[0][0])[k] = 0.0;
     }
     if (retire_moves && (int)threadIdx.x < I.nbodies) {
         DevBody& b = I.bodies[threadIdx.x];
@@ -299,23 +316,48 @@ __global__ __launch_bounds__(256) void k_finish(Inst I, int parity, int zero_oth
 }
 
 template <typename S>
-static void launch_convert_t(const Inst& I, int parity, int retire, hipStream_t s) {
-    const dim3 g(CONV_BLOCKS), b(256);
-    hipLaunchKernelGGL(k_conv_claim<S>, g, b, 0, s, I, parity);
-    hipLaunchKernelGGL(k_conv_share, g, b, 0, s, I, parity);
-    hipLaunchKernelGGL(k_conv_commit<S>, g, b, 0, s, I, parity, retire);
+__global__ __launch_bounds__(CONV_THREADS) void k_convert(Inst I, int parity, int retire_moves,
+                                                          unsigned long long seq) {
+    phase_forces(I, parity);
+    if (I.hout && seq) {
+        // hand the forces to the host early: the conversions do not change them
+        StepCounters& C = I.ctl->cnt[parity];
+        for (int q = threadIdx.x; q < I.nbodies * 6; q += blockDim.x) I.hout->acc[q / 6][q % 6] = C.acc[q / 6][q % 6];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence_system();
+            I.hout->seq = seq;
+        }
+    }
+    phase_claim<S>(I, parity);
+    __syncthreads();
+    phase_share(I, parity);
+    __syncthreads();
+    phase_commit<S>(I, parity);
+    __syncthreads();
+    phase_finish(I, parity, true, retire_moves != 0);
 }
 
-void launch_convert(const Inst& I, int parity, bool retire_moves, hipStream_t s) {
+// End of a step without conversions (phase-isolated calls).
+__global__ __launch_bounds__(CONV_THREADS) void k_finish(Inst I, int parity, int reduce, int zero_other,
+                                                         int retire_moves) {
+    if (reduce) phase_forces(I, parity);
+    phase_finish(I, parity, zero_other != 0, retire_moves != 0);
+}
+
+void launch_convert(const Inst& I, int parity, bool retire_moves, unsigned long long seq, hipStream_t s) {
+    const dim3 g(1), b(CONV_THREADS);
+    const int r = (int)retire_moves;
     switch (I.storage) {
-    case LBM_FP16_DEV: launch_convert_t<__half>(I, parity, retire_moves, s); break;
-    case LBM_BF16_DEV: launch_convert_t<__hip_bfloat16>(I, parity, retire_moves, s); break;
-    default: launch_convert_t<float>(I, parity, retire_moves, s); break;
+    case LBM_FP16_DEV: hipLaunchKernelGGL(k_convert<__half>, g, b, 0, s, I, parity, r, seq); break;
+    case LBM_BF16_DEV: hipLaunchKernelGGL(k_convert<__hip_bfloat16>, g, b, 0, s, I, parity, r, seq); break;
+    default: hipLaunchKernelGGL(k_convert<float>, g, b, 0, s, I, parity, r, seq); break;
     }
 }
 
-void launch_finish(const Inst& I, int parity, bool zero_other, bool retire_moves, hipStream_t s) {
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, I, parity, (int)zero_other, (int)retire_moves);
+void launch_finish(const Inst& I, int parity, bool reduce, bool zero_other, bool retire_moves, hipStream_t s) {
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(CONV_THREADS), 0, s, I, parity, (int)reduce, (int)zero_other,
+                       (int)retire_moves);
 }
 
 }  // namespace lgs

@@ -6,6 +6,8 @@
 // lattices ("parity"); per-step counters and force accumulators are kept per
 // parity so that no memset is ever needed inside a step.
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -44,7 +46,7 @@ struct InstHost {
     bool have_prev[MAXB];
     bool mapped[MAXB];
     double mapped_pos[MAXB][3];
-    int region_side;
+    double mapped_ext[MAXB][3];
     bool need_remap;
     size_t offset, bytes;
 };
@@ -76,6 +78,7 @@ size_t layout(const lbm_config& c, Inst* I, char* base) {
     char* l2 = take(4 * N);
     char* l3 = take(4 * N);
     char* l4 = take(4 * N);
+    char* fr = take(sizeof(ForceRec) * BND_BLOCKS_MAX * 4);
     char* ct = take(sizeof(Ctl));
     char* bd = take(sizeof(DevBody) * MAXB);
     if (I) {
@@ -96,6 +99,7 @@ size_t layout(const lbm_config& c, Inst* I, char* base) {
         I->newl = (int*)l2;
         I->recv = (int*)l3;
         I->bnd = (int*)l4;
+        I->frec = (ForceRec*)fr;
         I->ctl = (Ctl*)ct;
         I->bodies = (DevBody*)bd;
         I->list_cap = (int)N;
@@ -157,7 +161,8 @@ struct lbm_ctx {
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;  // begin/end pairs of timed sweeps
     size_t ev_used = 0;
-    double* pinned = nullptr;  // per instance: MAXB x 6 forces of the last step
+    HostOut* hout = nullptr;      // mapped coherent host records, one per instance
+    unsigned long long seq = 0;   // step sequence number for the host records
 };
 
 static hipEvent_t next_event(lbm_ctx* c) {
@@ -216,10 +221,19 @@ int32_t lbm_create(const lbm_config* cfgs, int32_t n_inst, void* d_workspace, si
         c->own_ws = true;
     }
     c->inst.resize(n_inst);
-    if (hipHostMalloc((void**)&c->pinned, sizeof(double) * MAXB * 6 * n_inst) != hipSuccess) {
+    if (hipHostMalloc((void**)&c->hout, sizeof(HostOut) * n_inst, hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess) {
         if (c->own_ws) (void)hipFree(c->ws);
         delete c;
-        return fail(LBM_ERR_NOMEM, "create: pinned host buffer");
+        return fail(LBM_ERR_NOMEM, "create: mapped host buffer");
+    }
+    memset((void*)c->hout, 0, sizeof(HostOut) * n_inst);
+    HostOut* hout_dev = nullptr;
+    if (hipHostGetDevicePointer((void**)&hout_dev, (void*)c->hout, 0) != hipSuccess || !hout_dev) {
+        (void)hipHostFree((void*)c->hout);
+        if (c->own_ws) (void)hipFree(c->ws);
+        delete c;
+        return fail(LBM_ERR_DEVICE, "create: no device view of the mapped host buffer");
     }
     size_t off = 0;
     for (int k = 0; k < n_inst; ++k) {
@@ -247,6 +261,7 @@ int32_t lbm_create(const lbm_config* cfgs, int32_t n_inst, void* d_workspace, si
         I.scale = h.cfg.storage == LBM_FP16_DEV ? (float)h.cfg.fp16_scale : 1.f;
         I.inv_scale = 1.f / I.scale;
         I.eps = h.cfg.eps;
+        I.hout = hout_dev ? hout_dev + k : nullptr;
         const size_t N = (size_t)I.N;
         HIP_OK(hipMemsetAsync(I.ctl, 0, sizeof(Ctl), c->stream));
         HIP_OK(hipMemsetAsync(I.bodies, 0, sizeof(DevBody) * MAXB, c->stream));
@@ -266,7 +281,7 @@ int32_t lbm_destroy(lbm_ctx* c) {
     else (void)hipDeviceSynchronize();
     if (c->own_ws) (void)hipFree(c->ws);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
-    if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->hout) (void)hipHostFree((void*)c->hout);
     delete c;
     return LBM_OK;
 }
@@ -348,8 +363,6 @@ static int set_body_impl(lbm_ctx* c, int inst, int k, const lbm_body* b, bool ke
     for (int a = 0; a < 3; ++a) d.prev_pos[a] = h.mapped[k] ? h.mapped_pos[k][a] : d.pos[a];
     h.bodies[k] = d;
     if (k + 1 > h.dev.nbodies) h.dev.nbodies = k + 1;
-    int side = 2 * (int)std::ceil(Rc) + 6;
-    if (side > h.region_side) h.region_side = side;
     h.need_remap = true;
     launch_set_body(h.dev, k, h.bodies[k], c->stream);
     return LBM_OK;
@@ -369,7 +382,7 @@ static void after_remap(InstHost& h) {
         DevBody& d = h.bodies[k];
         if (!d.active || !d.moved) continue;
         d.moved = 0;
-        for (int a = 0; a < 3; ++a) d.prev_pos[a] = d.pos[a], h.mapped_pos[k][a] = d.pos[a];
+        for (int a = 0; a < 3; ++a) d.prev_pos[a] = d.pos[a], h.mapped_pos[k][a] = d.pos[a], h.mapped_ext[k][a] = d.ext[a];
         h.mapped[k] = true;
     }
     h.need_remap = false;
@@ -377,27 +390,38 @@ static void after_remap(InstHost& h) {
 
 __global__ void k_copy_state(Inst I, int from);
 
-// Host update of free bodies after a full step (parity p): mean of this and
-// the previous step's force / torque -> lbm_integrate_body -> next pose.
+// Host update of free bodies after a full step: the end-of-step kernel writes
+// the forces into mapped host memory and then the step's sequence number; the
+// host spins on it (falling back to a stream synchronisation after 1 s), takes
+// the mean of this and the previous step's force / torque, runs
+// lbm_integrate_body and sets the next pose.
 static int couple_free_bodies(lbm_ctx* c, int p) {
+    (void)p;
     bool any = false;
-    for (int k = 0; k < c->n_inst; ++k) {
+    for (int k = 0; k < c->n_inst && !any; ++k) {
         InstHost& h = c->inst[k];
-        bool has = false;
         for (int b = 0; b < h.dev.nbodies; ++b)
-            if (h.bodies[b].active && h.desc[b].fixed == 0 && h.desc[b].dof_mask) has = true;
-        if (!has) continue;
-        any = true;
-        HIP_OK(hipMemcpyAsync(c->pinned + (size_t)k * MAXB * 6, &h.dev.ctl->cnt[p].acc[0][0], sizeof(double) * MAXB * 6,
-                              hipMemcpyDeviceToHost, c->stream));
+            if (h.bodies[b].active && h.desc[b].fixed == 0 && h.desc[b].dof_mask) any = true;
     }
     if (!any) return LBM_OK;
-    HIP_OK(hipStreamSynchronize(c->stream));
+    HIP_OK(hipGetLastError());
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int k = 0; k < c->n_inst; ++k) {
+        for (long spin = 0; c->hout[k].seq < c->seq; ++spin) {
+            if ((spin & 1023) == 1023 &&
+                std::chrono::steady_clock::now() - t0 > std::chrono::seconds(1)) {
+                HIP_OK(hipStreamSynchronize(c->stream));
+                if (c->hout[k].seq < c->seq) return fail(LBM_ERR_DEVICE, "step did not deliver body forces");
+            }
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
     for (int k = 0; k < c->n_inst; ++k) {
         InstHost& h = c->inst[k];
         for (int b = 0; b < h.dev.nbodies; ++b) {
             if (!h.bodies[b].active || h.desc[b].fixed != 0 || !h.desc[b].dof_mask) continue;
-            const double* fnow = c->pinned + ((size_t)k * MAXB + b) * 6;
+            double fnow[6];
+            for (int a = 0; a < 6; ++a) fnow[a] = c->hout[k].acc[b][a];
             double F[3], T[3];
             for (int a = 0; a < 3; ++a) {
                 F[a] = h.have_prev[b] ? 0.5 * (fnow[a] + h.fprev[b][a]) : fnow[a];
@@ -422,7 +446,33 @@ static int run_step(lbm_ctx* c, int mask) {
         InstHost& h = c->inst[k];
         bool remapped = false;
         if ((mask & LBM_PHASE_REMAP) && h.need_remap) {
-            launch_remap(h.dev, p, h.region_side, c->stream);
+            RemapRegions R;
+            memset(&R, 0, sizeof R);
+            const int n[3] = {h.cfg.nx, h.cfg.ny, h.cfg.nz};
+            for (int b = 0; b < h.dev.nbodies; ++b) {
+                const DevBody& d = h.bodies[b];
+                if (!d.active || !d.moved) continue;
+                int cells = 1;
+                for (int a = 0; a < 3; ++a) {
+                    const double pp = h.mapped[b] ? h.mapped_pos[b][a] : d.pos[a];
+                    const double pe = h.mapped[b] ? h.mapped_ext[b][a] : d.ext[a];
+                    // the minimum image keeps old and new pose together on a periodic axis
+                    const double np = pp + wrap_rel(d.pos[a] - pp, n[a], h.cfg.periodic & (1 << a));
+                    const int lo = (int)std::floor(std::min(pp - pe, np - d.ext[a]) - 2.0);
+                    const int hi = (int)std::ceil(std::max(pp + pe, np + d.ext[a]) + 2.0);
+                    int dim = hi - lo + 1;
+                    int l0 = lo;
+                    if ((h.cfg.periodic & (1 << a)) && dim >= n[a]) {
+                        l0 = 0;
+                        dim = n[a];
+                    }
+                    R.lo[b][a] = l0;
+                    R.dim[b][a] = dim;
+                    cells *= dim;
+                }
+                R.cells[b] = cells;
+            }
+            launch_remap(h.dev, p, R, c->stream);
             after_remap(h);
             remapped = true;
         }
@@ -439,8 +489,9 @@ static int run_step(lbm_ctx* c, int mask) {
             hipLaunchKernelGGL(k_copy_state, dim3((h.dev.N + 255) / 256), dim3(256), 0, c->stream, h.dev, p);
             launch_mark(h.dev, p, c->stream);
         }
-        if (mask & LBM_PHASE_CONVERT) launch_convert(h.dev, p, remapped, c->stream);
-        else if (advances || remapped) launch_finish(h.dev, p, advances, remapped, c->stream);
+        if (mask & LBM_PHASE_CONVERT) launch_convert(h.dev, p, remapped, mask == LBM_PHASE_ALL ? c->seq + 1 : 0, c->stream);
+        else if (advances || remapped)
+            launch_finish(h.dev, p, (mask & LBM_PHASE_SWEEP) != 0, advances, remapped, c->stream);
     }
     HIP_OK(hipGetLastError());
     if (advances) {
@@ -448,7 +499,10 @@ static int run_step(lbm_ctx* c, int mask) {
         c->have_forces = (mask & LBM_PHASE_SWEEP) != 0;
         c->parity ^= 1;
     }
-    if (mask == LBM_PHASE_ALL) return couple_free_bodies(c, p);
+    if (mask == LBM_PHASE_ALL) {
+        ++c->seq;
+        return couple_free_bodies(c, p);
+    }
     return LBM_OK;
 }
 

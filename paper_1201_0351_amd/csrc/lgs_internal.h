@@ -83,6 +83,25 @@ struct Ctl {
     int pad;
 };
 
+// Momentum-exchange partial sum of one wavefront of the boundary sweep (over
+// its grid-stride loop) for one body (the first body the wavefront touches; further bodies of the same
+// wavefront go to the FP64 accumulators with atomics).  Records are summed in
+// slot order, so the force / torque sums do not depend on scheduling.
+struct ForceRec {
+    int body;  // -1: no contribution
+    int pad;
+    double v[6];
+};
+
+// Per-instance record in mapped, coherent host memory: the end-of-step
+// kernel writes the body forces of the step, then (after a system-scope
+// fence) the step's sequence number, which the host spins on.
+struct HostOut {
+    double acc[MAXB][6];
+    volatile unsigned long long seq;
+    unsigned long long pad[7];
+};
+
 struct DevBody {
     double pos[3];
     double R[9];  // body -> world, row major
@@ -122,6 +141,8 @@ struct Inst {
     int* newl;
     int* recv;
     int* bnd;  // cells the bulk sweep leaves to the boundary sweep
+    ForceRec* frec;  // one record per wavefront of the boundary sweep's grid
+    HostOut* hout;   // device view of the mapped host record (or null)
     int list_cap;
     Ctl* ctl;
     DevBody* bodies;
@@ -132,26 +153,80 @@ struct Inst {
 // --------------------------------------------------------------------------
 template <typename S>
 struct Store;
+// Streaming accesses of the sweep: `load` / `store`; random accesses: `ld` /
+// `st`.  LGS_STREAM_NT_LOAD / LGS_STREAM_NT_STORE select non-temporal
+// (streaming) cache policy for the sweep's population traffic.
+#ifndef LGS_STREAM_NT_LOAD
+#define LGS_STREAM_NT_LOAD 0
+#endif
+#ifndef LGS_STREAM_NT_STORE
+#define LGS_STREAM_NT_STORE 0
+#endif
+template <typename T>
+__device__ __forceinline__ T stream_load(const T* p) {
+#if LGS_STREAM_NT_LOAD
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+template <typename T>
+__device__ __forceinline__ void stream_store(T v, T* p) {
+#if LGS_STREAM_NT_STORE
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
 template <>
 struct Store<float> {
-    __device__ static inline float load(const float* p, size_t k, float) { return __builtin_nontemporal_load(p + k); }
+    __device__ static inline float load(const float* p, size_t k, float) { return stream_load(p + k); }
     __device__ static inline float ld(const float* p, size_t k, float) { return p[k]; }
-    __device__ static inline void store(float* p, size_t k, float v, float) { __builtin_nontemporal_store(v, p + k); }
+    __device__ static inline void store(float* p, size_t k, float v, float) { stream_store(v, p + k); }
     __device__ static inline void st(float* p, size_t k, float v, float) { p[k] = v; }
 };
+// 16-bit storage: the bits are moved as unsigned short so the streaming
+// policy applies; conversion is round-to-nearest-even.
+__device__ __forceinline__ float h2f(unsigned short b) {
+    __half h;
+    __builtin_memcpy(&h, &b, 2);
+    return __half2float(h);
+}
+__device__ __forceinline__ unsigned short f2h(float f) {
+    __half h = __float2half_rn(f);
+    unsigned short b;
+    __builtin_memcpy(&b, &h, 2);
+    return b;
+}
+__device__ __forceinline__ float b2f(unsigned short b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ unsigned short f2b(float f) {
+    __hip_bfloat16 h = __float2bfloat16(f);
+    unsigned short b;
+    __builtin_memcpy(&b, &h, 2);
+    return b;
+}
 template <>
 struct Store<__half> {
-    __device__ static inline float load(const __half* p, size_t k, float inv) { return __half2float(p[k]) * inv; }
-    __device__ static inline float ld(const __half* p, size_t k, float inv) { return __half2float(p[k]) * inv; }
-    __device__ static inline void store(__half* p, size_t k, float v, float sc) { p[k] = __float2half_rn(v * sc); }
-    __device__ static inline void st(__half* p, size_t k, float v, float sc) { p[k] = __float2half_rn(v * sc); }
+    using U = unsigned short;
+    __device__ static inline float load(const __half* p, size_t k, float inv) {
+        return h2f(stream_load((const U*)p + k)) * inv;
+    }
+    __device__ static inline float ld(const __half* p, size_t k, float inv) { return h2f(((const U*)p)[k]) * inv; }
+    __device__ static inline void store(__half* p, size_t k, float v, float sc) { stream_store(f2h(v * sc), (U*)p + k); }
+    __device__ static inline void st(__half* p, size_t k, float v, float sc) { ((U*)p)[k] = f2h(v * sc); }
 };
 template <>
 struct Store<__hip_bfloat16> {
-    __device__ static inline float load(const __hip_bfloat16* p, size_t k, float) { return __bfloat162float(p[k]); }
-    __device__ static inline float ld(const __hip_bfloat16* p, size_t k, float) { return __bfloat162float(p[k]); }
-    __device__ static inline void store(__hip_bfloat16* p, size_t k, float v, float) { p[k] = __float2bfloat16(v); }
-    __device__ static inline void st(__hip_bfloat16* p, size_t k, float v, float) { p[k] = __float2bfloat16(v); }
+    using U = unsigned short;
+    __device__ static inline float load(const __hip_bfloat16* p, size_t k, float) {
+        return b2f(stream_load((const U*)p + k));
+    }
+    __device__ static inline float ld(const __hip_bfloat16* p, size_t k, float) { return b2f(((const U*)p)[k]); }
+    __device__ static inline void store(__hip_bfloat16* p, size_t k, float v, float) {
+        stream_store(f2b(v), (U*)p + k);
+    }
+    __device__ static inline void st(__hip_bfloat16* p, size_t k, float v, float) { ((U*)p)[k] = f2b(v); }
 };
 
 // --------------------------------------------------------------------------
@@ -207,6 +282,23 @@ __device__ inline int body_at(const Inst& I, int x, int y, int z) {
     return -1;
 }
 
+// Cells a body remap visits: per body an axis-aligned box covering its old
+// and new bounding boxes plus two cells (origin lo, extent dim; cells = 0 for
+// bodies that did not move).
+struct RemapRegions {
+    int lo[MAXB][3];
+    int dim[MAXB][3];
+    int cells[MAXB];
+};
+
+// Grid of the boundary sweep (256-thread workgroups, four wavefronts each);
+// every wavefront of it writes one force record per step.
+constexpr int BND_BLOCKS_MAX = 4096;
+__host__ __device__ inline int boundary_blocks(const Inst& I) {
+    const int need = (I.N + 255) / 256;
+    return need < BND_BLOCKS_MAX ? need : BND_BLOCKS_MAX;
+}
+
 // --------------------------------------------------------------------------
 // kernel launchers (implemented in the .hip files)
 // --------------------------------------------------------------------------
@@ -214,9 +306,9 @@ void launch_init(const Inst& I, const lbm_config& c, hipStream_t s);
 void launch_sweep_bulk(const Inst& I, int parity, hipStream_t s);
 void launch_sweep_boundary(const Inst& I, int parity, hipStream_t s);
 void launch_mark(const Inst& I, int parity, hipStream_t s);
-void launch_convert(const Inst& I, int parity, bool retire_moves, hipStream_t s);
-void launch_finish(const Inst& I, int parity, bool zero_other, bool retire_moves, hipStream_t s);
-void launch_remap(const Inst& I, int parity, int region_cells_max, hipStream_t s);
+void launch_convert(const Inst& I, int parity, bool retire_moves, unsigned long long seq, hipStream_t s);
+void launch_finish(const Inst& I, int parity, bool reduce, bool zero_other, bool retire_moves, hipStream_t s);
+void launch_remap(const Inst& I, int parity, const RemapRegions& R, hipStream_t s);
 void launch_set_body(const Inst& I, int slot, const DevBody& b, hipStream_t s);
 void launch_mass_total(const Inst& I, int parity, hipStream_t s);
 void launch_contacts(const Inst& I, hipStream_t s);
