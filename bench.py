@@ -115,6 +115,22 @@ def cpu_baseline(target_s=15.0):
                 sample="%d steps of the 128^3 heeled-box basin (box held), FP64, %d OpenMP threads" % (steps, threads))
 
 
+def copy_probe(mib):
+    """A fill (writes 4n bytes) then five copies (read 4n, write 4n bytes each)
+    of n float32: the kernels whose counter readings convert the profiler's
+    FETCH_SIZE / WRITE_SIZE into HBM bytes."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_per_copy": 4 * n}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,7 +138,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-storage run")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain fill and device copy of MIB MiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the workload is a single-GPU lattice); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)

@@ -117,8 +117,9 @@ typedef struct lbm_body {
     double omega[3];    /* world frame, radians per step                          */
     double density;     /* rho_s relative to the liquid's 1                       */
     uint32_t fixed;     /* 1: the caller holds the pose (moves it only through
-                           lbm_set_body); 0: free -- after every full step the
-                           library advances it with lbm_integrate_body, fed with
+                           lbm_set_body); 0: free -- at the end of every full
+                           step the device applies the update of
+                           lbm_integrate_body (same FP64 operations), fed with
                            the mean of this and the previous step's fluid force
                            and torque, on the DOFs of dof_mask                   */
     uint32_t dof_mask;  /* free bodies: bits 0-2 translation x,y,z, 3-5 rotation */
@@ -145,14 +146,20 @@ int32_t lbm_destroy(lbm_ctx* ctx);
  * mass goes to the ledger).  Checks: body inside the non-periodic extent with
  * one free cell of margin, surface speed < 1 cell per step (Sec. 2.4 assumes
  * obstacles move less than a cell per step), moves by less than one cell
- * since its last mapping, and no overlap (with margin) with another body. */
+ * since its last mapping, and three free cells between the bounding boxes of
+ * two bodies.  Synchronises the stream (reads the device's body records).
+ * A free body's previous-step force is forgotten. */
 int32_t lbm_set_body(lbm_ctx* ctx, int32_t inst, int32_t body, const lbm_body* b);
+/* Current state of a body (free bodies: as the device advanced it).
+ * Synchronises the stream. */
 int32_t lbm_get_body(lbm_ctx* ctx, int32_t inst, int32_t body, lbm_body* b);
 
-/* Advance all instances by nsteps full steps (remap if needed, sweep,
- * conversions, then the host update of free bodies).  Asynchronous on the
- * context's stream unless a free body exists: then every step ends with a
- * stream synchronisation and one small device-to-host copy of the forces. */
+/* Advance all instances by nsteps full steps (remap of moved bodies, sweep,
+ * conversions and force reduction, then the device update of free bodies,
+ * whose new pose the next step maps).  Asynchronous on the context's stream.
+ * A free-body update that breaks the lbm_set_body checks is rejected on the
+ * device (the body keeps its pose) and the next lbm_sync returns
+ * LBM_ERR_UNSTABLE naming the reason. */
 int32_t lbm_step(lbm_ctx* ctx, int32_t nsteps);
 
 /* One step restricted to the phases in phase_mask (LBM_PHASE_*), for tests.
@@ -202,8 +209,9 @@ int32_t lbm_kernel_time(lbm_ctx* ctx, int32_t kernel, double* total_ms, int64_t*
  * kernel (synchronises). */
 int32_t lbm_boundary_cells(lbm_ctx* ctx, int32_t inst, int64_t* n);
 
-/* Host rigid-body update (the paper couples to a rigid-body engine; this is
- * a plain semi-implicit Euler step, dt = 1): mass M = density * 8 hx hy hz,
+/* Rigid-body update on the host (the paper couples to a rigid-body engine;
+ * this is a plain semi-implicit Euler step, dt = 1), for callers that move
+ * held bodies themselves: mass M = density * 8 hx hy hz,
  * V += (F + M a) / M on translational DOFs (dof_mask bits 0-2),
  * Omega += I_SS^-1 T_S on rotational DOFs S (bits 3-5; I the world-frame
  * cuboid inertia about the centre), pos += V, quat rotated by Omega. */

@@ -1,8 +1,9 @@
 // k_body.hip -- basin initialisation, body upload, body remap (Sec. 2.3 cell
 // mapping, Sec. 2.4 conversions into and out of obstacle), and reductions.
 //
-// Remap of a moved body k works on a cube of cells around the union of its
-// old and new pose and runs in two kernels:
+// Remap of a moved body k works on a box of cells around the union of its
+// last mapped and its new pose (computed on the device from the body record,
+// so the launch does not depend on the pose) and runs in two kernels:
 //   eval    every cell of the region that is an obstacle cell no longer
 //           inside its body's new pose ("uncovered") gets its rule from the
 //           pre-remap state: B(x) = neighbours that are not obstacle and not
@@ -147,14 +148,13 @@ void launch_set_body(const Inst& I, int slot, const DevBody& b, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // remap
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool region_cell(const Inst& I, const RemapRegions& R, int k, int local, int& x, int& y,
-                                            int& z) {
-    const int d0 = R.dim[k][0], d1 = R.dim[k][1];
+__device__ __forceinline__ bool region_cell(const Inst& I, const Region& R, int local, int& x, int& y, int& z) {
+    const int d0 = R.dim[0], d1 = R.dim[1];
     const int l[3] = {local % d0, (local / d0) % d1, local / (d0 * d1)};
     const int n[3] = {I.nx, I.ny, I.nz};
     int c[3];
     for (int a = 0; a < 3; ++a) {
-        int v = R.lo[k][a] + l[a];
+        int v = R.lo[a] + l[a];
         if (I.periodic & (1 << a)) v = ((v % n[a]) + n[a]) % n[a];
         else if (v < 0 || v >= n[a]) return false;
         c[a] = v;
@@ -165,15 +165,11 @@ __device__ __forceinline__ bool region_cell(const Inst& I, const RemapRegions& R
     return true;
 }
 
+// remap rule of one cell of body k's region (pre-remap state only)
 template <typename S>
-__global__ __launch_bounds__(256) void k_remap_eval(Inst I, int parity, RemapRegions R) {
-    const int k = blockIdx.y;
-    const DevBody& B = I.bodies[k];
-    if (!B.active || !B.moved) return;
-    const int local = blockIdx.x * 256 + threadIdx.x;
-    if (local >= R.cells[k]) return;
+__device__ __forceinline__ void remap_eval_cell(const Inst& I, int parity, const Region& R, int local) {
     int x, y, z;
-    if (!region_cell(I, R, k, local, x, y, z)) return;
+    if (!region_cell(I, R, local, x, y, z)) return;
     const int id = x + I.nx * (y + I.ny * z);
     const uint8_t fl = I.flags[id];
     uint8_t r = 0;
@@ -218,15 +214,12 @@ __global__ __launch_bounds__(256) void k_remap_eval(Inst I, int parity, RemapReg
     I.rule[id] = r;
 }
 
+// cover / uncover one cell of body k's region
 template <typename S>
-__global__ __launch_bounds__(256) void k_remap_commit(Inst I, int parity, RemapRegions R) {
-    const int k = blockIdx.y;
-    const DevBody& B = I.bodies[k];
-    if (!B.active || !B.moved) return;
-    const int local = blockIdx.x * 256 + threadIdx.x;
-    if (local >= R.cells[k]) return;
+__device__ __forceinline__ void remap_commit_cell(const Inst& I, int parity, int k, const DevBody& B,
+                                                  const Region& R, int local) {
     int x, y, z;
-    if (!region_cell(I, R, k, local, x, y, z)) return;
+    if (!region_cell(I, R, local, x, y, z)) return;
     const int id = x + I.nx * (y + I.ny * z);
     const uint8_t fl = I.flags[id];
     const int t = fl & TYPE_MASK;
@@ -299,23 +292,41 @@ __global__ __launch_bounds__(256) void k_remap_commit(Inst I, int parity, RemapR
     atomicAdd(&I.ctl->ledger, m);
 }
 
-void launch_remap(const Inst& I, int parity, const RemapRegions& R, hipStream_t s) {
-    int cells = 0;
-    for (int k = 0; k < I.nbodies; ++k) cells = max(cells, R.cells[k]);
-    if (cells == 0) return;
-    const dim3 g((cells + 255) / 256, I.nbodies), b(256);
+template <typename S>
+__global__ __launch_bounds__(256) void k_remap_eval(Inst I, int parity) {
+    const int k = blockIdx.y;
+    const DevBody& B = I.bodies[k];
+    if (!B.active || !B.moved) return;
+    const Region R = body_region(B, I.nx, I.ny, I.nz, I.periodic);
+    for (int local = blockIdx.x * 256 + threadIdx.x; local < R.cells; local += gridDim.x * 256)
+        remap_eval_cell<S>(I, parity, R, local);
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_remap_commit(Inst I, int parity) {
+    const int k = blockIdx.y;
+    const DevBody& B = I.bodies[k];
+    if (!B.active || !B.moved) return;
+    const Region R = body_region(B, I.nx, I.ny, I.nz, I.periodic);
+    for (int local = blockIdx.x * 256 + threadIdx.x; local < R.cells; local += gridDim.x * 256)
+        remap_commit_cell<S>(I, parity, k, B, R, local);
+}
+
+void launch_remap(const Inst& I, int parity, int blocks_per_body, hipStream_t s) {
+    if (I.nbodies == 0 || blocks_per_body <= 0) return;
+    const dim3 g(blocks_per_body, I.nbodies), b(256);
     switch (I.storage) {
     case LBM_FP16_DEV:
-        hipLaunchKernelGGL(k_remap_eval<__half>, g, b, 0, s, I, parity, R);
-        hipLaunchKernelGGL(k_remap_commit<__half>, g, b, 0, s, I, parity, R);
+        hipLaunchKernelGGL(k_remap_eval<__half>, g, b, 0, s, I, parity);
+        hipLaunchKernelGGL(k_remap_commit<__half>, g, b, 0, s, I, parity);
         break;
     case LBM_BF16_DEV:
-        hipLaunchKernelGGL(k_remap_eval<__hip_bfloat16>, g, b, 0, s, I, parity, R);
-        hipLaunchKernelGGL(k_remap_commit<__hip_bfloat16>, g, b, 0, s, I, parity, R);
+        hipLaunchKernelGGL(k_remap_eval<__hip_bfloat16>, g, b, 0, s, I, parity);
+        hipLaunchKernelGGL(k_remap_commit<__hip_bfloat16>, g, b, 0, s, I, parity);
         break;
     default:
-        hipLaunchKernelGGL(k_remap_eval<float>, g, b, 0, s, I, parity, R);
-        hipLaunchKernelGGL(k_remap_commit<float>, g, b, 0, s, I, parity, R);
+        hipLaunchKernelGGL(k_remap_eval<float>, g, b, 0, s, I, parity);
+        hipLaunchKernelGGL(k_remap_commit<float>, g, b, 0, s, I, parity);
         break;
     }
 }

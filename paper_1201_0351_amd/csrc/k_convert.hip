@@ -1,21 +1,25 @@
 // k_convert.hip -- free-surface cell conversions (Sec. 2.2) on the state at
 // t+1, driven by the candidate list the sweep built, plus the end of a step.
 //
-// One workgroup of 1024 threads runs the phases one after the other,
+// One workgroup of 512 threads runs the phases one after the other,
 // separated by workgroup barriers (candidate lists are short: a few to a few
-// thousand cells per step).  Each phase is a function of the state before
-// it, so the result does not depend on the order of the (atomically
-// appended) lists:
-//   forces  the boundary sweep's per-wavefront momentum-exchange records are
+// thousand cells per step).  Per-cell work is spread over a 32-lane group
+// (lane i looks at neighbour x + c_i, or population i), so a cell costs a
+// few dependent memory round trips, not a serial walk over its neighbours.
+// Each phase is a function of the state before it, so the result does not
+// depend on the order of the (atomically appended) lists:
+//   forces  the boundary sweep's per-workgroup momentum-exchange records are
 //           summed per body in slot order (fixed-order FP64 reduction)
+//   bodies  (last wavefront, beside claim) retire the step's body moves; free
+//           bodies take the rigid-body update from the reduced force/torque
 //   claim   per candidate: a filled cell (phi >= 1+eps) records its excess
-//           m - rho and claims its gas neighbours as new interface cells,
-//           initialising each with f = f_eq(mean rho, mean u) over its
-//           neighbours that are liquid or interface and not emptying, m = 0;
-//           an emptied cell (phi <= -eps) touching a filled one stays
-//           interface (filling wins), otherwise it records its excess m and
-//           claims its liquid neighbours as new interface cells (m = rho).
-//           Claims go through a bitmap, so every new cell is initialised once.
+//           m - rho and claims its gas neighbours as new interface cells; an
+//           emptied cell (phi <= -eps) touching a filled one stays interface
+//           (filling wins), otherwise it records its excess m and claims its
+//           liquid neighbours as new interface cells (m = rho).  Claims go
+//           through a bitmap, so every new cell is listed once.
+//   newgas  each new cell from gas: f = f_eq(mean rho, mean u) over its
+//           neighbours that are liquid or interface and not emptying, m = 0
 //   share   per converted cell: count the neighbours that are interface after
 //           the conversion (a function of the flags, marks and claims), divide
 //           the excess among them and list them as receivers; with none the
@@ -24,7 +28,7 @@
 //           order i = 1..18 and recompute phi = m / rho; converted and new
 //           cells take their new types.  Converted cells keep their mark until
 //           the next sweep clears it.
-//   finish  clear the other parity's counters, retire body moves.
+//   finish  clear the other parity's counters.
 #include <cstddef>
 
 #include "lgs_internal.h"
@@ -121,105 +125,155 @@ __device__ __forceinline__ int post_type(const Inst& I, int id) {
 
 }  // namespace
 
+// group-aggregated append (one atomic per group)
+__device__ __forceinline__ void g_push(bool pred, int id, int* list, int* cnt, int cap, int* overflow) {
+    const unsigned m = g_ballot(pred);
+    if (m == 0) return;
+    const int leader = __ffs(m) - 1;
+    int base = 0;
+    if (g_lane() == leader) base = atomicAdd(cnt, __popc(m));
+    base = g_bcast(base, leader);
+    if (pred) {
+        const int pos = base + __popc(m & ((1u << g_lane()) - 1u));
+        if (pos < cap) list[pos] = id;
+        else atomicOr(overflow, 1);
+    }
+}
+
+// neighbour x + c_i of the calling lane's link (lanes 1..18), else -1
+__device__ __forceinline__ int lane_nbr(const Inst& I, int x, int y, int z) {
+    const int i = g_lane();
+    if (i < 1 || i >= Q) return -1;
+    return nbr_index(I, x, y, z, lane_c(CXP, i), lane_c(CYP, i), lane_c(CZP, i));
+}
+
+// (rho - 1) of cell id summed over the group: lane q contributes f_q
 template <typename S>
-__device__ __forceinline__ void phase_claim(const Inst& I, int parity) {
+__device__ __forceinline__ float g_drho(const Inst& I, const S* pop, int id) {
+    const int q = g_lane();
+    return gsum(q < Q ? Store<S>::ld(pop, (size_t)q * I.N + id, I.inv_scale) : 0.f);
+}
+
+// claim: one 32-lane group per candidate, lane i looks at neighbour x + c_i.
+template <typename S>
+__device__ __forceinline__ void phase_claim(const Inst& I, int parity, int g0, int ngroups) {
     StepCounters& C = I.ctl->cnt[parity];
     const int n = min(load_count(&C.n_cand), I.list_cap);
     S* pop = (S*)I.pop[parity ^ 1];
-    const size_t N = (size_t)I.N;
     float* phi = I.phi[parity ^ 1];
-    BLOCK_LOOP(k, n) {
+    const int i = g_lane();
+    for (int k = g0; k < n; k += ngroups) {
         const int id = I.cand[k];
         const uint8_t fl = I.flags[id];
         int x, y, z;
         cell_coords(I, id, x, y, z);
+        const int nb = lane_nbr(I, x, y, z);
+        const uint8_t nf = nb >= 0 ? I.flags[nb] : 0;
         if (fl & MARK_FILL) {
-            const float dr = drho_of<S>(I, pop, id);
-            I.share[id] = (float)(((double)I.m_hi[id] - 1.0) + ((double)I.m_lo[id] - (double)dr));
-            for (int i = 1; i < Q; ++i) {
-                const int g = nbr_index(I, x, y, z, cx(i), cy(i), cz(i));
-                if (g < 0 || (I.flags[g] & TYPE_MASK) != GAS || !claim(I.claim, g)) continue;
-                push(I.newg, &C.n_newg, I.list_cap, &C.overflow, g);
-                // new interface cell from gas: equilibrium of its liquid /
-                // interface neighbours that are not emptying
-                int gx, gy, gz;
-                cell_coords(I, g, gx, gy, gz);
-                float rs = 0.f, us0 = 0.f, us1 = 0.f, us2 = 0.f;
-                int ns = 0;
-                for (int j = 1; j < Q; ++j) {
-                    const int nb = nbr_index(I, gx, gy, gz, cx(j), cy(j), cz(j));
-                    if (nb < 0) continue;
-                    const uint8_t f = I.flags[nb];
-                    const int t = f & TYPE_MASK;
-                    if ((t != LIQ && t != IFC) || empties(I, nb, f)) continue;
-                    float d, u[3];
-                    moments<S>(I, pop, nb, d, u);
-                    rs += d;
-                    us0 += u[0];
-                    us1 += u[1];
-                    us2 += u[2];
-                    ++ns;
-                }
-                const float inv = 1.f / (float)max(ns, 1);
-                const float drb = ns > 0 ? rs * inv : I.rho_g - 1.f, rb = 1.f + drb;
-                const float u0 = us0 * inv, u1 = us1 * inv, u2 = us2 * inv;
-                const float uu = u0 * u0 + u1 * u1 + u2 * u2;
-#pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    const float cu = cx(q) * u0 + cy(q) * u1 + cz(q) * u2;
-                    const float deq = wgt(q) * (drb + rb * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
-                    Store<S>::st(pop, (size_t)q * N + g, deq, I.scale);
-                }
-                I.m_hi[g] = 0.f;
-                I.m_lo[g] = 0.f;
-                phi[g] = 0.f;
-            }
+            const float dr = g_drho<S>(I, pop, id);
+            if (i == 0) I.share[id] = (float)(((double)I.m_hi[id] - 1.0) + ((double)I.m_lo[id] - (double)dr));
+            const bool take = nb >= 0 && (nf & TYPE_MASK) == GAS && claim(I.claim, nb);
+            g_push(take, nb, I.newg, &C.n_newg, I.list_cap, &C.overflow);
         } else if (fl & MARK_EMPTY) {
-            if (has_fill_neighbour(I, x, y, z)) {
-                I.flags[id] = fl & (uint8_t)~MARK_EMPTY;  // filling wins: stays interface
+            if (g_ballot(nb >= 0 && (nf & MARK_FILL))) {
+                if (i == 0) I.flags[id] = fl & (uint8_t)~MARK_EMPTY;  // filling wins: stays interface
                 continue;
             }
-            I.share[id] = (float)((double)I.m_hi[id] + (double)I.m_lo[id]);
-            for (int i = 1; i < Q; ++i) {
-                const int l = nbr_index(I, x, y, z, cx(i), cy(i), cz(i));
-                if (l < 0 || (I.flags[l] & TYPE_MASK) != LIQ || !claim(I.claim, l)) continue;
-                push(I.newl, &C.n_newl, I.list_cap, &C.overflow, l);
-                I.m_hi[l] = 1.f;
-                I.m_lo[l] = drho_of<S>(I, pop, l);
-                phi[l] = 1.f;
+            if (i == 0) I.share[id] = (float)((double)I.m_hi[id] + (double)I.m_lo[id]);
+            const bool take = nb >= 0 && (nf & TYPE_MASK) == LIQ && claim(I.claim, nb);
+            g_push(take, nb, I.newl, &C.n_newl, I.list_cap, &C.overflow);
+            if (take) {
+                I.m_hi[nb] = 1.f;
+                I.m_lo[nb] = drho_of<S>(I, pop, nb);
+                phi[nb] = 1.f;
             }
         }
     }
 }
 
+// New interface cells from gas: equilibrium of the mean density and
+// velocity of their liquid / interface neighbours that are not emptying
+// (one group per new cell, lane j looks at neighbour j); m = 0.
+template <typename S>
+__device__ __forceinline__ void phase_newgas(const Inst& I, int parity) {
+    StepCounters& C = I.ctl->cnt[parity];
+    const int n = min(load_count(&C.n_newg), I.list_cap);
+    S* pop = (S*)I.pop[parity ^ 1];
+    const size_t N = (size_t)I.N;
+    float* phi = I.phi[parity ^ 1];
+    const int j = g_lane();
+    const int grp = threadIdx.x >> 5, ngrp = blockDim.x >> 5;
+    for (int k = grp; k < n; k += ngrp) {
+        const int g = I.newg[k];
+        int gx, gy, gz;
+        cell_coords(I, g, gx, gy, gz);
+        const int nb = lane_nbr(I, gx, gy, gz);
+        bool use = false;
+        if (nb >= 0) {
+            const uint8_t f = I.flags[nb];
+            const int t = f & TYPE_MASK;
+            use = (t == LIQ || t == IFC) && !empties(I, nb, f);
+        }
+        float d = 0.f, u0 = 0.f, u1 = 0.f, u2 = 0.f;
+        if (use) {
+            float u[3];
+            moments<S>(I, pop, nb, d, u);
+            u0 = u[0];
+            u1 = u[1];
+            u2 = u[2];
+        }
+        const int ns = __popc(g_ballot(use));
+        const float rs = gsum(d), us0 = gsum(u0), us1 = gsum(u1), us2 = gsum(u2);
+        const float inv = 1.f / (float)max(ns, 1);
+        const float drb = ns > 0 ? rs * inv : I.rho_g - 1.f, rb = 1.f + drb;
+        const float v0 = us0 * inv, v1 = us1 * inv, v2 = us2 * inv;
+        const float uu = v0 * v0 + v1 * v1 + v2 * v2;
+        if (j < Q) {
+            const float cu = lane_c(CXP, j) * v0 + lane_c(CYP, j) * v1 + lane_c(CZP, j) * v2;
+            const float deq = lane_w(j) * (drb + rb * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
+            Store<S>::st(pop, (size_t)j * N + g, deq, I.scale);
+        }
+        if (j == 0) {
+            I.m_hi[g] = 0.f;
+            I.m_lo[g] = 0.f;
+            phi[g] = 0.f;
+        }
+    }
+}
+
+// share: one group per converted cell; lane i counts neighbour x + c_i if it
+// is interface after the conversions (flags, marks and claims are not
+// modified in this phase).
 __device__ __forceinline__ void phase_share(const Inst& I, int parity) {
     StepCounters& C = I.ctl->cnt[parity];
     const int nc = min(load_count(&C.n_cand), I.list_cap);
-    BLOCK_LOOP(k, nc) {
+    const int grp = threadIdx.x >> 5, ngrp = blockDim.x >> 5;
+    for (int k = grp; k < nc; k += ngrp) {
         const int id = I.cand[k];
         const uint8_t fl = I.flags[id];
         if (!(fl & (MARK_FILL | MARK_EMPTY))) continue;
         int x, y, z;
         cell_coords(I, id, x, y, z);
-        int nr = 0;
-        for (int i = 1; i < Q; ++i) {
-            const int nb = nbr_index(I, x, y, z, cx(i), cy(i), cz(i));
-            if (nb >= 0 && post_type(I, nb) == IFC) ++nr;
-        }
+        const int nb = lane_nbr(I, x, y, z);
+        const bool rcv = nb >= 0 && post_type(I, nb) == IFC;
+        const int nr = __popc(g_ballot(rcv));
         if (nr == 0) {
-            atomicAdd(&I.ctl->ledger, -(double)I.share[id]);
-            I.share[id] = 0.f;
+            if (g_lane() == 0) {
+                atomicAdd(&I.ctl->ledger, -(double)I.share[id]);
+                I.share[id] = 0.f;
+            }
             continue;
         }
-        I.share[id] = (float)((double)I.share[id] / nr);
-        for (int i = 1; i < Q; ++i) {
-            const int nb = nbr_index(I, x, y, z, cx(i), cy(i), cz(i));
-            if (nb >= 0 && post_type(I, nb) == IFC && claim(I.claim2, nb))
-                push(I.recv, &C.n_recv, I.list_cap, &C.overflow, nb);
-        }
+        if (g_lane() == 0) I.share[id] = (float)((double)I.share[id] / nr);
+        const bool first = rcv && claim(I.claim2, nb);
+        g_push(first, nb, I.recv, &C.n_recv, I.list_cap, &C.overflow);
     }
 }
 
+// commit: converted and new cells take their new types; receivers add the
+// shares of their converted neighbours in link order i = 1..18 (lane i
+// fetches the share of neighbour i, lane 0 accumulates) and recompute
+// phi = m / rho.  One group per item.
 template <typename S>
 __device__ __forceinline__ void phase_commit(const Inst& I, int parity) {
     StepCounters& C = I.ctl->cnt[parity];
@@ -227,7 +281,8 @@ __device__ __forceinline__ void phase_commit(const Inst& I, int parity) {
     const int nl = min(load_count(&C.n_newl), I.list_cap), nr = min(load_count(&C.n_recv), I.list_cap);
     S* pop = (S*)I.pop[parity ^ 1];
     float* phi = I.phi[parity ^ 1];
-    BLOCK_LOOP(k, nc + ng + nl + nr) {
+    // single-thread items
+    BLOCK_LOOP(k, nc + ng + nl) {
         if (k < nc) {
             const int id = I.cand[k];
             const uint8_t fl = I.flags[id];
@@ -244,114 +299,237 @@ __device__ __forceinline__ void phase_commit(const Inst& I, int parity) {
                 phi[id] = 0.f;
                 atomicAdd(&C.emptied, 1);
             }
-        } else if (k < nc + ng + nl) {
+        } else {
             const bool g = k < nc + ng;
             const int id = g ? I.newg[k - nc] : I.newl[k - nc - ng];
             I.flags[id] = IFC;
             unclaim(I.claim, id);
             atomicAdd(g ? &C.newg : &C.newl, 1);
-        } else {
-            const int id = I.recv[k - nc - ng - nl];
-            int x, y, z;
-            cell_coords(I, id, x, y, z);
-            float hi = I.m_hi[id], lo = I.m_lo[id];
-            for (int i = 1; i < Q; ++i) {
-                const int nb = nbr_index(I, x, y, z, cx(i), cy(i), cz(i));
-                if (nb >= 0 && (I.flags[nb] & (MARK_FILL | MARK_EMPTY))) add_comp(hi, lo, I.share[nb]);
-            }
+        }
+    }
+    // receivers: one group each (the flags read here are not among those
+    // written above: receivers and their converted neighbours keep their
+    // marks, and new cells are never converted cells)
+    const int grp = threadIdx.x >> 5, ngrp = blockDim.x >> 5;
+    const int i = g_lane();
+    for (int k = grp; k < nr; k += ngrp) {
+        const int id = I.recv[k];
+        int x, y, z;
+        cell_coords(I, id, x, y, z);
+        const int nb = lane_nbr(I, x, y, z);
+        float sh = 0.f;
+        bool has = false;
+        if (nb >= 0 && (I.flags[nb] & (MARK_FILL | MARK_EMPTY))) {
+            has = true;
+            sh = I.share[nb];
+        }
+        const unsigned m = g_ballot(has);
+        const float dr = g_drho<S>(I, pop, id);
+        float hi = I.m_hi[id], lo = I.m_lo[id];
+        for (int l = 1; l < Q; ++l) {
+            const float v = g_bcastf(sh, l);
+            if ((m >> l) & 1u) add_comp(hi, lo, v);
+        }
+        if (i == 0) {
             I.m_hi[id] = hi;
             I.m_lo[id] = lo;
-            const float dr = drho_of<S>(I, pop, id);
             phi[id] = (float)(((double)hi + (double)lo) / (1.0 + (double)dr));
             unclaim(I.claim2, id);
         }
     }
 }
 
-// fixed-order FP64 sum of the boundary sweep's force records, per body
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Fixed-order FP64 sum of the boundary sweep's force records, per body.
+// Every thread loads its records (slots tid + j * CONV_THREADS) with
+// independent loads, sums them in slot order, then wavefront butterflies and
+// the wavefronts' partials in wavefront order.
 __device__ __forceinline__ void phase_forces(const Inst& I, int parity) {
-    __shared__ double red[6][CONV_THREADS];
+    constexpr int PER = BND_BLOCKS_MAX / CONV_THREADS;
+    constexpr int NW = CONV_THREADS / 64;
+    static_assert(PER * CONV_THREADS == BND_BLOCKS_MAX, "force records per thread");
+    __shared__ double part[NW][6];
     StepCounters& C = I.ctl->cnt[parity];
-    const int nrec = boundary_blocks(I) * 4;  // one record per wavefront of the boundary grid
+    const int nrec = boundary_blocks(I);
+    int rb[PER];
+    double rv[PER][6];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int k = threadIdx.x + j * CONV_THREADS;
+        rb[j] = k < nrec ? I.frec_body[k] : -1;
+    }
+    // values loaded without waiting for the body ids: one round trip
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int k = threadIdx.x + j * CONV_THREADS;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) rv[j][q] = k < nrec ? I.frec_v[q * BND_BLOCKS_MAX + k] : 0.0;
+    }
     for (int b = 0; b < I.nbodies; ++b) {
         double v[6] = {0, 0, 0, 0, 0, 0};
-        for (int k = threadIdx.x; k < nrec; k += blockDim.x) {
-            const ForceRec& r = I.frec[k];
-            if (r.body != b) continue;
 #pragma unroll
-            for (int q = 0; q < 6; ++q) v[q] += r.v[q];
-        }
+        for (int j = 0; j < PER; ++j)
+            if (rb[j] == b)
 #pragma unroll
-        for (int q = 0; q < 6; ++q) red[q][threadIdx.x] = v[q];
+                for (int q = 0; q < 6; ++q) v[q] += rv[j][q];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) v[q] = wave_sum_d(v[q]);
+        if ((threadIdx.x & 63) == 0)
+#pragma unroll
+            for (int q = 0; q < 6; ++q) part[threadIdx.x >> 6][q] = v[q];
         __syncthreads();
-        for (int o = blockDim.x >> 1; o > 0; o >>= 1) {
-            if ((int)threadIdx.x < o)
+        if (threadIdx.x < 6) {
+            double t = 0.0;
 #pragma unroll
-                for (int q = 0; q < 6; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + o];
-            __syncthreads();
+            for (int w = 0; w < NW; ++w) t += part[w][threadIdx.x];
+            C.acc[b][threadIdx.x] += t;
         }
-        if (threadIdx.x < 6) C.acc[b][threadIdx.x] += red[threadIdx.x][0];
         __syncthreads();
     }
 }
 
-// clear the other parity's counters and / or retire body moves
-__device__ __forceinline__ void phase_finish(const Inst& I, int parity, bool zero_other, bool retire_moves) {
-    if (zero_other) {
-        StepCounters& O = I.ctl->cnt[parity ^ 1];
-        int* ci = (int*)&O;
-        const int nint = (int)(offsetof(StepCounters, acc) / sizeof(int));
-        for (int q = threadIdx.x; q < nint; q += blockDim.x) ci[q] = 0;
-        for (int q = threadIdx.x; q < MAXB * 6; q += blockDim.x) (&O.acc[0][0])[q] = 0.0;
+// clear the other parity's counters
+__device__ __forceinline__ void phase_finish(const Inst& I, int parity) {
+    StepCounters& O = I.ctl->cnt[parity ^ 1];
+    int* ci = (int*)&O;
+    const int nint = (int)(offsetof(StepCounters, acc) / sizeof(int));
+    for (int q = threadIdx.x; q < nint; q += blockDim.x) ci[q] = 0;
+    for (int q = threadIdx.x; q < MAXB * 6; q += blockDim.x) (&O.acc[0][0])[q] = 0.0;
+}
+
+// Bodies after the force reduction of a full step, run by one wavefront
+// (lane b owns body b).  A body remapped at the start of the step now has
+// its obstacle cells at its pose (retire the move).  Free bodies then take
+// the rigid-body update driven by the mean of this and the previous step's
+// force and torque; the new pose is mapped by the next step's remap.  An
+// update that would leave the domain's interior, reach one cell per step at
+// the surface, jump a cell from the mapped pose or bring two bodies closer
+// than three cells is rejected: the body keeps its pose and Ctl::body_err
+// records why.
+__device__ __forceinline__ void bodies_wave(const Inst& I, int parity, bool retire_moves, bool integrate) {
+    const int b = threadIdx.x & 63;
+    const bool mine = b < I.nbodies;
+    double pos[3] = {0, 0, 0}, quat[4] = {1, 0, 0, 0}, vel[3] = {0, 0, 0}, om[3] = {0, 0, 0}, ext[3] = {0, 0, 0};
+    double R[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    bool upd = false, act = false;
+    if (mine) {
+        DevBody& B = I.bodies[b];
+        act = B.active != 0;
+        if (retire_moves && B.moved) {
+            B.moved = 0;
+            B.mapped = 1;
+            for (int a = 0; a < 3; ++a) {
+                B.prev_pos[a] = B.pos[a];
+                B.prev_ext[a] = B.ext[a];
+            }
+        }
+        for (int a = 0; a < 3; ++a) {
+            pos[a] = B.pos[a];
+            ext[a] = B.ext[a];
+        }
+        if (integrate && B.active && B.free_body && B.dof) {
+            const double* acc = I.ctl->cnt[parity].acc[b];
+            double F[3], T[3];
+            for (int a = 0; a < 3; ++a) {
+                F[a] = B.have_prev ? 0.5 * (acc[a] + B.fprev[a]) : acc[a];
+                T[a] = B.have_prev ? 0.5 * (acc[3 + a] + B.fprev[3 + a]) : acc[3 + a];
+            }
+            for (int a = 0; a < 6; ++a) B.fprev[a] = acc[a];
+            B.have_prev = 1;
+            const double accel[3] = {(double)I.ax, (double)I.ay, (double)I.az};
+            upd = integrate_rigid(B.half, B.pos, B.quat, B.vel, B.omega, B.density, F, T, accel, B.dof, pos, quat,
+                                  vel, om);
+            if (upd) {
+                const double n[3] = {(double)I.nx, (double)I.ny, (double)I.nz};
+                for (int a = 0; a < 3; ++a)
+                    if (I.periodic & (1u << a)) pos[a] = pos[a] - n[a] * floor(pos[a] / n[a]);
+                quat_to_R(quat, R);
+                box_extent(R, B.half, ext);
+            }
+        }
     }
-    if (retire_moves && (int)threadIdx.x < I.nbodies) {
-        DevBody& b = I.bodies[threadIdx.x];
-        if (b.moved) {
-            b.moved = 0;
-            b.prev_pos[0] = b.pos[0];
-            b.prev_pos[1] = b.pos[1];
-            b.prev_pos[2] = b.pos[2];
+    // separation from every other body at its (new) pose
+    const double n[3] = {(double)I.nx, (double)I.ny, (double)I.nz};
+    bool close = false;
+    for (int j = 0; j < I.nbodies; ++j) {
+        const bool aj = __shfl((int)act, j) != 0;
+        bool sep = false;
+        for (int a = 0; a < 3; ++a) {
+            const double pj = __shfl(pos[a], j), ej = __shfl(ext[a], j);
+            const double dd = wrap_rel(pos[a] - pj, n[a], I.periodic & (1u << a));
+            if (fabs(dd) >= ext[a] + ej + 3.0) sep = true;
+        }
+        if (j != b && aj && !sep) close = true;
+    }
+    if (upd) {
+        DevBody& B = I.bodies[b];
+        int err = close ? BODY_ERR_CLOSE : 0;
+        const double Rc = sqrt(B.half[0] * B.half[0] + B.half[1] * B.half[1] + B.half[2] * B.half[2]);
+        const double speed = sqrt(vel[0] * vel[0] + vel[1] * vel[1] + vel[2] * vel[2]) +
+                             sqrt(om[0] * om[0] + om[1] * om[1] + om[2] * om[2]) * Rc;
+        if (!(speed < 1.0)) err |= BODY_ERR_SPEED;
+        for (int a = 0; a < 3; ++a) {
+            const bool per = I.periodic & (1u << a);
+            if (per) {
+                if (2.0 * ext[a] >= n[a] && !(B.half[a] >= 0.5 * n[a] && ext[a] == B.half[a])) err |= BODY_ERR_WALL;
+            } else if (!(pos[a] - ext[a] >= 1.0 && pos[a] + ext[a] <= n[a] - 1.0)) {
+                err |= BODY_ERR_WALL;
+            }
+            if (B.mapped && !(fabs(wrap_rel(pos[a] - B.prev_pos[a], n[a], per)) < 1.0)) err |= BODY_ERR_JUMP;
+        }
+        if (err) {
+            atomicOr(&I.ctl->body_err, err);
+        } else {
+            for (int a = 0; a < 3; ++a) {
+                B.pos[a] = pos[a];
+                B.vel[a] = vel[a];
+                B.omega[a] = om[a];
+                B.ext[a] = ext[a];
+            }
+            for (int a = 0; a < 4; ++a) B.quat[a] = quat[a];
+            for (int a = 0; a < 9; ++a) B.R[a] = R[a];
+            B.moved = 1;
         }
     }
 }
 
+// One step's conversions.  The last wavefront updates the bodies while the
+// others claim; the later phases use all groups.
 template <typename S>
-__global__ __launch_bounds__(CONV_THREADS) void k_convert(Inst I, int parity, int retire_moves,
-                                                          unsigned long long seq) {
+__global__ __launch_bounds__(CONV_THREADS) void k_convert(Inst I, int parity, int retire_moves, int integrate) {
     phase_forces(I, parity);
-    if (I.hout && seq) {
-        // hand the forces to the host early: the conversions do not change them
-        StepCounters& C = I.ctl->cnt[parity];
-        for (int q = threadIdx.x; q < I.nbodies * 6; q += blockDim.x) I.hout->acc[q / 6][q % 6] = C.acc[q / 6][q % 6];
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            __threadfence_system();
-            I.hout->seq = seq;
-        }
-    }
-    phase_claim<S>(I, parity);
+    if ((int)(threadIdx.x >> 6) == CONV_THREADS / 64 - 1) bodies_wave(I, parity, retire_moves != 0, integrate != 0);
+    else phase_claim<S>(I, parity, threadIdx.x >> 5, CONV_THREADS / 32 - 2);
+    __syncthreads();
+    phase_newgas<S>(I, parity);
     __syncthreads();
     phase_share(I, parity);
     __syncthreads();
     phase_commit<S>(I, parity);
     __syncthreads();
-    phase_finish(I, parity, true, retire_moves != 0);
+    phase_finish(I, parity);
 }
 
 // End of a step without conversions (phase-isolated calls).
 __global__ __launch_bounds__(CONV_THREADS) void k_finish(Inst I, int parity, int reduce, int zero_other,
                                                          int retire_moves) {
     if (reduce) phase_forces(I, parity);
-    phase_finish(I, parity, zero_other != 0, retire_moves != 0);
+    if (threadIdx.x < 64) bodies_wave(I, parity, retire_moves != 0, false);
+    if (zero_other) phase_finish(I, parity);
 }
 
-void launch_convert(const Inst& I, int parity, bool retire_moves, unsigned long long seq, hipStream_t s) {
+void launch_convert(const Inst& I, int parity, bool retire_moves, bool integrate, hipStream_t s) {
     const dim3 g(1), b(CONV_THREADS);
-    const int r = (int)retire_moves;
+    const int r = (int)retire_moves, n = (int)integrate;
     switch (I.storage) {
-    case LBM_FP16_DEV: hipLaunchKernelGGL(k_convert<__half>, g, b, 0, s, I, parity, r, seq); break;
-    case LBM_BF16_DEV: hipLaunchKernelGGL(k_convert<__hip_bfloat16>, g, b, 0, s, I, parity, r, seq); break;
-    default: hipLaunchKernelGGL(k_convert<float>, g, b, 0, s, I, parity, r, seq); break;
+    case LBM_FP16_DEV: hipLaunchKernelGGL(k_convert<__half>, g, b, 0, s, I, parity, r, n); break;
+    case LBM_BF16_DEV: hipLaunchKernelGGL(k_convert<__hip_bfloat16>, g, b, 0, s, I, parity, r, n); break;
+    default: hipLaunchKernelGGL(k_convert<float>, g, b, 0, s, I, parity, r, n); break;
     }
 }
 

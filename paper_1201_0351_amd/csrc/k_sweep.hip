@@ -217,36 +217,7 @@ __global__ __launch_bounds__(256) void k_sweep_bulk(Inst I, int parity, int tile
 // mass exchange and the momentum exchange are butterfly reductions over the
 // group, values of the opposite link come from lane ibar by a shuffle.
 // ---------------------------------------------------------------------------
-namespace {
 
-// link tables packed into constants: 2 bits (c + 1) per link, 5 bits per
-// opposite index (links 0..11 in OPP_LO, 12..18 in OPP_HI)
-constexpr unsigned long long pack_c(int a) {
-    unsigned long long v = 0;
-    for (int i = 0; i < Q; ++i) v |= (unsigned long long)((a == 0 ? cx(i) : a == 1 ? cy(i) : cz(i)) + 1) << (2 * i);
-    return v;
-}
-constexpr unsigned long long pack_opp(int lo, int hi) {
-    unsigned long long v = 0;
-    for (int i = lo; i < hi; ++i) v |= (unsigned long long)opp(i) << (5 * (i - lo));
-    return v;
-}
-constexpr unsigned long long CXP = pack_c(0), CYP = pack_c(1), CZP = pack_c(2);
-constexpr unsigned long long OPP_LO = pack_opp(0, 12), OPP_HI = pack_opp(12, Q);
-
-__device__ __forceinline__ int lane_c(unsigned long long P, int i) { return (int)((P >> (2 * i)) & 3ull) - 1; }
-__device__ __forceinline__ int lane_opp(int i) {
-    return i < 12 ? (int)((OPP_LO >> (5 * i)) & 31ull) : (int)((OPP_HI >> (5 * (i - 12))) & 31ull);
-}
-__device__ __forceinline__ float lane_w(int i) { return i == 0 ? 1.f / 3.f : (i < 7 ? 1.f / 18.f : 1.f / 36.f); }
-
-__device__ __forceinline__ float gsum(float v) {
-#pragma unroll
-    for (int o = 16; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
-}  // namespace
 
 template <typename S>
 __global__ __launch_bounds__(256) void k_sweep_boundary(Inst I, int parity) {
@@ -266,7 +237,7 @@ __global__ __launch_bounds__(256) void k_sweep_boundary(Inst I, int parity) {
     const float wi = lane_w(i);
     const int nwaves = (gridDim.x * blockDim.x) >> 6;
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    // this wavefront's momentum-exchange record (first body it meets)
+    // this wavefront's momentum-exchange partial sum (first body it meets)
     int rec_body = -1;
     double rv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 
@@ -448,11 +419,34 @@ __global__ __launch_bounds__(256) void k_sweep_boundary(Inst I, int parity) {
             m &= ~__ballot(mine);
         }
     }
+    // the workgroup's record: its wavefronts' records in wavefront order
+    __shared__ int sb[4];
+    __shared__ double sv[4][6];
+    const int wv = threadIdx.x >> 6;
     if (lane_id() == 0) {
-        ForceRec& r = I.frec[wave];
-        r.body = rec_body;
+        sb[wv] = rec_body;
 #pragma unroll
-        for (int q = 0; q < 6; ++q) r.v[q] = rv[q];
+        for (int q = 0; q < 6; ++q) sv[wv][q] = rv[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int body = -1;
+        double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int w = 0; w < 4; ++w) {
+            const int b = sb[w];
+            if (b < 0) continue;
+            if (body < 0) body = b;
+            if (b == body) {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) acc[q] += sv[w][q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) atomicAdd(&C.acc[b][q], sv[w][q]);
+            }
+        }
+        I.frec_body[blockIdx.x] = body;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) I.frec_v[q * BND_BLOCKS_MAX + blockIdx.x] = acc[q];
     }
 }
 

@@ -40,14 +40,11 @@ size_t storage_bytes(int storage) { return storage == LBM_FP32 ? 4 : 2; }
 struct InstHost {
     lbm_config cfg;
     Inst dev;
-    DevBody bodies[MAXB];
-    lbm_body desc[MAXB];  // caller's description (free bodies are integrated from it)
-    double fprev[MAXB][6];
-    bool have_prev[MAXB];
-    bool mapped[MAXB];
-    double mapped_pos[MAXB][3];
-    double mapped_ext[MAXB][3];
-    bool need_remap;
+    DevBody bodies[MAXB];  // host copy, refreshed from the device before use
+    lbm_body desc[MAXB];   // caller's description (shape, density, mode)
+    bool need_remap;       // a body was set since the last remap
+    bool any_free;         // some body is integrated on the device
+    int remap_blocks;      // workgroups per body of the remap kernels
     size_t offset, bytes;
 };
 
@@ -78,7 +75,8 @@ size_t layout(const lbm_config& c, Inst* I, char* base) {
     char* l2 = take(4 * N);
     char* l3 = take(4 * N);
     char* l4 = take(4 * N);
-    char* fr = take(sizeof(ForceRec) * BND_BLOCKS_MAX * 4);
+    char* fb = take(sizeof(int) * BND_BLOCKS_MAX);
+    char* fv = take(sizeof(double) * 6 * BND_BLOCKS_MAX);
     char* ct = take(sizeof(Ctl));
     char* bd = take(sizeof(DevBody) * MAXB);
     if (I) {
@@ -99,7 +97,8 @@ size_t layout(const lbm_config& c, Inst* I, char* base) {
         I->newl = (int*)l2;
         I->recv = (int*)l3;
         I->bnd = (int*)l4;
-        I->frec = (ForceRec*)fr;
+        I->frec_body = (int*)fb;
+        I->frec_v = (double*)fv;
         I->ctl = (Ctl*)ct;
         I->bodies = (DevBody*)bd;
         I->list_cap = (int)N;
@@ -133,19 +132,6 @@ int validate(const lbm_config& c, int k) {
     return LBM_OK;
 }
 
-void quat_to_R(const double q[4], double R[9]) {
-    const double w = q[0], x = q[1], y = q[2], z = q[3];
-    R[0] = 1.0 - 2.0 * (y * y + z * z);
-    R[1] = 2.0 * (x * y - w * z);
-    R[2] = 2.0 * (x * z + w * y);
-    R[3] = 2.0 * (x * y + w * z);
-    R[4] = 1.0 - 2.0 * (x * x + z * z);
-    R[5] = 2.0 * (y * z - w * x);
-    R[6] = 2.0 * (x * z - w * y);
-    R[7] = 2.0 * (y * z + w * x);
-    R[8] = 1.0 - 2.0 * (x * x + y * y);
-}
-
 }  // namespace
 
 struct lbm_ctx {
@@ -161,8 +147,6 @@ struct lbm_ctx {
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;  // begin/end pairs of timed sweeps
     size_t ev_used = 0;
-    HostOut* hout = nullptr;      // mapped coherent host records, one per instance
-    unsigned long long seq = 0;   // step sequence number for the host records
 };
 
 static hipEvent_t next_event(lbm_ctx* c) {
@@ -221,20 +205,6 @@ int32_t lbm_create(const lbm_config* cfgs, int32_t n_inst, void* d_workspace, si
         c->own_ws = true;
     }
     c->inst.resize(n_inst);
-    if (hipHostMalloc((void**)&c->hout, sizeof(HostOut) * n_inst, hipHostMallocMapped | hipHostMallocCoherent) !=
-        hipSuccess) {
-        if (c->own_ws) (void)hipFree(c->ws);
-        delete c;
-        return fail(LBM_ERR_NOMEM, "create: mapped host buffer");
-    }
-    memset((void*)c->hout, 0, sizeof(HostOut) * n_inst);
-    HostOut* hout_dev = nullptr;
-    if (hipHostGetDevicePointer((void**)&hout_dev, (void*)c->hout, 0) != hipSuccess || !hout_dev) {
-        (void)hipHostFree((void*)c->hout);
-        if (c->own_ws) (void)hipFree(c->ws);
-        delete c;
-        return fail(LBM_ERR_DEVICE, "create: no device view of the mapped host buffer");
-    }
     size_t off = 0;
     for (int k = 0; k < n_inst; ++k) {
         InstHost& h = c->inst[k];
@@ -261,7 +231,6 @@ int32_t lbm_create(const lbm_config* cfgs, int32_t n_inst, void* d_workspace, si
         I.scale = h.cfg.storage == LBM_FP16_DEV ? (float)h.cfg.fp16_scale : 1.f;
         I.inv_scale = 1.f / I.scale;
         I.eps = h.cfg.eps;
-        I.hout = hout_dev ? hout_dev + k : nullptr;
         const size_t N = (size_t)I.N;
         HIP_OK(hipMemsetAsync(I.ctl, 0, sizeof(Ctl), c->stream));
         HIP_OK(hipMemsetAsync(I.bodies, 0, sizeof(DevBody) * MAXB, c->stream));
@@ -281,7 +250,6 @@ int32_t lbm_destroy(lbm_ctx* c) {
     else (void)hipDeviceSynchronize();
     if (c->own_ws) (void)hipFree(c->ws);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
-    if (c->hout) (void)hipHostFree((void*)c->hout);
     delete c;
     return LBM_OK;
 }
@@ -292,19 +260,42 @@ static int check_inst(lbm_ctx* c, int inst) {
     return LBM_OK;
 }
 
-static int set_body_impl(lbm_ctx* c, int inst, int k, const lbm_body* b, bool keep_prev);
+// Copy the device body records into the host copy (the device owns the
+// state of free bodies and the mapping bookkeeping).
+static int pull_bodies(lbm_ctx* c, InstHost& h) {
+    HIP_OK(hipStreamSynchronize(c->stream));
+    HIP_OK(hipMemcpy(h.bodies, h.dev.bodies, sizeof(DevBody) * MAXB, hipMemcpyDeviceToHost));
+    return LBM_OK;
+}
+
+static void refresh_instance_flags(InstHost& h) {
+    h.any_free = false;
+    h.remap_blocks = 0;
+    for (int k = 0; k < h.dev.nbodies; ++k) {
+        const DevBody& d = h.bodies[k];
+        if (!d.active) continue;
+        if (d.free_body && d.dof) h.any_free = true;
+        // the remap box is at most 2 Rc + 9 cells wide on each axis (old and
+        // new bounding boxes within a cell of each other, two cells margin)
+        const double Rc = std::sqrt(d.half[0] * d.half[0] + d.half[1] * d.half[1] + d.half[2] * d.half[2]);
+        const double w = std::ceil(2.0 * Rc) + 9.0;
+        const double cells = w * w * w;
+        const int blocks = (int)std::min(512.0, std::ceil(cells / 256.0));
+        h.remap_blocks = std::max(h.remap_blocks, blocks);
+    }
+}
 
 int32_t lbm_set_body(lbm_ctx* c, int32_t inst, int32_t k, const lbm_body* b) {
     int rc = check_inst(c, inst);
     if (rc) return rc;
-    return set_body_impl(c, inst, k, b, false);
-}
-
-static int set_body_impl(lbm_ctx* c, int inst, int k, const lbm_body* b, bool keep_prev) {
     InstHost& h = c->inst[inst];
     if (!b || k < 0 || k >= MAXB || k >= std::max(1, h.cfg.max_bodies))
         return fail(LBM_ERR_INVALID, "set_body: body index out of range (raise max_bodies)");
+    rc = pull_bodies(c, h);
+    if (rc) return rc;
     const double n[3] = {(double)h.cfg.nx, (double)h.cfg.ny, (double)h.cfg.nz};
+    const DevBody& old = h.bodies[k];
+    const bool was_mapped = old.active && old.mapped;
     DevBody d;
     memset(&d, 0, sizeof d);
     for (int a = 0; a < 3; ++a) {
@@ -319,10 +310,9 @@ static int set_body_impl(lbm_ctx* c, int inst, int k, const lbm_body* b, bool ke
     const double qn = std::sqrt(b->quat[0] * b->quat[0] + b->quat[1] * b->quat[1] + b->quat[2] * b->quat[2] +
                                 b->quat[3] * b->quat[3]);
     if (!(std::fabs(qn - 1.0) < 1e-6)) return fail(LBM_ERR_INVALID, "set_body: quaternion must be unit");
+    for (int a = 0; a < 4; ++a) d.quat[a] = b->quat[a];
     quat_to_R(b->quat, d.R);
-    for (int a = 0; a < 3; ++a)
-        d.ext[a] = std::fabs(d.R[a * 3 + 0]) * d.half[0] + std::fabs(d.R[a * 3 + 1]) * d.half[1] +
-                   std::fabs(d.R[a * 3 + 2]) * d.half[2];
+    box_extent(d.R, d.half, d.ext);
     const double Rc = std::sqrt(d.half[0] * d.half[0] + d.half[1] * d.half[1] + d.half[2] * d.half[2]);
     // inside the non-periodic extent with a free cell of margin
     for (int a = 0; a < 3; ++a) {
@@ -337,9 +327,9 @@ static int set_body_impl(lbm_ctx* c, int inst, int k, const lbm_body* b, bool ke
     const double speed = std::sqrt(d.vel[0] * d.vel[0] + d.vel[1] * d.vel[1] + d.vel[2] * d.vel[2]) +
                          std::sqrt(d.omega[0] * d.omega[0] + d.omega[1] * d.omega[1] + d.omega[2] * d.omega[2]) * Rc;
     if (!(speed < 1.0)) return fail(LBM_ERR_INVALID, "set_body: surface speed must be below one cell per step");
-    if (h.mapped[k]) {
+    if (was_mapped) {
         for (int a = 0; a < 3; ++a) {
-            const double dd = wrap_rel(d.pos[a] - h.mapped_pos[k][a], n[a], h.cfg.periodic & (1 << a));
+            const double dd = wrap_rel(d.pos[a] - old.prev_pos[a], n[a], h.cfg.periodic & (1 << a));
             if (!(std::fabs(dd) < 1.0))
                 return fail(LBM_ERR_INVALID, "set_body: body moved a cell or more since its last mapping");
         }
@@ -355,16 +345,24 @@ static int set_body_impl(lbm_ctx* c, int inst, int k, const lbm_body* b, bool ke
     }
     if (b->fixed == 0 && (b->dof_mask & ~0x3Fu)) return fail(LBM_ERR_INVALID, "set_body: dof_mask has unknown bits");
     if (b->fixed == 0 && !(b->density > 0.0)) return fail(LBM_ERR_INVALID, "set_body: free body needs a density > 0");
+    d.density = b->density;
+    d.free_body = b->fixed == 0 ? 1 : 0;
+    d.dof = b->fixed == 0 ? b->dof_mask : 0u;
     d.active = 1;
     d.moved = 1;
+    d.mapped = was_mapped ? 1 : 0;
+    for (int a = 0; a < 3; ++a) {
+        d.prev_pos[a] = was_mapped ? old.prev_pos[a] : d.pos[a];
+        d.prev_ext[a] = was_mapped ? old.prev_ext[a] : d.ext[a];
+    }
     h.desc[k] = *b;
     for (int a = 0; a < 3; ++a) h.desc[k].pos[a] = d.pos[a];
-    if (!keep_prev) h.have_prev[k] = false;
-    for (int a = 0; a < 3; ++a) d.prev_pos[a] = h.mapped[k] ? h.mapped_pos[k][a] : d.pos[a];
     h.bodies[k] = d;
     if (k + 1 > h.dev.nbodies) h.dev.nbodies = k + 1;
     h.need_remap = true;
+    refresh_instance_flags(h);
     launch_set_body(h.dev, k, h.bodies[k], c->stream);
+    HIP_OK(hipGetLastError());
     return LBM_OK;
 }
 
@@ -373,71 +371,20 @@ int32_t lbm_get_body(lbm_ctx* c, int32_t inst, int32_t k, lbm_body* b) {
     if (rc) return rc;
     InstHost& h = c->inst[inst];
     if (!b || k < 0 || k >= h.dev.nbodies || !h.bodies[k].active) return fail(LBM_ERR_INVALID, "get_body: no such body");
+    rc = pull_bodies(c, h);
+    if (rc) return rc;
+    const DevBody& d = h.bodies[k];
     *b = h.desc[k];
-    return LBM_OK;
-}
-
-static void after_remap(InstHost& h) {
-    for (int k = 0; k < h.dev.nbodies; ++k) {
-        DevBody& d = h.bodies[k];
-        if (!d.active || !d.moved) continue;
-        d.moved = 0;
-        for (int a = 0; a < 3; ++a) d.prev_pos[a] = d.pos[a], h.mapped_pos[k][a] = d.pos[a], h.mapped_ext[k][a] = d.ext[a];
-        h.mapped[k] = true;
+    for (int a = 0; a < 3; ++a) {
+        b->pos[a] = d.pos[a];
+        b->vel[a] = d.vel[a];
+        b->omega[a] = d.omega[a];
     }
-    h.need_remap = false;
+    for (int a = 0; a < 4; ++a) b->quat[a] = d.quat[a];
+    return LBM_OK;
 }
 
 __global__ void k_copy_state(Inst I, int from);
-
-// Host update of free bodies after a full step: the end-of-step kernel writes
-// the forces into mapped host memory and then the step's sequence number; the
-// host spins on it (falling back to a stream synchronisation after 1 s), takes
-// the mean of this and the previous step's force / torque, runs
-// lbm_integrate_body and sets the next pose.
-static int couple_free_bodies(lbm_ctx* c, int p) {
-    (void)p;
-    bool any = false;
-    for (int k = 0; k < c->n_inst && !any; ++k) {
-        InstHost& h = c->inst[k];
-        for (int b = 0; b < h.dev.nbodies; ++b)
-            if (h.bodies[b].active && h.desc[b].fixed == 0 && h.desc[b].dof_mask) any = true;
-    }
-    if (!any) return LBM_OK;
-    HIP_OK(hipGetLastError());
-    const auto t0 = std::chrono::steady_clock::now();
-    for (int k = 0; k < c->n_inst; ++k) {
-        for (long spin = 0; c->hout[k].seq < c->seq; ++spin) {
-            if ((spin & 1023) == 1023 &&
-                std::chrono::steady_clock::now() - t0 > std::chrono::seconds(1)) {
-                HIP_OK(hipStreamSynchronize(c->stream));
-                if (c->hout[k].seq < c->seq) return fail(LBM_ERR_DEVICE, "step did not deliver body forces");
-            }
-        }
-    }
-    std::atomic_thread_fence(std::memory_order_acquire);
-    for (int k = 0; k < c->n_inst; ++k) {
-        InstHost& h = c->inst[k];
-        for (int b = 0; b < h.dev.nbodies; ++b) {
-            if (!h.bodies[b].active || h.desc[b].fixed != 0 || !h.desc[b].dof_mask) continue;
-            double fnow[6];
-            for (int a = 0; a < 6; ++a) fnow[a] = c->hout[k].acc[b][a];
-            double F[3], T[3];
-            for (int a = 0; a < 3; ++a) {
-                F[a] = h.have_prev[b] ? 0.5 * (fnow[a] + h.fprev[b][a]) : fnow[a];
-                T[a] = h.have_prev[b] ? 0.5 * (fnow[3 + a] + h.fprev[b][3 + a]) : fnow[3 + a];
-            }
-            for (int a = 0; a < 6; ++a) h.fprev[b][a] = fnow[a];
-            h.have_prev[b] = true;
-            lbm_body nb;
-            int rc = lbm_integrate_body(&h.desc[b], F, T, h.cfg.accel, h.desc[b].dof_mask, &nb);
-            if (rc) return rc;
-            rc = set_body_impl(c, k, b, &nb, true);
-            if (rc) return rc;
-        }
-    }
-    return LBM_OK;
-}
 
 static int run_step(lbm_ctx* c, int mask) {
     const int p = c->parity;
@@ -446,34 +393,8 @@ static int run_step(lbm_ctx* c, int mask) {
         InstHost& h = c->inst[k];
         bool remapped = false;
         if ((mask & LBM_PHASE_REMAP) && h.need_remap) {
-            RemapRegions R;
-            memset(&R, 0, sizeof R);
-            const int n[3] = {h.cfg.nx, h.cfg.ny, h.cfg.nz};
-            for (int b = 0; b < h.dev.nbodies; ++b) {
-                const DevBody& d = h.bodies[b];
-                if (!d.active || !d.moved) continue;
-                int cells = 1;
-                for (int a = 0; a < 3; ++a) {
-                    const double pp = h.mapped[b] ? h.mapped_pos[b][a] : d.pos[a];
-                    const double pe = h.mapped[b] ? h.mapped_ext[b][a] : d.ext[a];
-                    // the minimum image keeps old and new pose together on a periodic axis
-                    const double np = pp + wrap_rel(d.pos[a] - pp, n[a], h.cfg.periodic & (1 << a));
-                    const int lo = (int)std::floor(std::min(pp - pe, np - d.ext[a]) - 2.0);
-                    const int hi = (int)std::ceil(std::max(pp + pe, np + d.ext[a]) + 2.0);
-                    int dim = hi - lo + 1;
-                    int l0 = lo;
-                    if ((h.cfg.periodic & (1 << a)) && dim >= n[a]) {
-                        l0 = 0;
-                        dim = n[a];
-                    }
-                    R.lo[b][a] = l0;
-                    R.dim[b][a] = dim;
-                    cells *= dim;
-                }
-                R.cells[b] = cells;
-            }
-            launch_remap(h.dev, p, R, c->stream);
-            after_remap(h);
+            launch_remap(h.dev, p, h.remap_blocks, c->stream);
+            h.need_remap = false;
             remapped = true;
         }
         if (mask & LBM_PHASE_SWEEP) {
@@ -489,19 +410,18 @@ static int run_step(lbm_ctx* c, int mask) {
             hipLaunchKernelGGL(k_copy_state, dim3((h.dev.N + 255) / 256), dim3(256), 0, c->stream, h.dev, p);
             launch_mark(h.dev, p, c->stream);
         }
-        if (mask & LBM_PHASE_CONVERT) launch_convert(h.dev, p, remapped, mask == LBM_PHASE_ALL ? c->seq + 1 : 0, c->stream);
+        const bool integrate = mask == LBM_PHASE_ALL && h.any_free;
+        if (mask & LBM_PHASE_CONVERT) launch_convert(h.dev, p, remapped, integrate, c->stream);
         else if (advances || remapped)
             launch_finish(h.dev, p, (mask & LBM_PHASE_SWEEP) != 0, advances, remapped, c->stream);
+        // free bodies moved on the device: the next step maps them
+        if (integrate) h.need_remap = true;
     }
     HIP_OK(hipGetLastError());
     if (advances) {
         c->last_parity = p;
         c->have_forces = (mask & LBM_PHASE_SWEEP) != 0;
         c->parity ^= 1;
-    }
-    if (mask == LBM_PHASE_ALL) {
-        ++c->seq;
-        return couple_free_bodies(c, p);
     }
     return LBM_OK;
 }
@@ -531,7 +451,17 @@ static int sync_and_check(lbm_ctx* c) {
         int ov[2];
         HIP_OK(hipMemcpy(&ov[0], &ctl->cnt[0].overflow, sizeof(int), hipMemcpyDeviceToHost));
         HIP_OK(hipMemcpy(&ov[1], &ctl->cnt[1].overflow, sizeof(int), hipMemcpyDeviceToHost));
+        int berr = 0;
+        HIP_OK(hipMemcpy(&berr, &ctl->body_err, sizeof(int), hipMemcpyDeviceToHost));
         if (flags[0]) return fail(LBM_ERR_UNSTABLE, "non-finite or non-positive density detected");
+        if (berr) {
+            std::string why;
+            if (berr & BODY_ERR_WALL) why += " left the domain interior;";
+            if (berr & BODY_ERR_SPEED) why += " surface speed reached one cell per step;";
+            if (berr & BODY_ERR_CLOSE) why += " bodies closer than three cells;";
+            if (berr & BODY_ERR_JUMP) why += " moved a cell from its mapping;";
+            return fail(LBM_ERR_UNSTABLE, "free-body update rejected:" + why);
+        }
         if (ov[0] || ov[1]) return fail(LBM_ERR_UNSTABLE, "conversion list overflow");
     }
     return LBM_OK;
@@ -773,14 +703,21 @@ int32_t lbm_write_fields(lbm_ctx* c, int32_t inst, int32_t field, int32_t dtype,
             }
         }
         HIP_OK(hipMemcpy(I.flags, a.data(), N, hipMemcpyHostToDevice));
-        // the written obstacle cells are the bodies' mappings
+        // the written obstacle cells are the bodies' mappings at their poses
+        rc = pull_bodies(c, h);
+        if (rc) return rc;
         for (int k = 0; k < h.dev.nbodies; ++k) {
-            if (!h.bodies[k].active) continue;
-            h.bodies[k].moved = 1;
+            DevBody& d = h.bodies[k];
+            if (!d.active) continue;
+            d.moved = 0;
+            d.mapped = 1;
+            for (int a2 = 0; a2 < 3; ++a2) {
+                d.prev_pos[a2] = d.pos[a2];
+                d.prev_ext[a2] = d.ext[a2];
+            }
+            launch_set_body(I, k, d, c->stream);
         }
-        after_remap(h);
-        for (int k = 0; k < h.dev.nbodies; ++k)
-            if (h.bodies[k].active) launch_set_body(I, k, h.bodies[k], c->stream);
+        h.need_remap = false;
         HIP_OK(hipStreamSynchronize(c->stream));
         return LBM_OK;
     }
@@ -822,65 +759,10 @@ int32_t lbm_write_fields(lbm_ctx* c, int32_t inst, int32_t field, int32_t dtype,
 int32_t lbm_integrate_body(const lbm_body* in, const double F[3], const double T[3], const double accel[3],
                            uint32_t dof, lbm_body* out) {
     if (!in || !F || !T || !accel || !out) return fail(LBM_ERR_INVALID, "integrate_body: NULL argument");
-    const double* h = in->half_ext;
-    const double M = in->density * 8.0 * h[0] * h[1] * h[2];
-    if (!(M > 0.0)) return fail(LBM_ERR_INVALID, "integrate_body: body mass must be positive");
     lbm_body o = *in;
-    for (int a = 0; a < 3; ++a)
-        if (dof & (1u << a)) o.vel[a] = in->vel[a] + (F[a] + M * accel[a]) / M;
-    double R[9];
-    quat_to_R(in->quat, R);
-    const double Ib[3] = {M / 3.0 * (h[1] * h[1] + h[2] * h[2]), M / 3.0 * (h[0] * h[0] + h[2] * h[2]),
-                          M / 3.0 * (h[0] * h[0] + h[1] * h[1])};
-    double Iw[9];
-    for (int r = 0; r < 3; ++r)
-        for (int cc = 0; cc < 3; ++cc) {
-            double acc = 0.0;
-            for (int k = 0; k < 3; ++k) acc += R[r * 3 + k] * Ib[k] * R[cc * 3 + k];
-            Iw[r * 3 + cc] = acc;
-        }
-    int S[3], ns = 0;
-    for (int a = 0; a < 3; ++a)
-        if (dof & (8u << a)) S[ns++] = a;
-    if (ns > 0) {
-        double A[3][4];
-        for (int r = 0; r < ns; ++r) {
-            for (int cc = 0; cc < ns; ++cc) A[r][cc] = Iw[S[r] * 3 + S[cc]];
-            A[r][ns] = T[S[r]];
-        }
-        for (int pv = 0; pv < ns; ++pv) {
-            int best = pv;
-            for (int r = pv + 1; r < ns; ++r)
-                if (std::fabs(A[r][pv]) > std::fabs(A[best][pv])) best = r;
-            if (best != pv)
-                for (int cc = 0; cc <= ns; ++cc) std::swap(A[pv][cc], A[best][cc]);
-            for (int r = pv + 1; r < ns; ++r) {
-                const double f = A[r][pv] / A[pv][pv];
-                for (int cc = pv; cc <= ns; ++cc) A[r][cc] -= f * A[pv][cc];
-            }
-        }
-        double dw[3];
-        for (int r = ns - 1; r >= 0; --r) {
-            double acc = A[r][ns];
-            for (int cc = r + 1; cc < ns; ++cc) acc -= A[r][cc] * dw[cc];
-            dw[r] = acc / A[r][r];
-        }
-        for (int r = 0; r < ns; ++r) o.omega[S[r]] = in->omega[S[r]] + dw[r];
-    }
-    for (int a = 0; a < 3; ++a) o.pos[a] = in->pos[a] + o.vel[a];
-    const double* w = o.omega;
-    const double th = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
-    if (th > 0.0) {
-        const double s = std::sin(0.5 * th) / th;
-        const double dq[4] = {std::cos(0.5 * th), s * w[0], s * w[1], s * w[2]};
-        const double* q = in->quat;
-        double r[4] = {dq[0] * q[0] - dq[1] * q[1] - dq[2] * q[2] - dq[3] * q[3],
-                       dq[0] * q[1] + dq[1] * q[0] + dq[2] * q[3] - dq[3] * q[2],
-                       dq[0] * q[2] - dq[1] * q[3] + dq[2] * q[0] + dq[3] * q[1],
-                       dq[0] * q[3] + dq[1] * q[2] - dq[2] * q[1] + dq[3] * q[0]};
-        const double nn = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3]);
-        for (int a = 0; a < 4; ++a) o.quat[a] = r[a] / nn;
-    }
+    if (!integrate_rigid(in->half_ext, in->pos, in->quat, in->vel, in->omega, in->density, F, T, accel, dof, o.pos,
+                         o.quat, o.vel, o.omega))
+        return fail(LBM_ERR_INVALID, "integrate_body: body mass must be positive");
     *out = o;
     return LBM_OK;
 }

@@ -80,38 +80,31 @@ struct Ctl {
     double mass_total;
     unsigned long long contacts;
     int nonfinite;
-    int pad;
+    int body_err;  // BODY_ERR_* bits of a rejected free-body update
 };
 
-// Momentum-exchange partial sum of one wavefront of the boundary sweep (over
-// its grid-stride loop) for one body (the first body the wavefront touches; further bodies of the same
-// wavefront go to the FP64 accumulators with atomics).  Records are summed in
-// slot order, so the force / torque sums do not depend on scheduling.
-struct ForceRec {
-    int body;  // -1: no contribution
-    int pad;
-    double v[6];
-};
-
-// Per-instance record in mapped, coherent host memory: the end-of-step
-// kernel writes the body forces of the step, then (after a system-scope
-// fence) the step's sequence number, which the host spins on.
-struct HostOut {
-    double acc[MAXB][6];
-    volatile unsigned long long seq;
-    unsigned long long pad[7];
-};
+// Reasons the device update of a free body was rejected (the body keeps its
+// pose; the next synchronising call reports the error).
+enum : int { BODY_ERR_WALL = 1, BODY_ERR_SPEED = 2, BODY_ERR_CLOSE = 4, BODY_ERR_JUMP = 8 };
 
 struct DevBody {
-    double pos[3];
-    double R[9];  // body -> world, row major
+    double pos[3];   // centre of gravity o
+    double quat[4];  // orientation (w, x, y, z), unit
+    double R[9];     // body -> world, row major
     double half[3];
     double vel[3];
     double omega[3];
-    double prev_pos[3];
-    double ext[3];  // world-frame half extent of the bounding box
+    double ext[3];       // world-frame half extent of the bounding box
+    double prev_pos[3];  // pose of the last mapping (valid if mapped)
+    double prev_ext[3];
+    double fprev[6];  // previous step's force / torque (free bodies)
+    double density;
+    uint32_t dof;  // free bodies: DOF mask (bits 0-2 translation, 3-5 rotation)
     int active;
-    int moved;  // pose changed since the last remap
+    int moved;      // pose changed since the last remap
+    int mapped;     // the obstacle cells of the body exist
+    int free_body;  // integrated on the device after every full step
+    int have_prev;
 };
 
 // Everything a kernel needs about one instance (passed by value).
@@ -141,8 +134,15 @@ struct Inst {
     int* newl;
     int* recv;
     int* bnd;  // cells the bulk sweep leaves to the boundary sweep
-    ForceRec* frec;  // one record per wavefront of the boundary sweep's grid
-    HostOut* hout;   // device view of the mapped host record (or null)
+    // Momentum-exchange partial sums of the boundary sweep, one record per
+    // workgroup of its grid (structure of arrays): the body the workgroup's
+    // first contributing wavefront met (-1: none) and F (3), T (3) in FP64
+    // at frec_v[q * BND_BLOCKS_MAX + block].  Contributions of the
+    // workgroup to any other body go to the FP64 accumulators by atomics.
+    // Records are summed in slot order, so with one body per workgroup the
+    // sums do not depend on scheduling.
+    int* frec_body;
+    double* frec_v;
     int list_cap;
     Ctl* ctl;
     DevBody* bodies;
@@ -282,14 +282,199 @@ __device__ inline int body_at(const Inst& I, int x, int y, int z) {
     return -1;
 }
 
-// Cells a body remap visits: per body an axis-aligned box covering its old
-// and new bounding boxes plus two cells (origin lo, extent dim; cells = 0 for
-// bodies that did not move).
-struct RemapRegions {
-    int lo[MAXB][3];
-    int dim[MAXB][3];
-    int cells[MAXB];
+// Cells a body remap visits: an axis-aligned box covering the bounding boxes
+// of the body's last mapped pose and its new pose plus two cells (origin lo,
+// extent dim).  On a periodic axis the new pose is taken at its minimum image
+// relative to the old one, and a box as wide as the axis covers it once.
+struct Region {
+    int lo[3];
+    int dim[3];
+    int cells;
 };
+
+__host__ __device__ inline Region body_region(const DevBody& d, int nx, int ny, int nz, uint32_t periodic) {
+    Region R;
+    const int n[3] = {nx, ny, nz};
+    R.cells = 1;
+    for (int a = 0; a < 3; ++a) {
+        const double pp = d.mapped ? d.prev_pos[a] : d.pos[a];
+        const double pe = d.mapped ? d.prev_ext[a] : d.ext[a];
+        const double np = pp + wrap_rel(d.pos[a] - pp, (double)n[a], periodic & (1u << a));
+        const double lo = floor(fmin(pp - pe, np - d.ext[a]) - 2.0);
+        const double hi = ceil(fmax(pp + pe, np + d.ext[a]) + 2.0);
+        int l0 = (int)lo;
+        int dim = (int)hi - l0 + 1;
+        if ((periodic & (1u << a)) && dim >= n[a]) {
+            l0 = 0;
+            dim = n[a];
+        }
+        R.lo[a] = l0;
+        R.dim[a] = dim;
+        R.cells *= dim;
+    }
+    return R;
+}
+
+// Rotation matrix (body -> world, row major) of a unit quaternion (w,x,y,z).
+__host__ __device__ inline void quat_to_R(const double q[4], double R[9]) {
+#pragma clang fp contract(off)
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1.0 - 2.0 * (y * y + z * z);
+    R[1] = 2.0 * (x * y - w * z);
+    R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);
+    R[4] = 1.0 - 2.0 * (x * x + z * z);
+    R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);
+    R[7] = 2.0 * (y * z + w * x);
+    R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+// World-frame half extents of the bounding box of a cuboid.
+__host__ __device__ inline void box_extent(const double R[9], const double half[3], double ext[3]) {
+#pragma clang fp contract(off)
+    for (int a = 0; a < 3; ++a)
+        ext[a] = fabs(R[a * 3 + 0]) * half[0] + fabs(R[a * 3 + 1]) * half[1] + fabs(R[a * 3 + 2]) * half[2];
+}
+
+// Rigid-body update of a cuboid of density rho_s (relative to the liquid)
+// over one time step (Sec. 2.3: the fluid force and torque drive the body,
+// which the next step maps anew): semi-implicit Euler,
+//   V' = V + (F + M a) / M                     (translation DOFs in `dof`)
+//   I_w (Omega' - Omega) = T                   (rotation DOFs, restricted to
+//                                               the selected axes)
+//   o' = o + V',  q' = exp(Omega' / 2) q  (renormalised)
+// with M = rho_s l b h and I_w = R diag(M/3 (h_y^2 + h_z^2), ...) R^T.
+// Returns false if the mass is not positive.  FP64, no contraction, so host
+// and device evaluate the same operations.
+__host__ __device__ inline bool integrate_rigid(const double half[3], const double pos[3], const double quat[4],
+                                                const double vel[3], const double omega[3], double density,
+                                                const double F[3], const double T[3], const double accel[3],
+                                                uint32_t dof, double opos[3], double oquat[4], double ovel[3],
+                                                double oomega[3]) {
+#pragma clang fp contract(off)
+    const double M = density * 8.0 * half[0] * half[1] * half[2];
+    if (!(M > 0.0)) return false;
+    for (int a = 0; a < 3; ++a) {
+        ovel[a] = (dof & (1u << a)) ? vel[a] + (F[a] + M * accel[a]) / M : vel[a];
+        oomega[a] = omega[a];
+    }
+    double R[9];
+    quat_to_R(quat, R);
+    const double Ib[3] = {M / 3.0 * (half[1] * half[1] + half[2] * half[2]),
+                          M / 3.0 * (half[0] * half[0] + half[2] * half[2]),
+                          M / 3.0 * (half[0] * half[0] + half[1] * half[1])};
+    double Iw[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double acc = 0.0;
+            for (int k = 0; k < 3; ++k) acc += R[r * 3 + k] * Ib[k] * R[c * 3 + k];
+            Iw[r * 3 + c] = acc;
+        }
+    // Gaussian elimination with partial pivoting on the system restricted to
+    // the selected axes S (in increasing axis order).  Every loop has a
+    // constant trip count and every array a constant index after unrolling
+    // (selects instead of indexing), so the device keeps it in registers.
+    int S[3] = {0, 0, 0}, ns = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (dof & (8u << a)) {
+            if (ns == 0) S[0] = a;
+            else if (ns == 1) S[1] = a;
+            else S[2] = a;
+            ++ns;
+        }
+    if (ns > 0) {
+        double A[3][4];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double v = 0.0;
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j)
+                        if (S[r] == i && S[c] == j) v = Iw[i * 3 + j];
+                A[r][c] = (r < ns && c < ns) ? v : 0.0;
+            }
+            double t = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                if (S[r] == i) t = T[i];
+            A[r][3] = r < ns ? t : 0.0;
+        }
+        // the right-hand side sits in column ns of the reduced system
+        double rhs[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) rhs[r] = A[r][3];
+#pragma unroll
+        for (int pv = 0; pv < 3; ++pv) {
+            if (pv >= ns) break;
+            int best = pv;
+#pragma unroll
+            for (int r = pv + 1; r < 3; ++r)
+                if (r < ns && fabs(A[r][pv]) > fabs(best == 0 ? A[0][pv] : (best == 1 ? A[1][pv] : A[2][pv])))
+                    best = r;
+            if (best != pv) {
+#pragma unroll
+                for (int r = pv + 1; r < 3; ++r)
+                    if (r == best) {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            const double t = A[pv][c];
+                            A[pv][c] = A[r][c];
+                            A[r][c] = t;
+                        }
+                        const double t = rhs[pv];
+                        rhs[pv] = rhs[r];
+                        rhs[r] = t;
+                    }
+            }
+#pragma unroll
+            for (int r = pv + 1; r < 3; ++r) {
+                if (r >= ns) break;
+                const double f = A[r][pv] / A[pv][pv];
+#pragma unroll
+                for (int c = pv; c < 3; ++c)
+                    if (c < ns) A[r][c] -= f * A[pv][c];
+                rhs[r] -= f * rhs[pv];
+            }
+        }
+        double dw[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int r = 2; r >= 0; --r) {
+            if (r >= ns) continue;
+            double acc = rhs[r];
+#pragma unroll
+            for (int c = r + 1; c < 3; ++c)
+                if (c < ns) acc -= A[r][c] * dw[c];
+            dw[r] = acc / A[r][r];
+        }
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+            if (r < ns) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    if (S[r] == i) oomega[i] = omega[i] + dw[r];
+            }
+    }
+    for (int a = 0; a < 3; ++a) opos[a] = pos[a] + ovel[a];
+    const double th = sqrt(oomega[0] * oomega[0] + oomega[1] * oomega[1] + oomega[2] * oomega[2]);
+    for (int a = 0; a < 4; ++a) oquat[a] = quat[a];
+    if (th > 0.0) {
+        const double s = sin(0.5 * th) / th;
+        const double dq[4] = {cos(0.5 * th), s * oomega[0], s * oomega[1], s * oomega[2]};
+        const double* q = quat;
+        const double r[4] = {dq[0] * q[0] - dq[1] * q[1] - dq[2] * q[2] - dq[3] * q[3],
+                             dq[0] * q[1] + dq[1] * q[0] + dq[2] * q[3] - dq[3] * q[2],
+                             dq[0] * q[2] - dq[1] * q[3] + dq[2] * q[0] + dq[3] * q[1],
+                             dq[0] * q[3] + dq[1] * q[2] - dq[2] * q[1] + dq[3] * q[0]};
+        const double nn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3]);
+        for (int a = 0; a < 4; ++a) oquat[a] = r[a] / nn;
+    }
+    return true;
+}
 
 // Grid of the boundary sweep (256-thread workgroups, four wavefronts each);
 // every wavefront of it writes one force record per step.
@@ -300,15 +485,54 @@ __host__ __device__ inline int boundary_blocks(const Inst& I) {
 }
 
 // --------------------------------------------------------------------------
+// 32-lane groups (half a wavefront): lane i of a group owns D3Q19 link i
+// --------------------------------------------------------------------------
+// link tables packed into constants: 2 bits (c + 1) per link, 5 bits per
+// opposite index (links 0..11 in OPP_LO, 12..18 in OPP_HI)
+constexpr unsigned long long pack_c(int a) {
+    unsigned long long v = 0;
+    for (int i = 0; i < Q; ++i) v |= (unsigned long long)((a == 0 ? cx(i) : a == 1 ? cy(i) : cz(i)) + 1) << (2 * i);
+    return v;
+}
+constexpr unsigned long long pack_opp(int lo, int hi) {
+    unsigned long long v = 0;
+    for (int i = lo; i < hi; ++i) v |= (unsigned long long)opp(i) << (5 * (i - lo));
+    return v;
+}
+constexpr unsigned long long CXP = pack_c(0), CYP = pack_c(1), CZP = pack_c(2);
+constexpr unsigned long long OPP_LO = pack_opp(0, 12), OPP_HI = pack_opp(12, Q);
+
+__device__ __forceinline__ int lane_c(unsigned long long P, int i) { return (int)((P >> (2 * i)) & 3ull) - 1; }
+__device__ __forceinline__ int lane_opp(int i) {
+    return i < 12 ? (int)((OPP_LO >> (5 * i)) & 31ull) : (int)((OPP_HI >> (5 * (i - 12))) & 31ull);
+}
+__device__ __forceinline__ float lane_w(int i) { return i == 0 ? 1.f / 3.f : (i < 7 ? 1.f / 18.f : 1.f / 36.f); }
+
+// sum over the 32-lane group of the calling lane (butterfly: every lane
+// ends with the same operations in a different order)
+__device__ __forceinline__ float gsum(float v) {
+#pragma unroll
+    for (int o = 16; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+
+__device__ __forceinline__ int g_lane() { return threadIdx.x & 31; }
+__device__ __forceinline__ int g_base() { return threadIdx.x & 32; }  // first lane of the group in its wavefront
+__device__ __forceinline__ unsigned g_ballot(bool p) { return (unsigned)(__ballot(p) >> g_base()); }
+__device__ __forceinline__ int g_bcast(int v, int src) { return __shfl(v, g_base() + src); }
+__device__ __forceinline__ float g_bcastf(float v, int src) { return __shfl(v, g_base() + src); }
+
+// --------------------------------------------------------------------------
 // kernel launchers (implemented in the .hip files)
 // --------------------------------------------------------------------------
 void launch_init(const Inst& I, const lbm_config& c, hipStream_t s);
 void launch_sweep_bulk(const Inst& I, int parity, hipStream_t s);
 void launch_sweep_boundary(const Inst& I, int parity, hipStream_t s);
 void launch_mark(const Inst& I, int parity, hipStream_t s);
-void launch_convert(const Inst& I, int parity, bool retire_moves, unsigned long long seq, hipStream_t s);
+void launch_convert(const Inst& I, int parity, bool retire_moves, bool integrate, hipStream_t s);
 void launch_finish(const Inst& I, int parity, bool reduce, bool zero_other, bool retire_moves, hipStream_t s);
-void launch_remap(const Inst& I, int parity, const RemapRegions& R, hipStream_t s);
+void launch_remap(const Inst& I, int parity, int blocks_per_body, hipStream_t s);
 void launch_set_body(const Inst& I, int slot, const DevBody& b, hipStream_t s);
 void launch_mass_total(const Inst& I, int parity, hipStream_t s);
 void launch_contacts(const Inst& I, hipStream_t s);

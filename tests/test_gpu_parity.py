@@ -370,6 +370,25 @@ def test_multi_instance_independent(lbm):
     compare_pop(L, o, 1e-5, inst=0, label="multi inst0")
 
 
+def test_free_body_update_rejected_on_device(lbm):
+    """A dense free box falling through gas (no liquid) toward the floor of a
+    24^3 box, g 1e-4: about 77 steps in, the device update would put its
+    bounding box within one cell of the wall.  That update is rejected on the
+    device, the body keeps its last valid pose, and the next synchronising
+    call reports the error."""
+    cfg = W.basin((24, 24, 24), 0.0, 0.6, 1e-4)
+    L = lbm.Lattice(dict(cfg, max_bodies=1))
+    L.set_body(0, dict(W.box((4, 4, 2), (12, 12, 2.3)), fixed=0, dof=0x07, density=2.0))
+    say("free body falling onto the floor, 200 steps")
+    L.step(200)
+    with pytest.raises(lbm.LBMError, match="left the domain interior"):
+        L.sync()
+    b = L.get_body(0)
+    assert b["pos"][2] - 1.0 >= 1.0  # bottom face still a cell above the wall
+    assert b["pos"][2] < 2.3
+    assert b["vel"][2] < 0
+
+
 def test_invalid_body_rejected(lbm):
     cfg = W.basin((32, 32, 32), 16, 0.6, 1e-5)
     L = lbm.Lattice(dict(cfg, max_bodies=2))
