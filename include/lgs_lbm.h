@@ -101,7 +101,10 @@ typedef struct lbm_config {
     double noise_amp;          /* noise amplitude A: rho += A (2U - 1)                 */
     double fp16_scale;         /* power of two (FP16 storage); 0 = default 4096        */
     int32_t max_bodies;        /* bodies per instance, 0 .. LBM_MAX_BODIES             */
-    int32_t reserved;
+    int32_t host_body_update;  /* free bodies: 0 = rigid-body update on the device at
+                                  the end of every step (no host round trip);
+                                  1 = on the host: every step synchronises,
+                                  reads the forces and runs lbm_integrate_body */
 } lbm_config;
 
 /* A cuboid rigid body (Sec. 2.3).  A cell is an obstacle cell of the body iff
@@ -117,11 +120,12 @@ typedef struct lbm_body {
     double omega[3];    /* world frame, radians per step                          */
     double density;     /* rho_s relative to the liquid's 1                       */
     uint32_t fixed;     /* 1: the caller holds the pose (moves it only through
-                           lbm_set_body); 0: free -- at the end of every full
-                           step the device applies the update of
-                           lbm_integrate_body (same FP64 operations), fed with
-                           the mean of this and the previous step's fluid force
-                           and torque, on the DOFs of dof_mask                   */
+                           lbm_set_body); 0: free -- after every full step the
+                           update of lbm_integrate_body, fed with the mean of
+                           this and the previous step's fluid force and torque,
+                           advances it on the DOFs of dof_mask (on the device,
+                           same FP64 operations, or on the host: see
+                           lbm_config.host_body_update)                          */
     uint32_t dof_mask;  /* free bodies: bits 0-2 translation x,y,z, 3-5 rotation */
 } lbm_body;
 
@@ -156,10 +160,11 @@ int32_t lbm_get_body(lbm_ctx* ctx, int32_t inst, int32_t body, lbm_body* b);
 
 /* Advance all instances by nsteps full steps (remap of moved bodies, sweep,
  * conversions and force reduction, then the device update of free bodies,
- * whose new pose the next step maps).  Asynchronous on the context's stream.
- * A free-body update that breaks the lbm_set_body checks is rejected on the
- * device (the body keeps its pose) and the next lbm_sync returns
- * LBM_ERR_UNSTABLE naming the reason. */
+ * whose new pose the next step maps).  Asynchronous on the context's stream
+ * unless an instance updates its free bodies on the host.  A free-body update
+ * that breaks the lbm_set_body checks is rejected (the body keeps its pose):
+ * on the device the next lbm_sync returns LBM_ERR_UNSTABLE naming the reason,
+ * on the host lbm_step returns it. */
 int32_t lbm_step(lbm_ctx* ctx, int32_t nsteps);
 
 /* One step restricted to the phases in phase_mask (LBM_PHASE_*), for tests.

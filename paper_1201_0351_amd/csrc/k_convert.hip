@@ -1,7 +1,7 @@
 // k_convert.hip -- free-surface cell conversions (Sec. 2.2) on the state at
 // t+1, driven by the candidate list the sweep built, plus the end of a step.
 //
-// One workgroup of 512 threads runs the phases one after the other,
+// One workgroup of 1024 threads runs the phases one after the other,
 // separated by workgroup barriers (candidate lists are short: a few to a few
 // thousand cells per step).  Per-cell work is spread over a 32-lane group
 // (lane i looks at neighbour x + c_i, or population i), so a cell costs a
@@ -37,7 +37,7 @@ namespace lgs {
 
 namespace {
 
-constexpr int CONV_THREADS = 512;
+constexpr int CONV_THREADS = 1024;
 
 __device__ __forceinline__ bool claim(uint32_t* bits, int id) {
     const uint32_t m = 1u << (id & 31);
@@ -317,12 +317,9 @@ __device__ __forceinline__ void phase_commit(const Inst& I, int parity) {
         int x, y, z;
         cell_coords(I, id, x, y, z);
         const int nb = lane_nbr(I, x, y, z);
-        float sh = 0.f;
-        bool has = false;
-        if (nb >= 0 && (I.flags[nb] & (MARK_FILL | MARK_EMPTY))) {
-            has = true;
-            sh = I.share[nb];
-        }
+        // share loaded without waiting for the flags (one round trip)
+        const float sh = nb >= 0 ? I.share[nb] : 0.f;
+        const bool has = nb >= 0 && (I.flags[nb] & (MARK_FILL | MARK_EMPTY));
         const unsigned m = g_ballot(has);
         const float dr = g_drho<S>(I, pop, id);
         float hi = I.m_hi[id], lo = I.m_lo[id];

@@ -213,11 +213,23 @@ __global__ __launch_bounds__(256) void k_sweep_bulk(Inst I, int parity, int tile
 
 // ---------------------------------------------------------------------------
 // boundary sweep: interface cells, liquid cells next to gas or a body.
-// One group of 32 lanes per cell: lane i (< 19) owns link i; moments, the
-// mass exchange and the momentum exchange are butterfly reductions over the
-// group, values of the opposite link come from lane ibar by a shuffle.
+// One group of 8 lanes per listed cell; lane l owns links l, l+8, l+16.
+// The links' loaded values go through LDS so that every lane can read the
+// opposite link's, and sums over the links are 3-step butterflies.  A few
+// thousand wavefronts, all resident at once: the chain of dependent loads is
+// paid once and each lane's arithmetic is a sixth of the cell's.
 // ---------------------------------------------------------------------------
+namespace {
+constexpr int BL = 8;             // lanes per cell
+constexpr int BCELLS = 256 / BL;  // cells per workgroup pass
 
+__device__ __forceinline__ float osum(float v) {
+    v += __shfl_xor(v, 4);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 1);
+    return v;
+}
+}  // namespace
 
 template <typename S>
 __global__ __launch_bounds__(256) void k_sweep_boundary(Inst I, int parity) {
@@ -228,205 +240,306 @@ __global__ __launch_bounds__(256) void k_sweep_boundary(Inst I, int parity) {
     StepCounters& C = I.ctl->cnt[parity];
     const int nlist = min(C.n_bnd, I.list_cap);
     const bool px = I.periodic & 1, py = I.periodic & 2, pz = I.periodic & 4;
-
-    const int i = threadIdx.x & 31;          // link of this lane
-    const int gbase = threadIdx.x & 32;      // first lane of this group in the wavefront
-    const bool link = i < Q;
-    const int cxi = link ? lane_c(CXP, i) : 0, cyi = link ? lane_c(CYP, i) : 0, czi = link ? lane_c(CZP, i) : 0;
-    const int oi = link ? lane_opp(i) : i;
-    const float wi = lane_w(i);
-    const int nwaves = (gridDim.x * blockDim.x) >> 6;
-    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    // this wavefront's momentum-exchange partial sum (first body it meets)
+    const float* __restrict__ phi_t = I.phi[parity];
+    const int l = threadIdx.x & (BL - 1);
+    const int cell = threadIdx.x / BL;
+    // this lane's momentum-exchange partial sum (first body it meets)
     int rec_body = -1;
     double rv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    // the bodies' centre, velocity and angular velocity, read once per
+    // workgroup
+    __shared__ double bpos[MAXB][3];
+    __shared__ float bvel[MAXB][3], bom[MAXB][3];
+    // per cell of the pass and link: source flag (-1: wall), pulled raw
+    // deviation f_i(x - c_i), own deviation f_i(x), fill level of the source
+    __shared__ int lsf[BCELLS][Q];
+    __shared__ float ldr[BCELLS][Q], ldx[BCELLS][Q], lsph[BCELLS][Q];
+    if ((int)threadIdx.x < I.nbodies * 3) {
+        const int b = threadIdx.x / 3, a = threadIdx.x % 3;
+        const DevBody& B = I.bodies[b];
+        bpos[b][a] = B.pos[a];
+        bvel[b][a] = (float)B.vel[a];
+        bom[b][a] = (float)B.omega[a];
+    }
 
-    for (int k0 = 2 * wave; k0 < nlist; k0 += 2 * nwaves) {
-        const int k = k0 + (gbase >> 5);
+    for (int base = blockIdx.x * BCELLS; base < nlist; base += gridDim.x * BCELLS) {
+        const int k = base + cell;
         const bool active = k < nlist;
-        const int id = active ? I.bnd[k] : I.bnd[k0];
+        const int id = active ? I.bnd[k] : I.bnd[base];
         int x, y, z;
         cell_coords(I, id, x, y, z);
         const uint8_t fl = I.flags[id];
         const int type = fl & TYPE_MASK;
-
-        // source of this lane's link and everything read from it
-        const int X = step_axis(x, -cxi, I.nx, px), Y = step_axis(y, -cyi, I.ny, py), Z = step_axis(z, -czi, I.nz, pz);
-        const bool ok = link && (X | Y | Z) >= 0;
-        const int s = ok ? X + I.nx * (Y + I.ny * Z) : id;
-        const uint8_t sf = ok ? I.flags[s] : (uint8_t)OBS;  // wall: obstacle at rest
-        const int st = sf & TYPE_MASK;
-        const float sph = I.phi[parity][s];
-        const float draw = link ? Store<S>::ld(src, (size_t)i * N + s, isc) : 0.f;
-        const float dxi = link ? Store<S>::ld(src, (size_t)i * N + id, isc) : 0.f;
-        const float phix = type == IFC ? I.phi[parity][id] : 1.f;
+        const float phix = type == IFC ? phi_t[id] : 1.f;
         float mhi = 0.f, mlo = 0.f;
-        if (type == IFC) {
+        if (type == IFC && l == 0) {
             mhi = I.m_hi[id];
             mlo = I.m_lo[id];
         }
-        // the opposite link's lane: own f_ibar(x); raw f_ibar(x + c_i) and
-        // its type / fill (x + c_i is the source of link ibar)
-        const float dxo = __shfl(dxi, gbase + oi);
-        const float drawo = __shfl(draw, gbase + oi);
-        const int sto = __shfl(ok ? st : -1, gbase + oi);
-        const float spho = __shfl(sph, gbase + oi);
+        // this lane's links: sources s_i = x - c_i (a wall reads as an
+        // obstacle at rest) and everything read from them
+        float dx[3], dr[3];
+        int sfe[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int i = l + BL * j;
+            dx[j] = 0.f;
+            dr[j] = 0.f;
+            sfe[j] = -1;
+            if (i < Q) {
+                const int ci = lane_c(CXP, i), cyi = lane_c(CYP, i), czi = lane_c(CZP, i);
+                const int X = step_axis(x, -ci, I.nx, px), Y = step_axis(y, -cyi, I.ny, py);
+                const int Z = step_axis(z, -czi, I.nz, pz);
+                const bool ok = (X | Y | Z) >= 0;
+                const int s = ok ? X + I.nx * (Y + I.ny * Z) : id;
+                sfe[j] = ok ? (int)I.flags[s] : -1;
+                dr[j] = Store<S>::ld(src, (size_t)i * N + s, isc);
+                dx[j] = Store<S>::ld(src, (size_t)i * N + id, isc);
+                const float sp = phi_t[s];
+                lsf[cell][i] = sfe[j];
+                ldr[cell][i] = dr[j];
+                ldx[cell][i] = dx[j];
+                lsph[cell][i] = sp;
+            }
+        }
+        __syncthreads();
 
         // moments of f(x, t)
-        const float drx = gsum(dxi);
-        const float jx0 = gsum(cxi * dxi), jx1 = gsum(cyi * dxi), jx2 = gsum(czi * dxi);
+        float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int i = l + BL * j;
+            if (i < Q) {
+                p0 += dx[j];
+                p1 += lane_c(CXP, i) * dx[j];
+                p2 += lane_c(CYP, i) * dx[j];
+                p3 += lane_c(CZP, i) * dx[j];
+            }
+        }
+        const float drx = osum(p0), jx0 = osum(p1), jx1 = osum(p2), jx2 = osum(p3);
         const float rhox = 1.f + drx;
         const float ux0 = jx0 / rhox, ux1 = jx1 / rhox, ux2 = jx2 / rhox;
         const float uu = ux0 * ux0 + ux1 * ux1 + ux2 * ux2;
 
-        // interface normal n = -grad(phi): fill of the sources of links 1..6
-        // (FP64 sign test, same operations on every lane)
+        // interface normal n = -grad(phi) from the fill of the sources of
+        // links 1..6 (wall / obstacle: own fill); FP64 sign test, the same
+        // operations on every lane
         double n0 = 0.0, n1 = 0.0, n2 = 0.0, nthr = 0.0;
         if (type == IFC && I.recon_mode != LBM_RECON_GAS_ONLY) {
-            double fv = (double)phix;  // wall / obstacle: own fill
-            if (ok && st == LIQ) fv = 1.0;
-            else if (ok && st == GAS) fv = 0.0;
-            else if (ok && st == IFC) fv = (double)sph;
-            const double f1 = __shfl(fv, gbase + 1), f2 = __shfl(fv, gbase + 2), f3 = __shfl(fv, gbase + 3);
-            const double f4 = __shfl(fv, gbase + 4), f5 = __shfl(fv, gbase + 5), f6 = __shfl(fv, gbase + 6);
+            double f[7];
+#pragma unroll
+            for (int i = 1; i <= 6; ++i) {
+                const int e = lsf[cell][i];
+                const int st = e & TYPE_MASK;
+                double v = (double)phix;
+                if (e >= 0 && st == LIQ) v = 1.0;
+                else if (e >= 0 && st == GAS) v = 0.0;
+                else if (e >= 0 && st == IFC) v = (double)lsph[cell][i];
+                f[i] = v;
+            }
             // the source of link E (c = +x) is x-1, of W (c = -x) is x+1
-            n0 = 0.5 * (f2 - f1);
-            n1 = 0.5 * (f3 - f4);
-            n2 = 0.5 * (f5 - f6);
+            n0 = 0.5 * (f[2] - f[1]);
+            n1 = 0.5 * (f[3] - f[4]);
+            n2 = 0.5 * (f[5] - f[6]);
             nthr = NORMAL_TOL * ((fabs(n0) + fabs(n1)) + fabs(n2));
         }
 
-        // mass exchange with neighbour x + c_i (interface cells)
-        float dmi = 0.f;
-        if (type == IFC && link && i > 0) {
-            const float ex = drawo - dxi;
-            if (sto == LIQ) dmi = ex;
-            else if (sto == IFC) dmi = 0.5f * (phix + spho) * ex;
-        }
-        const float dm = gsum(dmi);
-
-        // this lane's incoming population
-        float dpi = draw;
+        // per link: mass exchange with x + c_i = s_ibar, incoming population,
+        // momentum exchange with a body
+        float pdm = 0.f;
+        float d[3];
         float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f, a5 = 0.f;
-        int bk = -1;
-        if (i == 0) {
-            dpi = dxi;
-        } else if (link && (!ok || st == OBS)) {
-            float cu = 0.f;
-            float r0 = 0.f, r1 = 0.f, r2 = 0.f;
-            const float xc0 = x + 0.5f, xc1 = y + 0.5f, xc2 = z + 0.5f;
-            if (ok) {
-                bk = (sf >> 2) & 15;
-                const DevBody& B = I.bodies[bk];
-                // body velocity at the link midpoint x_c - c_i/2
-                const float p0 = (float)wrap_rel(xc0 - 0.5f * cxi - B.pos[0], I.nx, px);
-                const float p1 = (float)wrap_rel(xc1 - 0.5f * cyi - B.pos[1], I.ny, py);
-                const float p2 = (float)wrap_rel(xc2 - 0.5f * czi - B.pos[2], I.nz, pz);
-                const float w0 = (float)B.omega[0], w1 = (float)B.omega[1], w2 = (float)B.omega[2];
-                const float u0 = (float)B.vel[0] + (w1 * p2 - w2 * p1);
-                const float u1 = (float)B.vel[1] + (w2 * p0 - w0 * p2);
-                const float u2 = (float)B.vel[2] + (w0 * p1 - w1 * p0);
-                cu = cxi * u0 + cyi * u1 + czi * u2;
-                r0 = (float)wrap_rel(xc0 - B.pos[0], I.nx, px);
-                r1 = (float)wrap_rel(xc1 - B.pos[1], I.ny, py);
-                r2 = (float)wrap_rel(xc2 - B.pos[2], I.nz, pz);
+        int abody = -1;
+        const float xc0 = x + 0.5f, xc1 = y + 0.5f, xc2 = z + 0.5f;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int i = l + BL * j;
+            d[j] = 0.f;
+            if (i >= Q) continue;
+            if (i == 0) {
+                d[j] = dx[j];
+                continue;
             }
-            const float mw = 6.f * wi * rhox * cu;
-            dpi = dxo + mw;
-            if (bk >= 0) {
-                // momentum the fluid gains on this link (deviation form); the
-                // body receives the opposite
-                const float phat = type == LIQ ? 1.f : phix;
-                const float amp = 2.f * phat * (dxo + wi * (1.f - I.rho_g) + 0.5f * mw);
-                const float j0 = amp * cxi, j1 = amp * cyi, j2 = amp * czi;
-                a0 = -j0;
-                a1 = -j1;
-                a2 = -j2;
-                a3 = -(r1 * j2 - r2 * j1);
-                a4 = -(r2 * j0 - r0 * j2);
-                a5 = -(r0 * j1 - r1 * j0);
+            const int o = lane_opp(i);
+            const float cxf = (float)lane_c(CXP, i), cyf = (float)lane_c(CYP, i), czf = (float)lane_c(CZP, i);
+            const float wi = lane_w(i);
+            const float dxo = ldx[cell][o];
+            if (type == IFC) {
+                const int eo = lsf[cell][o];
+                if (eo >= 0) {
+                    const int sto = eo & TYPE_MASK;
+                    const float ex = ldr[cell][o] - dx[j];  // f_ibar(x + c_i) - f_i(x)
+                    if (sto == LIQ) pdm += ex;
+                    else if (sto == IFC) pdm += 0.5f * (phix + lsph[cell][o]) * ex;
+                }
             }
-        } else if (link) {
-            bool recon = (st == GAS);
-            if (!recon && type == IFC && I.recon_mode != LBM_RECON_GAS_ONLY) {
-                const double cn = cxi * n0 + cyi * n1 + czi * n2;
-                recon = I.recon_mode == LBM_RECON_GAS_SIDE ? (cn < -nthr) : (cn <= nthr);
-            }
-            if (recon) {
-                const float cu = cxi * ux0 + cyi * ux1 + czi * ux2;
-                // (f_eq,i + f_eq,ibar)(rho_G, u_x) - 2 w_i, minus d_ibar(x)
-                dpi = 2.f * wi * (I.rho_g * (1.f + 4.5f * cu * cu - 1.5f * uu) - 1.f) - dxo;
+            const int e = sfe[j];
+            const int st = e & TYPE_MASK;
+            if (e < 0 || st == OBS) {
+                float cu = 0.f;
+                int bk = -1;
+                float r0 = 0.f, r1 = 0.f, r2 = 0.f;
+                if (e >= 0) {
+                    bk = (e >> 2) & 15;
+                    // body velocity at the link midpoint x_c - c_i/2
+                    const float q0 = (float)wrap_rel(xc0 - 0.5f * cxf - bpos[bk][0], I.nx, px);
+                    const float q1 = (float)wrap_rel(xc1 - 0.5f * cyf - bpos[bk][1], I.ny, py);
+                    const float q2 = (float)wrap_rel(xc2 - 0.5f * czf - bpos[bk][2], I.nz, pz);
+                    const float w0 = bom[bk][0], w1 = bom[bk][1], w2 = bom[bk][2];
+                    const float u0 = bvel[bk][0] + (w1 * q2 - w2 * q1);
+                    const float u1 = bvel[bk][1] + (w2 * q0 - w0 * q2);
+                    const float u2 = bvel[bk][2] + (w0 * q1 - w1 * q0);
+                    cu = cxf * u0 + cyf * u1 + czf * u2;
+                    r0 = (float)wrap_rel(xc0 - bpos[bk][0], I.nx, px);
+                    r1 = (float)wrap_rel(xc1 - bpos[bk][1], I.ny, py);
+                    r2 = (float)wrap_rel(xc2 - bpos[bk][2], I.nz, pz);
+                }
+                const float mw = 6.f * wi * rhox * cu;
+                d[j] = dxo + mw;
+                if (bk >= 0 && active) {
+                    // momentum the fluid gains on this link (deviation form);
+                    // the body receives the opposite
+                    const float phat = type == LIQ ? 1.f : phix;
+                    const float amp = 2.f * phat * (dxo + wi * (1.f - I.rho_g) + 0.5f * mw);
+                    const float j0 = amp * cxf, j1 = amp * cyf, j2 = amp * czf;
+                    const float t3 = r1 * j2 - r2 * j1, t4 = r2 * j0 - r0 * j2, t5 = r0 * j1 - r1 * j0;
+                    if (abody < 0) abody = bk;
+                    if (bk == abody) {
+                        a0 -= j0;
+                        a1 -= j1;
+                        a2 -= j2;
+                        a3 -= t3;
+                        a4 -= t4;
+                        a5 -= t5;
+                    } else {
+                        // a second body on this lane's links
+                        double* acc = &C.acc[bk][0];
+                        atomicAdd(acc + 0, (double)-j0);
+                        atomicAdd(acc + 1, (double)-j1);
+                        atomicAdd(acc + 2, (double)-j2);
+                        atomicAdd(acc + 3, (double)-t3);
+                        atomicAdd(acc + 4, (double)-t4);
+                        atomicAdd(acc + 5, (double)-t5);
+                    }
+                }
+            } else {
+                bool recon = st == GAS;
+                if (!recon && type == IFC && I.recon_mode != LBM_RECON_GAS_ONLY) {
+                    const double cn = cxf * n0 + cyf * n1 + czf * n2;
+                    recon = I.recon_mode == LBM_RECON_GAS_SIDE ? (cn < -nthr) : (cn <= nthr);
+                }
+                if (recon) {
+                    const float cu = cxf * ux0 + cyf * ux1 + czf * ux2;
+                    // (f_eq,i + f_eq,ibar)(rho_G, u_x) - 2 w_i, minus d_ibar(x)
+                    d[j] = 2.f * wi * (I.rho_g * (1.f + 4.5f * cu * cu - 1.5f * uu) - 1.f) - dxo;
+                } else {
+                    d[j] = dr[j];
+                }
             }
         }
-        if (!active || !link) dpi = 0.f;
+        const float dm = osum(pdm);
 
-        // moments after streaming, collide
-        const float drho = gsum(dpi);
-        const float j0 = gsum(cxi * dpi), j1 = gsum(cyi * dpi), j2 = gsum(czi * dpi);
+        // moments after streaming, fill level and marks, collision
+        float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int i = l + BL * j;
+            if (i < Q) {
+                q0 += d[j];
+                q1 += lane_c(CXP, i) * d[j];
+                q2 += lane_c(CYP, i) * d[j];
+                q3 += lane_c(CZP, i) * d[j];
+            }
+        }
+        const float drho = osum(q0), j0 = osum(q1), j1 = osum(q2), j2 = osum(q3);
         const float rho = 1.f + drho;
-        uint8_t mark = 0;
-        if (type == IFC) {
+        if (active && type == IFC && l == 0) {
             two_sum_add(mhi, mlo, dm);
             const float ph = (float)(((double)mhi + (double)mlo) / (1.0 + (double)drho));
             const double phd = (double)ph;
+            uint8_t mark = 0;
             if (phd >= 1.0 + I.eps) mark = MARK_FILL;
             else if (phd <= -I.eps) mark = MARK_EMPTY;
-            if (active && i == 0) {
-                I.m_hi[id] = mhi;
-                I.m_lo[id] = mlo;
-                I.phi[parity ^ 1][id] = ph;
-                if (mark) I.flags[id] = (fl & KEEP_MASK) | mark;
+            I.m_hi[id] = mhi;
+            I.m_lo[id] = mlo;
+            I.phi[parity ^ 1][id] = ph;
+            if (mark) {
+                I.flags[id] = (fl & KEEP_MASK) | mark;
+                const int p = atomicAdd(&C.n_cand, 1);
+                if (p < I.list_cap) I.cand[p] = id;
+                else atomicOr(&C.overflow, 1);
             }
         }
-        if (active && link) {
+        if (active) {
             const float irho = 1.f / rho;
             const float u0 = j0 * irho, u1 = j1 * irho, u2 = j2 * irho;
-            const float cu = cxi * u0 + cyi * u1 + czi * u2;
-            const float ca = cxi * I.ax + cyi * I.ay + czi * I.az;
+            const float uq = 1.5f * (u0 * u0 + u1 * u1 + u2 * u2);
             const float ua = u0 * I.ax + u1 * I.ay + u2 * I.az;
-            const float deq = wi * (drho + rho * (3.f * cu + 4.5f * cu * cu - 1.5f * (u0 * u0 + u1 * u1 + u2 * u2)));
-            const float F = wi * rho * (3.f * (ca - ua) + 9.f * cu * ca);
-            Store<S>::store(dst, (size_t)i * N + id, dpi + I.omega * (deq - dpi) + F, I.scale);
-            if (i == 0 && !(rho > 0.f && rho < 1e6f)) atomicOr(&I.ctl->nonfinite, 1);
-        }
-
-        // candidates for the conversion phase (one lane per group)
-        wave_append(active && i == 0 && mark != 0, id, I.cand, &C.n_cand, I.list_cap, &C.overflow);
-
-        // momentum exchange: wavefront reduction in FP64 into this wavefront's
-        // record (first body it meets), FP64 atomics for any other body
-        const bool has = active && bk >= 0;
-        unsigned long long m = __ballot(has);
-        while (m) {
-            const int leader = __ffsll((long long)m) - 1;
-            const int b = __shfl(bk, leader);
-            const bool mine = has && bk == b;
-            double v[6];
-            v[0] = wave_sum(mine ? (double)a0 : 0.0);
-            v[1] = wave_sum(mine ? (double)a1 : 0.0);
-            v[2] = wave_sum(mine ? (double)a2 : 0.0);
-            v[3] = wave_sum(mine ? (double)a3 : 0.0);
-            v[4] = wave_sum(mine ? (double)a4 : 0.0);
-            v[5] = wave_sum(mine ? (double)a5 : 0.0);
-            if (rec_body < 0) rec_body = b;
-            if (b == rec_body) {
+            if (l == 0 && !(rho > 0.f && rho < 1e6f)) atomicOr(&I.ctl->nonfinite, 1);
 #pragma unroll
-                for (int q = 0; q < 6; ++q) rv[q] += v[q];
-            } else if (lane_id() == leader) {
-#pragma unroll
-                for (int q = 0; q < 6; ++q) atomicAdd(&C.acc[b][q], v[q]);
+            for (int j = 0; j < 3; ++j) {
+                const int i = l + BL * j;
+                if (i >= Q) continue;
+                const float cxf = (float)lane_c(CXP, i), cyf = (float)lane_c(CYP, i), czf = (float)lane_c(CZP, i);
+                const float wi = lane_w(i);
+                const float cu = cxf * u0 + cyf * u1 + czf * u2;
+                const float ca = cxf * I.ax + cyf * I.ay + czf * I.az;
+                const float deq = wi * (drho + rho * (3.f * cu + 4.5f * cu * cu - uq));
+                const float F = wi * rho * (3.f * (ca - ua) + 9.f * cu * ca);
+                Store<S>::store(dst, (size_t)i * N + id, d[j] + I.omega * (deq - d[j]) + F, I.scale);
             }
-            m &= ~__ballot(mine);
+            if (abody >= 0) {
+                if (rec_body < 0) rec_body = abody;
+                if (abody == rec_body) {
+                    rv[0] += (double)a0;
+                    rv[1] += (double)a1;
+                    rv[2] += (double)a2;
+                    rv[3] += (double)a3;
+                    rv[4] += (double)a4;
+                    rv[5] += (double)a5;
+                } else {
+                    double* acc = &C.acc[abody][0];
+                    atomicAdd(acc + 0, (double)a0);
+                    atomicAdd(acc + 1, (double)a1);
+                    atomicAdd(acc + 2, (double)a2);
+                    atomicAdd(acc + 3, (double)a3);
+                    atomicAdd(acc + 4, (double)a4);
+                    atomicAdd(acc + 5, (double)a5);
+                }
+            }
         }
+        __syncthreads();  // the next pass overwrites the LDS arrays
     }
-    // the workgroup's record: its wavefronts' records in wavefront order
+
+    // wavefront sums per body (in order of first appearance), then the
+    // workgroup's record from its wavefronts' records in wavefront order
+    int wbody = -1;
+    double wv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    unsigned long long m = __ballot(rec_body >= 0);
+    while (m) {
+        const int leader = __ffsll((long long)m) - 1;
+        const int b = __shfl(rec_body, leader);
+        const bool mine = rec_body == b;
+        double v[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) v[q] = wave_sum(mine ? rv[q] : 0.0);
+        if (wbody < 0) wbody = b;
+        if (b == wbody) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) wv[q] += v[q];
+        } else if (lane_id() == leader) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) atomicAdd(&C.acc[b][q], v[q]);
+        }
+        m &= ~__ballot(mine);
+    }
     __shared__ int sb[4];
     __shared__ double sv[4][6];
-    const int wv = threadIdx.x >> 6;
+    const int wv_id = threadIdx.x >> 6;
     if (lane_id() == 0) {
-        sb[wv] = rec_body;
+        sb[wv_id] = wbody;
 #pragma unroll
-        for (int q = 0; q < 6; ++q) sv[wv][q] = rv[q];
+        for (int q = 0; q < 6; ++q) sv[wv_id][q] = wv[q];
     }
     __syncthreads();
     if (threadIdx.x == 0) {

@@ -120,6 +120,7 @@ int validate(const lbm_config& c, int k) {
     if (!(c.eps >= 0.0)) return bad("eps must be >= 0");
     if (c.recon_mode < 0 || c.recon_mode > 2) return bad("unknown recon_mode");
     if (c.max_bodies < 0 || c.max_bodies > MAXB) return bad("max_bodies out of range");
+    if (c.host_body_update != 0 && c.host_body_update != 1) return bad("host_body_update must be 0 or 1");
     const double n[3] = {(double)c.nx, (double)c.ny, (double)c.nz};
     for (int a = 0; a < 3; ++a)
         if (!(n[a] * std::fabs(c.accel[a]) < 0.1 / 3.0))
@@ -285,6 +286,44 @@ static void refresh_instance_flags(InstHost& h) {
     }
 }
 
+// The lbm_set_body checks of a new pose d of body k (h.bodies holds the
+// device's current records).
+static int check_pose(const InstHost& h, int k, const DevBody& d, bool was_mapped, const char* who) {
+    const double n[3] = {(double)h.cfg.nx, (double)h.cfg.ny, (double)h.cfg.nz};
+    const double Rc = std::sqrt(d.half[0] * d.half[0] + d.half[1] * d.half[1] + d.half[2] * d.half[2]);
+    // inside the non-periodic extent with a free cell of margin
+    for (int a = 0; a < 3; ++a) {
+        if (h.cfg.periodic & (1 << a)) {
+            if (2.0 * d.ext[a] >= n[a] && !(d.half[a] >= 0.5 * n[a] && d.ext[a] == d.half[a]))
+                return fail(LBM_ERR_INVALID, std::string(who) + ": body wider than a periodic axis");
+            continue;
+        }
+        if (d.pos[a] - d.ext[a] < 1.0 || d.pos[a] + d.ext[a] > n[a] - 1.0)
+            return fail(LBM_ERR_INVALID, std::string(who) + ": body must stay one cell inside the walls");
+    }
+    const double speed = std::sqrt(d.vel[0] * d.vel[0] + d.vel[1] * d.vel[1] + d.vel[2] * d.vel[2]) +
+                         std::sqrt(d.omega[0] * d.omega[0] + d.omega[1] * d.omega[1] + d.omega[2] * d.omega[2]) * Rc;
+    if (!(speed < 1.0))
+        return fail(LBM_ERR_INVALID, std::string(who) + ": surface speed must be below one cell per step");
+    if (was_mapped) {
+        for (int a = 0; a < 3; ++a) {
+            const double dd = wrap_rel(d.pos[a] - h.bodies[k].prev_pos[a], n[a], h.cfg.periodic & (1 << a));
+            if (!(std::fabs(dd) < 1.0))
+                return fail(LBM_ERR_INVALID, std::string(who) + ": body moved a cell or more since its last mapping");
+        }
+    }
+    for (int j = 0; j < h.dev.nbodies; ++j) {
+        if (j == k || !h.bodies[j].active) continue;
+        bool sep = false;
+        for (int a = 0; a < 3; ++a) {
+            const double dd = wrap_rel(d.pos[a] - h.bodies[j].pos[a], n[a], h.cfg.periodic & (1 << a));
+            if (std::fabs(dd) >= d.ext[a] + h.bodies[j].ext[a] + 3.0) sep = true;
+        }
+        if (!sep) return fail(LBM_ERR_INVALID, std::string(who) + ": bodies must stay three cells apart");
+    }
+    return LBM_OK;
+}
+
 int32_t lbm_set_body(lbm_ctx* c, int32_t inst, int32_t k, const lbm_body* b) {
     int rc = check_inst(c, inst);
     if (rc) return rc;
@@ -313,36 +352,8 @@ int32_t lbm_set_body(lbm_ctx* c, int32_t inst, int32_t k, const lbm_body* b) {
     for (int a = 0; a < 4; ++a) d.quat[a] = b->quat[a];
     quat_to_R(b->quat, d.R);
     box_extent(d.R, d.half, d.ext);
-    const double Rc = std::sqrt(d.half[0] * d.half[0] + d.half[1] * d.half[1] + d.half[2] * d.half[2]);
-    // inside the non-periodic extent with a free cell of margin
-    for (int a = 0; a < 3; ++a) {
-        if (h.cfg.periodic & (1 << a)) {
-            if (2.0 * d.ext[a] >= n[a] && !(d.half[a] >= 0.5 * n[a] && d.ext[a] == d.half[a]))
-                return fail(LBM_ERR_INVALID, "set_body: body wider than a periodic axis");
-            continue;
-        }
-        if (d.pos[a] - d.ext[a] < 1.0 || d.pos[a] + d.ext[a] > n[a] - 1.0)
-            return fail(LBM_ERR_INVALID, "set_body: body must stay one cell inside the walls");
-    }
-    const double speed = std::sqrt(d.vel[0] * d.vel[0] + d.vel[1] * d.vel[1] + d.vel[2] * d.vel[2]) +
-                         std::sqrt(d.omega[0] * d.omega[0] + d.omega[1] * d.omega[1] + d.omega[2] * d.omega[2]) * Rc;
-    if (!(speed < 1.0)) return fail(LBM_ERR_INVALID, "set_body: surface speed must be below one cell per step");
-    if (was_mapped) {
-        for (int a = 0; a < 3; ++a) {
-            const double dd = wrap_rel(d.pos[a] - old.prev_pos[a], n[a], h.cfg.periodic & (1 << a));
-            if (!(std::fabs(dd) < 1.0))
-                return fail(LBM_ERR_INVALID, "set_body: body moved a cell or more since its last mapping");
-        }
-    }
-    for (int j = 0; j < h.dev.nbodies; ++j) {
-        if (j == k || !h.bodies[j].active) continue;
-        bool sep = false;
-        for (int a = 0; a < 3; ++a) {
-            const double dd = wrap_rel(d.pos[a] - h.bodies[j].pos[a], n[a], h.cfg.periodic & (1 << a));
-            if (std::fabs(dd) >= d.ext[a] + h.bodies[j].ext[a] + 3.0) sep = true;
-        }
-        if (!sep) return fail(LBM_ERR_INVALID, "set_body: bodies must stay three cells apart");
-    }
+    rc = check_pose(h, k, d, was_mapped, "set_body");
+    if (rc) return rc;
     if (b->fixed == 0 && (b->dof_mask & ~0x3Fu)) return fail(LBM_ERR_INVALID, "set_body: dof_mask has unknown bits");
     if (b->fixed == 0 && !(b->density > 0.0)) return fail(LBM_ERR_INVALID, "set_body: free body needs a density > 0");
     d.density = b->density;
@@ -386,6 +397,58 @@ int32_t lbm_get_body(lbm_ctx* c, int32_t inst, int32_t k, lbm_body* b) {
 
 __global__ void k_copy_state(Inst I, int from);
 
+// Host update of the free bodies of an instance configured for it, after a
+// full step of parity p: wait for the step, read the reduced forces and the
+// body records, apply lbm_integrate_body fed with the mean of this and the
+// previous step's force and torque, check the new pose as lbm_set_body does
+// and upload it; the next step maps it.
+static int couple_on_host(lbm_ctx* c, InstHost& h, int p) {
+    double acc[MAXB][6];
+    HIP_OK(hipStreamSynchronize(c->stream));
+    HIP_OK(hipMemcpy(acc, &h.dev.ctl->cnt[p].acc[0][0], sizeof acc, hipMemcpyDeviceToHost));
+    int rc = pull_bodies(c, h);
+    if (rc) return rc;
+    for (int b = 0; b < h.dev.nbodies; ++b) {
+        DevBody d = h.bodies[b];
+        if (!d.active || !d.free_body || !d.dof) continue;
+        double F[3], T[3];
+        for (int a = 0; a < 3; ++a) {
+            F[a] = d.have_prev ? 0.5 * (acc[b][a] + d.fprev[a]) : acc[b][a];
+            T[a] = d.have_prev ? 0.5 * (acc[b][3 + a] + d.fprev[3 + a]) : acc[b][3 + a];
+        }
+        for (int a = 0; a < 6; ++a) d.fprev[a] = acc[b][a];
+        d.have_prev = 1;
+        lbm_body in = h.desc[b], out;
+        for (int a = 0; a < 3; ++a) {
+            in.pos[a] = d.pos[a];
+            in.vel[a] = d.vel[a];
+            in.omega[a] = d.omega[a];
+        }
+        for (int a = 0; a < 4; ++a) in.quat[a] = d.quat[a];
+        rc = lbm_integrate_body(&in, F, T, h.cfg.accel, d.dof, &out);
+        if (rc) return rc;
+        const double n[3] = {(double)h.cfg.nx, (double)h.cfg.ny, (double)h.cfg.nz};
+        for (int a = 0; a < 3; ++a) {
+            double q = out.pos[a];
+            if (h.cfg.periodic & (1 << a)) q = q - n[a] * std::floor(q / n[a]);
+            d.pos[a] = q;
+            d.vel[a] = out.vel[a];
+            d.omega[a] = out.omega[a];
+        }
+        for (int a = 0; a < 4; ++a) d.quat[a] = out.quat[a];
+        quat_to_R(d.quat, d.R);
+        box_extent(d.R, d.half, d.ext);
+        rc = check_pose(h, b, d, d.mapped != 0, "free-body update (host)");
+        if (rc) return fail(LBM_ERR_UNSTABLE, lbm_last_error());
+        d.moved = 1;
+        h.bodies[b] = d;
+        launch_set_body(h.dev, b, d, c->stream);
+    }
+    HIP_OK(hipGetLastError());
+    h.need_remap = true;
+    return LBM_OK;
+}
+
 static int run_step(lbm_ctx* c, int mask) {
     const int p = c->parity;
     const bool advances = (mask & (LBM_PHASE_SWEEP | LBM_PHASE_CONVERT)) != 0;
@@ -410,7 +473,7 @@ static int run_step(lbm_ctx* c, int mask) {
             hipLaunchKernelGGL(k_copy_state, dim3((h.dev.N + 255) / 256), dim3(256), 0, c->stream, h.dev, p);
             launch_mark(h.dev, p, c->stream);
         }
-        const bool integrate = mask == LBM_PHASE_ALL && h.any_free;
+        const bool integrate = mask == LBM_PHASE_ALL && h.any_free && h.cfg.host_body_update == 0;
         if (mask & LBM_PHASE_CONVERT) launch_convert(h.dev, p, remapped, integrate, c->stream);
         else if (advances || remapped)
             launch_finish(h.dev, p, (mask & LBM_PHASE_SWEEP) != 0, advances, remapped, c->stream);
@@ -423,6 +486,13 @@ static int run_step(lbm_ctx* c, int mask) {
         c->have_forces = (mask & LBM_PHASE_SWEEP) != 0;
         c->parity ^= 1;
     }
+    if (mask == LBM_PHASE_ALL)
+        for (int k = 0; k < c->n_inst; ++k) {
+            InstHost& h = c->inst[k];
+            if (!h.any_free || h.cfg.host_body_update == 0) continue;
+            int rc = couple_on_host(c, h, p);
+            if (rc) return rc;
+        }
     return LBM_OK;
 }
 

@@ -477,8 +477,8 @@ __host__ __device__ inline bool integrate_rigid(const double half[3], const doub
 }
 
 // Grid of the boundary sweep (256-thread workgroups, four wavefronts each);
-// every wavefront of it writes one force record per step.
-constexpr int BND_BLOCKS_MAX = 4096;
+// every workgroup of it writes one force record per step.
+constexpr int BND_BLOCKS_MAX = 1024;
 __host__ __device__ inline int boundary_blocks(const Inst& I) {
     const int need = (I.N + 255) / 256;
     return need < BND_BLOCKS_MAX ? need : BND_BLOCKS_MAX;

@@ -282,16 +282,18 @@ def test_dam_break_conserves_mass(lbm):
     assert abs(Mg - lg - Mg0) / Mg0 < 2e-6
 
 
-def test_config1_free_body(lbm):
+@pytest.mark.parametrize("host_update", [0, 1])
+def test_config1_free_body(lbm, host_update):
     """32^3 basin, tau 0.6, g 1e-5, depth 16, 8x8x4 box of density 0.5 free
-    in 6 DOF, noise 1e-4 seed 1, 200 coupled steps (host update fed with the
-    mean force of two steps) on both sides: flags, populations, pose and
-    forces stay together and the box floats at its draft."""
+    in 6 DOF, noise 1e-4 seed 1, 200 coupled steps (rigid-body update fed
+    with the mean force of two steps; on the device or on the host) on both
+    sides: flags, populations, pose and forces stay together and the box
+    floats at its draft."""
     w = W.config1()
-    cfg = w["lattice"]
+    cfg = dict(w["lattice"], host_body_update=host_update)
     body = dict(w["bodies"][0], fixed=0, dof=w["dof"])
     L, o = pair(lbm, cfg, [body])
-    say("config1 free body 200 coupled steps")
+    say("config1 free body 200 coupled steps, host update %d" % host_update)
     L.step(w["steps"])
     o.step_coupled(w["steps"], [w["dof"]])
     rel, mism = compare_pop(L, o, 1e-5, label="config1")
@@ -306,6 +308,28 @@ def test_config1_free_body(lbm):
     # floating: buoyancy balances the weight rho_s V g = 0.5 * 256 * 1e-5
     assert Fg[2] == pytest.approx(1.28e-3, rel=0.05)
     assert abs(bg["pos"][2] - 16.0) < 0.05
+
+
+def test_device_and_host_body_update_agree(lbm):
+    """The device rigid-body update and the host one (lbm_integrate_body)
+    run the same FP64 operations, except that sin / cos come from different
+    math libraries (an ulp apart): over 120 released steps of the 32^3 box
+    the fluid feedback grows that to ~1e-10 cells, so pose and velocities
+    agree to 1e-8 (absolute, in cells and cells per step) and the cell flags
+    exactly."""
+    w = W.config1()
+    body = dict(w["bodies"][0], fixed=0, dof=w["dof"])
+    runs = []
+    for mode in (0, 1):
+        L = lbm.Lattice(dict(w["lattice"], max_bodies=1, host_body_update=mode))
+        L.set_body(0, body)
+        L.step(120)
+        L.sync()
+        runs.append((L.get_body(0), L.flags()))
+    (bd, fd), (bh, fh) = runs
+    for k in ("pos", "quat", "vel", "omega"):
+        np.testing.assert_allclose(bd[k], bh[k], rtol=0, atol=1e-8)
+    assert np.array_equal(fd, fh)
 
 
 def test_released_heeled_box_128(lbm):
