@@ -5,17 +5,24 @@ basin, tau 0.55, gravity 5e-6, liquid depth 64, with a 32x32x16 box of
 density 0.5 released at 20 deg heel about x (roll only).  One "step" is one
 pass of the whole hot path: body remap, fused stream/collide/boundary/mass-
 exchange/momentum-exchange sweep, interface conversions, force reduction and
-the host rigid-body update feeding the next remap.  Inputs are synthetic and
+the rigid-body update feeding the next remap.  Inputs are synthetic and
 resident in HBM before the timed region.
 
 Prints one JSON line.  `value` is MLUPS over all cells of the FP32-storage
-run; `fp16` repeats the timed run with FP16 deviation storage.  `roofline`
-prices the dominant kernel (the sweep) with its algorithmic bytes against
-the 8 TB/s HBM peak, its duration measured with HIP events around every
-sweep launch inside the timed region.  `cpu_baseline` times the FP64 oracle
-on the host on a bounded sample of the same workload.
+run with the rigid-body update on the device; `fp16` repeats the timed run
+with FP16 deviation storage, `host_body_update` with the update on the host.
+`roofline` prices the dominant kernel (the bulk sweep) with its algorithmic
+bytes against the 8 TB/s HBM peak, its duration measured with HIP events
+around every launch inside the timed region; `traffic` is the HBM bytes per
+launch the profiler counted (profiles/k_sweep_bulk_basin128_traffic.txt),
+reported only while the kernel source is the one that was profiled.
+`righting_moment` holds the box at the heel angles of the oracle's golden
+run and compares the averaged -T_x with the FP64 oracle's values
+(tests/golden/righting_moment_128.json).  `cpu_baseline` times the FP64
+oracle on the host on a bounded sample of the same workload.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -28,6 +35,34 @@ if ROOT not in sys.path:
 
 METRIC = "MLUPS + % of HBM roofline (FP32 vs FP16-storage) at ≤1% righting-moment error"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_bulk_basin128_traffic.txt")
+GOLDEN_RM = os.path.join(ROOT, "tests", "golden", "righting_moment_128.json")
+SWEEP_SOURCES = ("paper_1201_0351_amd/csrc/k_sweep.hip", "paper_1201_0351_amd/csrc/lgs_internal.h")
+
+
+def sweep_source_hash():
+    h = hashlib.sha256()
+    for p in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(storage):
+    """HBM bytes per bulk-sweep launch from the committed counter summary,
+    if it was taken on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith(" "):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_sha256_16") != sweep_source_hash():
+        return None
+    v = vals.get("traffic_bytes_per_launch_%s" % storage)
+    return int(float(v)) if v else None
 
 
 def algorithmic_bytes(types, storage_bytes, n_boundary):
@@ -49,43 +84,74 @@ def algorithmic_bytes(types, storage_bytes, n_boundary):
                                                                   boundary_list=n_boundary)
 
 
-def run_gpu(storage, steps, warmup):
-    import numpy as np
+def run_gpu(storage, steps, warmup, host_update=0, timing=True):
     import torch
 
     from paper_1201_0351_amd import lbm
     from paper_1201_0351_amd import workloads as W
 
     w = W.config2(20.0, released=True, storage=storage)
-    cfg = w["lattice"]
-    L = lbm.Lattice(dict(cfg, max_bodies=1))
-    # free body: the library runs the host rigid-body update after every step
+    cfg = dict(w["lattice"], max_bodies=1, host_body_update=host_update)
+    L = lbm.Lattice(cfg)
+    # free body: the rigid-body update runs after every step
     L.set_body(0, dict(w["bodies"][0], fixed=0, dof=w["dof"]))
     L.step(max(1, warmup))
     types = L.types()
     alg_bytes, counts = algorithmic_bytes(types, 4 if storage == "fp32" else 2, L.boundary_cells())
     L.sync()
     torch.cuda.synchronize()
-    L.enable_kernel_timing(True)
+    # plain timed run (no events), then the same number of steps with the
+    # sweep kernels bracketed by HIP events
     t0 = time.perf_counter()
     L.step(steps)
     L.sync()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    dt = time.perf_counter() - t0
+    n = L.ncells()
+    res = dict(value=n * steps / dt / 1e6, ms_per_step=1e3 * dt / steps, cells=n, counts=counts, alg_bytes=alg_bytes)
+    if timing:
+        L.enable_kernel_timing(True)
+        L.step(steps)
+        bulk_ms, launches = L.kernel_time(0)
+        bnd_ms, _ = L.kernel_time(1)
+        L.enable_kernel_timing(False)
+        res.update(bulk_ms=bulk_ms / max(1, launches), boundary_ms=bnd_ms / max(1, launches))
     F, T = L.body_forces(0)
     body = L.get_body(0)
-    bulk_ms, launches = L.kernel_time(0)
-    bnd_ms, _ = L.kernel_time(1)
-    L.enable_kernel_timing(False)
-    n = L.ncells()
-    dt = t1 - t0
-    res = dict(value=n * steps / dt / 1e6, ms_per_step=1e3 * dt / steps, cells=n, counts=counts,
-               bulk_ms=bulk_ms / max(1, launches), boundary_ms=bnd_ms / max(1, launches), alg_bytes=alg_bytes)
     q = body["quat"]
-    heel = math.degrees(2.0 * math.atan2(q[1], q[0]))
-    res["body"] = dict(heel_deg=heel, torque_x=float(T[0]), force_z=float(F[2]))
+    res["body"] = dict(heel_deg=math.degrees(2.0 * math.atan2(q[1], q[0])), torque_x=float(T[0]),
+                       force_z=float(F[2]))
     L.close()
     return res
+
+
+def righting_moment(storage):
+    """Held box at the golden heel angles: -T_x averaged like the oracle's
+    golden run (every `every` steps over the last `window` of `steps`)."""
+    from paper_1201_0351_amd import lbm
+    from paper_1201_0351_amd import workloads as W
+
+    if not os.path.exists(GOLDEN_RM):
+        return None
+    with open(GOLDEN_RM) as f:
+        gold = json.load(f)
+    out = []
+    for run in gold["runs"]:
+        w = W.config2(run["heel_deg"], released=False, storage=storage)
+        L = lbm.Lattice(dict(w["lattice"], max_bodies=1))
+        L.set_body(0, w["bodies"][0])
+        done, samples = 0, []
+        while done < run["steps"]:
+            k = min(run["every"], run["steps"] - done)
+            L.step(k)
+            done += k
+            if done > run["steps"] - run["window"]:
+                samples.append(-L.body_forces(0)[1][0])
+        L.close()
+        ms = sum(samples) / len(samples)
+        out.append(dict(heel_deg=run["heel_deg"], m_s=ms, m_s_oracle=run["m_s"],
+                        rel_err=abs(ms - run["m_s"]) / abs(run["m_s"]), analytic=run["analytic_polygon"]))
+    return out
 
 
 def cpu_baseline(target_s=15.0):
@@ -131,6 +197,18 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes_per_copy": 4 * n}))
 
 
+def roofline(r, storage):
+    achieved = r["alg_bytes"]["bulk"] / (r["bulk_ms"] * 1e-3) / 1e9
+    sweep_gbs = r["alg_bytes"]["total"] / ((r["bulk_ms"] + r["boundary_ms"]) * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(storage),
+            "kernel": "k_sweep_bulk<%s,64>" % ("float" if storage == "fp32" else "__half"),
+            "alg_bytes_per_launch": r["alg_bytes"]["bulk"], "avg_launch_ms": round(r["bulk_ms"], 5),
+            "sweep_both_kernels": {"alg_bytes": r["alg_bytes"]["total"],
+                                   "avg_ms": round(r["bulk_ms"] + r["boundary_ms"], 5),
+                                   "achieved": round(sweep_gbs, 1), "frac": round(sweep_gbs / HBM_PEAK_GBS, 4)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +216,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-storage run")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the timed runs (no host-update run, no righting moment)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain fill and device copy of MIB MiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -149,13 +229,9 @@ def main():
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    from oracle import analytic as A
-
     r32 = run_gpu("fp32", args.steps, args.warmup)
     print("fp32: %.1f MLUPS, %.4f ms/step, bulk %.4f ms, boundary %.4f ms" % (
         r32["value"], r32["ms_per_step"], r32["bulk_ms"], r32["boundary_ms"]), file=sys.stderr, flush=True)
-    achieved = r32["alg_bytes"]["bulk"] / (r32["bulk_ms"] * 1e-3) / 1e9
-    sweep_gbs = r32["alg_bytes"]["total"] / ((r32["bulk_ms"] + r32["boundary_ms"]) * 1e-3) / 1e9
     out = {
         "metric": METRIC,
         "value": round(r32["value"], 1),
@@ -170,29 +246,35 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "basin 128^3, tau 0.55, g 5e-6, depth 64, box 32x32x16 rho_s 0.5 released at "
-                               "20 deg heel (roll only), FP32 deviation storage",
+                               "20 deg heel (roll only), FP32 deviation storage, rigid-body update on the device",
                    "cells": r32["cells"], "cell_types": r32["counts"]},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_sweep_bulk<float,64>", "alg_bytes_per_launch": r32["alg_bytes"]["bulk"],
-                     "avg_launch_ms": round(r32["bulk_ms"], 5),
-                     "sweep_both_kernels": {"alg_bytes": r32["alg_bytes"]["total"],
-                                            "avg_ms": round(r32["bulk_ms"] + r32["boundary_ms"], 5),
-                                            "achieved": round(sweep_gbs, 1),
-                                            "frac": round(sweep_gbs / HBM_PEAK_GBS, 4)}},
+        "roofline": roofline(r32, "fp32"),
     }
+    from oracle import analytic as A
+
     heel = r32["body"]["heel_deg"]
-    ana = A.righting_moment_polygon(32, 16, 32, math.radians(heel), 5e-6, zw=0.0)
-    out["body"] = dict(r32["body"], analytic_righting_moment=ana,
-                       note="dynamic roll; measured -T_x vs the static curve at the current heel")
+    out["body"] = dict(r32["body"], analytic_righting_moment=A.righting_moment_polygon(
+        32, 16, 32, math.radians(heel), 5e-6, zw=0.0), note="dynamic roll; measured -T_x vs the static curve")
     if not args.no_fp16:
         r16 = run_gpu("fp16", args.steps, args.warmup)
-        a16 = r16["alg_bytes"]["bulk"] / (r16["bulk_ms"] * 1e-3) / 1e9
         out["fp16"] = {"value": round(r16["value"], 1), "ms_per_step": round(r16["ms_per_step"], 4),
-                       "bulk_roofline_frac": round(a16 / HBM_PEAK_GBS, 4), "bulk_achieved_GBs": round(a16, 1),
-                       "bulk_avg_launch_ms": round(r16["bulk_ms"], 5),
-                       "boundary_avg_launch_ms": round(r16["boundary_ms"], 5), "body": r16["body"]}
+                       "roofline": roofline(r16, "fp16"), "body": r16["body"]}
         print("fp16: %.1f MLUPS" % r16["value"], file=sys.stderr, flush=True)
+    if not args.no_extra:
+        steps_h = max(1, args.steps // 4)
+        rh = run_gpu("fp32", steps_h, args.warmup, host_update=1, timing=False)
+        out["host_body_update"] = {"value": round(rh["value"], 1), "ms_per_step": round(rh["ms_per_step"], 4),
+                                   "steps": steps_h, "body": rh["body"]}
+        print("fp32 host update: %.1f MLUPS" % rh["value"], file=sys.stderr, flush=True)
+        rm = {}
+        for st in ("fp32", "fp16"):
+            v = righting_moment(st)
+            if v is not None:
+                rm[st] = v
+        if rm:
+            out["righting_moment"] = dict(rm, reference="FP64 oracle, held box, tests/golden/righting_moment_128.json",
+                                          max_rel_err={k: round(max(x["rel_err"] for x in v), 5)
+                                                       for k, v in rm.items()})
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

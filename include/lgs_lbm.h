@@ -201,8 +201,10 @@ int32_t lbm_liq_gas_contacts(lbm_ctx* ctx, int32_t inst, int64_t* contacts);
 /* Wait for all work of the context. */
 int32_t lbm_sync(lbm_ctx* ctx);
 
-/* Kernel timing: while enabled, HIP events bracket the two sweep kernels of
- * every step (on the context's stream).  lbm_kernel_time returns the summed
+/* Kernel timing: while enabled, HIP start / stop events are attached to the
+ * dispatches of the two sweep kernels of every step (extended launch on the
+ * context's stream: the events time the kernel itself, not marker packets
+ * around it).  lbm_kernel_time returns the summed
  * duration in milliseconds and the number of timed steps since the last
  * enable (synchronises).  Kernel ids: 0 = bulk sweep (liquid cells whose
  * sources are fluid or static wall), 1 = boundary sweep (interface cells and

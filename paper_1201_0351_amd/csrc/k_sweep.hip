@@ -33,6 +33,8 @@
 //                     nothing and the sums keep their precision.
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 #include "lgs_internal.h"
 
 namespace lgs {
@@ -563,39 +565,45 @@ __global__ __launch_bounds__(256) void k_sweep_boundary(Inst I, int parity) {
     }
 }
 
+// The sweep kernels go through the extended launch, which records the
+// optional start / stop events with the dispatch itself (the kernel's own
+// execution, without separate marker packets).
 template <typename S, int TX>
-static void launch_bulk_t(const Inst& I, int parity, hipStream_t s) {
+static void launch_bulk_t(const Inst& I, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     constexpr int TY = 256 / TX;
     const int tiles_x = (I.nx + TX - 1) / TX;
     const int tiles_y = (I.ny + TY - 1) / TY;
     const int nblk = tiles_x * tiles_y * I.nz;
-    hipLaunchKernelGGL((k_sweep_bulk<S, TX>), dim3(nblk), dim3(256), 0, s, I, parity, tiles_x, tiles_y);
+    hipExtLaunchKernelGGL((k_sweep_bulk<S, TX>), dim3(nblk), dim3(256), 0, s, e0, e1, 0, I, parity, tiles_x,
+                          tiles_y);
 }
 
-void launch_sweep_bulk(const Inst& I, int parity, hipStream_t s) {
+void launch_sweep_bulk(const Inst& I, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const bool wide = I.nx >= 64;
     switch (I.storage) {
     case LBM_FP16_DEV:
-        if (wide) launch_bulk_t<__half, 64>(I, parity, s);
-        else launch_bulk_t<__half, 32>(I, parity, s);
+        if (wide) launch_bulk_t<__half, 64>(I, parity, s, e0, e1);
+        else launch_bulk_t<__half, 32>(I, parity, s, e0, e1);
         break;
     case LBM_BF16_DEV:
-        if (wide) launch_bulk_t<__hip_bfloat16, 64>(I, parity, s);
-        else launch_bulk_t<__hip_bfloat16, 32>(I, parity, s);
+        if (wide) launch_bulk_t<__hip_bfloat16, 64>(I, parity, s, e0, e1);
+        else launch_bulk_t<__hip_bfloat16, 32>(I, parity, s, e0, e1);
         break;
     default:
-        if (wide) launch_bulk_t<float, 64>(I, parity, s);
-        else launch_bulk_t<float, 32>(I, parity, s);
+        if (wide) launch_bulk_t<float, 64>(I, parity, s, e0, e1);
+        else launch_bulk_t<float, 32>(I, parity, s, e0, e1);
         break;
     }
 }
 
-void launch_sweep_boundary(const Inst& I, int parity, hipStream_t s) {
+void launch_sweep_boundary(const Inst& I, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const dim3 g(boundary_blocks(I)), b(256);
     switch (I.storage) {
-    case LBM_FP16_DEV: hipLaunchKernelGGL(k_sweep_boundary<__half>, g, b, 0, s, I, parity); break;
-    case LBM_BF16_DEV: hipLaunchKernelGGL(k_sweep_boundary<__hip_bfloat16>, g, b, 0, s, I, parity); break;
-    default: hipLaunchKernelGGL(k_sweep_boundary<float>, g, b, 0, s, I, parity); break;
+    case LBM_FP16_DEV: hipExtLaunchKernelGGL(k_sweep_boundary<__half>, g, b, 0, s, e0, e1, 0, I, parity); break;
+    case LBM_BF16_DEV:
+        hipExtLaunchKernelGGL(k_sweep_boundary<__hip_bfloat16>, g, b, 0, s, e0, e1, 0, I, parity);
+        break;
+    default: hipExtLaunchKernelGGL(k_sweep_boundary<float>, g, b, 0, s, e0, e1, 0, I, parity); break;
     }
 }
 

@@ -153,7 +153,9 @@ struct lbm_ctx {
 static hipEvent_t next_event(lbm_ctx* c) {
     if (c->ev_used == c->ev_pool.size()) {
         hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        // timing only: no system-scope fence when the event completes, so the
+        // brackets add as little as possible to the measured kernels
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
         c->ev_pool.push_back(e);
     }
     return c->ev_pool[c->ev_used++];
@@ -461,14 +463,14 @@ static int run_step(lbm_ctx* c, int mask) {
             remapped = true;
         }
         if (mask & LBM_PHASE_SWEEP) {
-            hipEvent_t e0 = c->timing ? next_event(c) : nullptr;
-            hipEvent_t e1 = c->timing ? next_event(c) : nullptr;
-            hipEvent_t e2 = c->timing ? next_event(c) : nullptr;
-            if (e0) HIP_OK(hipEventRecord(e0, c->stream));
-            launch_sweep_bulk(h.dev, p, c->stream);
-            if (e1) HIP_OK(hipEventRecord(e1, c->stream));
-            launch_sweep_boundary(h.dev, p, c->stream);
-            if (e2) HIP_OK(hipEventRecord(e2, c->stream));
+            hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+            if (c->timing)
+                for (int q = 0; q < 4; ++q) {
+                    e[q] = next_event(c);
+                    if (!e[q]) return fail(LBM_ERR_DEVICE, "kernel timing: event creation failed");
+                }
+            launch_sweep_bulk(h.dev, p, c->stream, e[0], e[1]);
+            launch_sweep_boundary(h.dev, p, c->stream, e[2], e[3]);
         } else if (mask & LBM_PHASE_CONVERT) {
             hipLaunchKernelGGL(k_copy_state, dim3((h.dev.N + 255) / 256), dim3(256), 0, c->stream, h.dev, p);
             launch_mark(h.dev, p, c->stream);
@@ -554,15 +556,21 @@ int32_t lbm_kernel_time(lbm_ctx* c, int32_t kernel, double* total_ms, int64_t* l
     if (!c || !total_ms || !launches) return fail(LBM_ERR_INVALID, "kernel_time: bad arguments");
     if (kernel < 0 || kernel > 2) return fail(LBM_ERR_INVALID, "kernel_time: unknown kernel id");
     HIP_OK(hipStreamSynchronize(c->stream));
+    // four events per timed sweep: bulk start / end, boundary start / end
     double tot = 0.0;
-    const int a = kernel == 1 ? 1 : 0, b = kernel == 0 ? 1 : 2;
-    for (size_t k = 0; k + 2 < c->ev_used; k += 3) {
+    for (size_t k = 0; k + 3 < c->ev_used; k += 4) {
         float ms = 0.f;
-        HIP_OK(hipEventElapsedTime(&ms, c->ev_pool[k + a], c->ev_pool[k + b]));
-        tot += ms;
+        if (kernel != 1) {
+            HIP_OK(hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]));
+            tot += ms;
+        }
+        if (kernel != 0) {
+            HIP_OK(hipEventElapsedTime(&ms, c->ev_pool[k + 2], c->ev_pool[k + 3]));
+            tot += ms;
+        }
     }
     *total_ms = tot;
-    *launches = (int64_t)(c->ev_used / 3);
+    *launches = (int64_t)(c->ev_used / 4);
     return LBM_OK;
 }
 

@@ -527,8 +527,10 @@ __device__ __forceinline__ float g_bcastf(float v, int src) { return __shfl(v, g
 // kernel launchers (implemented in the .hip files)
 // --------------------------------------------------------------------------
 void launch_init(const Inst& I, const lbm_config& c, hipStream_t s);
-void launch_sweep_bulk(const Inst& I, int parity, hipStream_t s);
-void launch_sweep_boundary(const Inst& I, int parity, hipStream_t s);
+// e0 / e1: optional events recorded at the start / end of the kernel itself
+void launch_sweep_bulk(const Inst& I, int parity, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+void launch_sweep_boundary(const Inst& I, int parity, hipStream_t s, hipEvent_t e0 = nullptr,
+                           hipEvent_t e1 = nullptr);
 void launch_mark(const Inst& I, int parity, hipStream_t s);
 void launch_convert(const Inst& I, int parity, bool retire_moves, bool integrate, hipStream_t s);
 void launch_finish(const Inst& I, int parity, bool reduce, bool zero_other, bool retire_moves, hipStream_t s);
