@@ -42,23 +42,21 @@ __device__ __forceinline__ double fill0(double H, int z) {
 
 template <typename S>
 __device__ __forceinline__ void write_feq(const Inst& I, S* pop, int id, double rho, const double u[3]) {
-    const size_t N = (size_t)I.N;
     const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const double cu = cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2];
         const double w = wgtd(i);
         const double dev = w * ((rho - 1.0) + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
-        Store<S>::st(pop, (size_t)i * N + id, (float)dev, I.scale);
+        Store<S>::st(pop, (size_t)i * I.ps + id, (float)dev, I.scale);
     }
 }
 
 template <typename S>
 __device__ __forceinline__ float cell_drho(const Inst& I, const S* pop, int id) {
-    const size_t N = (size_t)I.N;
     float dr = 0.f;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) dr += Store<S>::ld(pop, (size_t)i * N + id, I.inv_scale);
+    for (int i = 0; i < Q; ++i) dr += Store<S>::ld(pop, (size_t)i * I.ps + id, I.inv_scale);
     return dr;
 }
 
@@ -83,7 +81,6 @@ __global__ __launch_bounds__(256) void k_init(Inst I, InitParams P) {
     if (id >= I.N) return;
     int x, y, z;
     cell_coords(I, id, x, y, z);
-    const size_t N = (size_t)I.N;
     const double ph = fill0(P.H, z);
     int t = ph >= 1.0 ? LIQ : (ph > 0.0 ? IFC : GAS);
     if (t == LIQ) {
@@ -103,8 +100,8 @@ __global__ __launch_bounds__(256) void k_init(Inst I, InitParams P) {
     I.flags[id] = (uint8_t)t;
     if (t == GAS) {
         for (int i = 0; i < Q; ++i) {
-            Store<S>::st(p0, (size_t)i * N + id, 0.f, I.scale);
-            Store<S>::st(p1, (size_t)i * N + id, 0.f, I.scale);
+            Store<S>::st(p0, (size_t)i * I.ps + id, 0.f, I.scale);
+            Store<S>::st(p1, (size_t)i * I.ps + id, 0.f, I.scale);
         }
         I.m_hi[id] = I.m_lo[id] = 0.f;
         I.phi[0][id] = I.phi[1][id] = 0.f;
@@ -116,7 +113,7 @@ __global__ __launch_bounds__(256) void k_init(Inst I, InitParams P) {
     double u[3] = {0.0, 0.0, 0.0};
     if (P.us != 0.0 && P.H > 0.0) u[0] = P.us * zc * (2.0 * P.H - zc) / (P.H * P.H);
     write_feq<S>(I, p0, id, rho, u);
-    for (int i = 0; i < Q; ++i) Store<S>::st(p1, (size_t)i * N + id, 0.f, I.scale);
+    for (int i = 0; i < Q; ++i) Store<S>::st(p1, (size_t)i * I.ps + id, 0.f, I.scale);
     float hi, lo;
     split_mass(ph * rho, hi, lo);
     I.m_hi[id] = hi;

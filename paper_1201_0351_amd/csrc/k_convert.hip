@@ -59,11 +59,10 @@ __device__ __forceinline__ void push(int* list, int* cnt, int cap, int* overflow
 
 template <typename S>
 __device__ __forceinline__ void moments(const Inst& I, const S* pop, int id, float& drho, float u[3]) {
-    const size_t N = (size_t)I.N;
     float dr = 0.f, j0 = 0.f, j1 = 0.f, j2 = 0.f;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const float v = Store<S>::ld(pop, (size_t)i * N + id, I.inv_scale);
+        const float v = Store<S>::ld(pop, (size_t)i * I.ps + id, I.inv_scale);
         dr += v;
         j0 += cx(i) * v;
         j1 += cy(i) * v;
@@ -78,10 +77,9 @@ __device__ __forceinline__ void moments(const Inst& I, const S* pop, int id, flo
 
 template <typename S>
 __device__ __forceinline__ float drho_of(const Inst& I, const S* pop, int id) {
-    const size_t N = (size_t)I.N;
     float dr = 0.f;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) dr += Store<S>::ld(pop, (size_t)i * N + id, I.inv_scale);
+    for (int i = 0; i < Q; ++i) dr += Store<S>::ld(pop, (size_t)i * I.ps + id, I.inv_scale);
     return dr;
 }
 
@@ -151,7 +149,7 @@ __device__ __forceinline__ int lane_nbr(const Inst& I, int x, int y, int z) {
 template <typename S>
 __device__ __forceinline__ float g_drho(const Inst& I, const S* pop, int id) {
     const int q = g_lane();
-    return gsum(q < Q ? Store<S>::ld(pop, (size_t)q * I.N + id, I.inv_scale) : 0.f);
+    return gsum(q < Q ? Store<S>::ld(pop, (size_t)q * I.ps + id, I.inv_scale) : 0.f);
 }
 
 // claim: one 32-lane group per candidate, lane i looks at neighbour x + c_i.
@@ -199,7 +197,6 @@ __device__ __forceinline__ void phase_newgas(const Inst& I, int parity) {
     StepCounters& C = I.ctl->cnt[parity];
     const int n = min(load_count(&C.n_newg), I.list_cap);
     S* pop = (S*)I.pop[parity ^ 1];
-    const size_t N = (size_t)I.N;
     float* phi = I.phi[parity ^ 1];
     const int j = g_lane();
     const int grp = threadIdx.x >> 5, ngrp = blockDim.x >> 5;
@@ -231,7 +228,7 @@ __device__ __forceinline__ void phase_newgas(const Inst& I, int parity) {
         if (j < Q) {
             const float cu = lane_c(CXP, j) * v0 + lane_c(CYP, j) * v1 + lane_c(CZP, j) * v2;
             const float deq = lane_w(j) * (drb + rb * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
-            Store<S>::st(pop, (size_t)j * N + g, deq, I.scale);
+            Store<S>::st(pop, (size_t)j * I.ps + g, deq, I.scale);
         }
         if (j == 0) {
             I.m_hi[g] = 0.f;

@@ -81,11 +81,11 @@ __device__ __forceinline__ void two_sum_add(float& hi, float& lo, float dm) {
 // The nine pairs (i, ibar) of opposite D3Q19 links, primary member first.
 __device__ constexpr int PAIR_P[9] = {2, 3, 5, 8, 9, 10, 12, 14, 16};
 
-// BGK collision with the force term on pulled deviations d[], written to dst.
-// Evaluated per pair of opposite links: the equilibrium and the force term
-// split into a part even in c_i (shared) and a part odd in c_i (sign flips).
-template <typename S>
-__device__ __forceinline__ void collide_store(const Inst& I, float (&d)[Q], S* __restrict__ dst, size_t N, int id) {
+// BGK collision with the force term on pulled deviations d[]: post-collision
+// deviations in out[].  Evaluated per pair of opposite links: the equilibrium
+// and the force term split into a part even in c_i (shared) and a part odd
+// in c_i (sign flips).
+__device__ __forceinline__ void collide(const Inst& I, const float (&d)[Q], float (&out)[Q]) {
     float drho = d[0], j0 = 0.f, j1 = 0.f, j2 = 0.f;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
@@ -107,7 +107,7 @@ __device__ __forceinline__ void collide_store(const Inst& I, float (&d)[Q], S* _
         const float w = wgt(0);
         const float deq = w * (drho - rho * uu15);
         const float F = -w * rho * ua3;
-        Store<S>::store(dst, id, d[0] + om * (deq - d[0]) + F, I.scale);
+        out[0] = d[0] + om * (deq - d[0]) + F;
     }
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
@@ -120,11 +120,18 @@ __device__ __forceinline__ void collide_store(const Inst& I, float (&d)[Q], S* _
         const float odd = 3.f * wr * cu;
         const float Fe = wr * (9.f * cu * ca - ua3);
         const float Fo = 3.f * wr * ca;
-        const float dp = d[p] + om * (even + odd - d[p]) + (Fe + Fo);
-        const float dq = d[q] + om * (even - odd - d[q]) + (Fe - Fo);
-        Store<S>::store(dst, (size_t)p * N + id, dp, I.scale);
-        Store<S>::store(dst, (size_t)q * N + id, dq, I.scale);
+        out[p] = d[p] + om * (even + odd - d[p]) + (Fe + Fo);
+        out[q] = d[q] + om * (even - odd - d[q]) + (Fe - Fo);
     }
+}
+
+template <typename S>
+__device__ __forceinline__ void collide_store(const Inst& I, const float (&d)[Q], S* __restrict__ dst, size_t N,
+                                              int id) {
+    float o[Q];
+    collide(I, d, o);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) Store<S>::store(dst, (size_t)i * I.ps + id, o[i], I.scale);
 }
 
 }  // namespace
@@ -132,6 +139,55 @@ __device__ __forceinline__ void collide_store(const Inst& I, float (&d)[Q], S* _
 // ---------------------------------------------------------------------------
 // bulk sweep
 // ---------------------------------------------------------------------------
+// One liquid cell: true if a source is gas or an obstacle (the cell is left
+// to the boundary sweep), else pull, collide and store.
+template <typename S>
+__device__ __forceinline__ bool bulk_cell(const Inst& I, const S* __restrict__ src, S* __restrict__ dst, int x, int y,
+                                          int z, int id) {
+    // all 37 loads are issued without branches; per-link array bases are
+    // wavefront-uniform and the per-cell offset is 32-bit
+    float d[Q];
+    uint8_t sf[Q];
+    d[0] = Store<S>::load(src, id, I.inv_scale);
+    const bool interior = x > 0 && x < I.nx - 1 && y > 0 && y < I.ny - 1 && z > 0 && z < I.nz - 1;
+    if (interior) {
+        const int sxy = I.nx, sz = I.nx * I.ny;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const int s = id - (cx(i) + sxy * cy(i) + sz * cz(i));
+            d[i] = Store<S>::load(src + (size_t)i * I.ps, (unsigned)s, I.inv_scale);
+            sf[i] = I.flags[(unsigned)s];
+        }
+    } else {
+        const bool px = I.periodic & 1, py = I.periodic & 2, pz = I.periodic & 4;
+        const int xm = step_axis(x, -1, I.nx, px), xp = step_axis(x, 1, I.nx, px);
+        const int ym = step_axis(y, -1, I.ny, py), yp = step_axis(y, 1, I.ny, py);
+        const int zm = step_axis(z, -1, I.nz, pz), zp = step_axis(z, 1, I.nz, pz);
+        // a wall source reads this cell's own flag (liquid) and, for the
+        // halfway bounce-back, its own f_ibar
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const int X = cx(i) == 1 ? xm : (cx(i) == -1 ? xp : x);
+            const int Y = cy(i) == 1 ? ym : (cy(i) == -1 ? yp : y);
+            const int Z = cz(i) == 1 ? zm : (cz(i) == -1 ? zp : z);
+            const bool ok = (X | Y | Z) >= 0;
+            const int s = ok ? X + I.nx * (Y + I.ny * Z) : id;
+            const int arr = ok ? i : opp(i);
+            d[i] = Store<S>::load(src + (size_t)arr * I.ps, (unsigned)s, I.inv_scale);
+            sf[i] = I.flags[(unsigned)s];
+        }
+    }
+    uint32_t bad = 0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const uint32_t st = sf[i] & TYPE_MASK;
+        bad |= (uint32_t)(st == GAS) | (uint32_t)(st == OBS);
+    }
+    if (bad) return true;
+    collide_store<S>(I, d, dst, I.ps, id);
+    return false;
+}
+
 template <typename S, int TX>
 __global__ __launch_bounds__(256) void k_sweep_bulk(Inst I, int parity, int tiles_x, int tiles_y) {
     constexpr int TY = 256 / TX;
@@ -154,7 +210,6 @@ __global__ __launch_bounds__(256) void k_sweep_bulk(Inst I, int parity, int tile
     const int x = tx * TX + (threadIdx.x % TX);
     const int y = ty * TY + (threadIdx.x / TX);
 
-    const size_t N = (size_t)I.N;
     const S* __restrict__ src = (const S*)I.pop[parity];
     S* __restrict__ dst = (S*)I.pop[parity ^ 1];
     StepCounters& C = I.ctl->cnt[parity];
@@ -167,49 +222,7 @@ __global__ __launch_bounds__(256) void k_sweep_bulk(Inst I, int parity, int tile
     if (inb && (fl & ~KEEP_MASK)) I.flags[id] = fl & KEEP_MASK;
 
     bool defer = (type == IFC);
-    if (type == LIQ) {
-        // all 37 loads are issued without branches; per-link array bases are
-        // wavefront-uniform and the per-cell offset is 32-bit
-        float d[Q];
-        uint8_t sf[Q];
-        d[0] = Store<S>::load(src, id, I.inv_scale);
-        const bool interior = x > 0 && x < I.nx - 1 && y > 0 && y < I.ny - 1 && z > 0 && z < I.nz - 1;
-        if (interior) {
-            const int sxy = I.nx, sz = I.nx * I.ny;
-#pragma unroll
-            for (int i = 1; i < Q; ++i) {
-                const int s = id - (cx(i) + sxy * cy(i) + sz * cz(i));
-                d[i] = Store<S>::load(src + (size_t)i * N, (unsigned)s, I.inv_scale);
-                sf[i] = I.flags[(unsigned)s];
-            }
-        } else {
-            const bool px = I.periodic & 1, py = I.periodic & 2, pz = I.periodic & 4;
-            const int xm = step_axis(x, -1, I.nx, px), xp = step_axis(x, 1, I.nx, px);
-            const int ym = step_axis(y, -1, I.ny, py), yp = step_axis(y, 1, I.ny, py);
-            const int zm = step_axis(z, -1, I.nz, pz), zp = step_axis(z, 1, I.nz, pz);
-            // a wall source reads this cell's own flag (liquid) and, for the
-            // halfway bounce-back, its own f_ibar
-#pragma unroll
-            for (int i = 1; i < Q; ++i) {
-                const int X = cx(i) == 1 ? xm : (cx(i) == -1 ? xp : x);
-                const int Y = cy(i) == 1 ? ym : (cy(i) == -1 ? yp : y);
-                const int Z = cz(i) == 1 ? zm : (cz(i) == -1 ? zp : z);
-                const bool ok = (X | Y | Z) >= 0;
-                const int s = ok ? X + I.nx * (Y + I.ny * Z) : id;
-                const int arr = ok ? i : opp(i);
-                d[i] = Store<S>::load(src + (size_t)arr * N, (unsigned)s, I.inv_scale);
-                sf[i] = I.flags[(unsigned)s];
-            }
-        }
-        uint32_t bad = 0;
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            const uint32_t st = sf[i] & TYPE_MASK;
-            bad |= (uint32_t)(st == GAS) | (uint32_t)(st == OBS);
-        }
-        if (bad) defer = true;
-        else collide_store<S>(I, d, dst, N, id);
-    }
+    if (type == LIQ) defer = bulk_cell<S>(I, src, dst, x, y, z, id);
     wave_append(defer, id, I.bnd, &C.n_bnd, I.list_cap, &C.overflow);
 }
 
@@ -235,7 +248,6 @@ __device__ __forceinline__ float osum(float v) {
 
 template <typename S>
 __global__ __launch_bounds__(256) void k_sweep_boundary(Inst I, int parity) {
-    const size_t N = (size_t)I.N;
     const S* __restrict__ src = (const S*)I.pop[parity];
     S* __restrict__ dst = (S*)I.pop[parity ^ 1];
     const float isc = I.inv_scale;
@@ -295,8 +307,8 @@ __global__ __launch_bounds__(256) void k_sweep_boundary(Inst I, int parity) {
                 const bool ok = (X | Y | Z) >= 0;
                 const int s = ok ? X + I.nx * (Y + I.ny * Z) : id;
                 sfe[j] = ok ? (int)I.flags[s] : -1;
-                dr[j] = Store<S>::ld(src, (size_t)i * N + s, isc);
-                dx[j] = Store<S>::ld(src, (size_t)i * N + id, isc);
+                dr[j] = Store<S>::ld(src, (size_t)i * I.ps + s, isc);
+                dx[j] = Store<S>::ld(src, (size_t)i * I.ps + id, isc);
                 const float sp = phi_t[s];
                 lsf[cell][i] = sfe[j];
                 ldr[cell][i] = dr[j];
@@ -488,7 +500,7 @@ __global__ __launch_bounds__(256) void k_sweep_boundary(Inst I, int parity) {
                 const float ca = cxf * I.ax + cyf * I.ay + czf * I.az;
                 const float deq = wi * (drho + rho * (3.f * cu + 4.5f * cu * cu - uq));
                 const float F = wi * rho * (3.f * (ca - ua) + 9.f * cu * ca);
-                Store<S>::store(dst, (size_t)i * N + id, d[j] + I.omega * (deq - d[j]) + F, I.scale);
+                Store<S>::store(dst, (size_t)i * I.ps + id, d[j] + I.omega * (deq - d[j]) + F, I.scale);
             }
             if (abody >= 0) {
                 if (rec_body < 0) rec_body = abody;

@@ -37,6 +37,19 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 size_t storage_bytes(int storage) { return storage == LBM_FP32 ? 4 : 2; }
 
+// Elements between two population planes: N plus a pad, so that the planes a
+// wavefront streams do not all start at the same offset modulo a large power
+// of two (LGS_PLANE_PAD_BYTES, a multiple of 256).
+#ifndef LGS_PLANE_PAD_BYTES
+#define LGS_PLANE_PAD_BYTES 0
+#endif
+size_t plane_stride(const lbm_config& c) {
+    const size_t N = (size_t)c.nx * c.ny * c.nz;
+    const size_t sb = storage_bytes(c.storage);
+    const size_t bytes = (N * sb + 255) / 256 * 256 + LGS_PLANE_PAD_BYTES;
+    return bytes / sb;
+}
+
 struct InstHost {
     lbm_config cfg;
     Inst dev;
@@ -58,8 +71,9 @@ size_t layout(const lbm_config& c, Inst* I, char* base) {
         off += align256(bytes);
         return p;
     };
-    char* p0 = take(Q * N * sb);
-    char* p1 = take(Q * N * sb);
+    const size_t ps = plane_stride(c);
+    char* p0 = take(Q * ps * sb);
+    char* p1 = take(Q * ps * sb);
     char* fl = take(N);
     char* ph0 = take(4 * N);
     char* ph1 = take(4 * N);
@@ -222,6 +236,7 @@ int32_t lbm_create(const lbm_config* cfgs, int32_t n_inst, void* d_workspace, si
         I.ny = h.cfg.ny;
         I.nz = h.cfg.nz;
         I.N = h.cfg.nx * h.cfg.ny * h.cfg.nz;
+        I.ps = plane_stride(h.cfg);
         I.periodic = h.cfg.periodic & 7;
         I.recon_mode = h.cfg.recon_mode;
         I.storage = h.cfg.storage;
@@ -719,7 +734,8 @@ int32_t lbm_read_fields(lbm_ctx* c, int32_t inst, int32_t field, int32_t dtype, 
         return fail(LBM_ERR_INVALID, "read_fields: unknown field");
     const size_t sb = storage_bytes(I.storage);
     std::vector<char> raw(Q * N * sb);
-    HIP_OK(hipMemcpy(raw.data(), I.pop[p], raw.size(), hipMemcpyDeviceToHost));
+    // planes are ps apart on the device, N apart here
+    HIP_OK(hipMemcpy2D(raw.data(), N * sb, I.pop[p], I.ps * sb, N * sb, Q, hipMemcpyDeviceToHost));
     auto dev = [&](int i, size_t k) -> double {
         const size_t j = (size_t)i * N + k;
         if (I.storage == LBM_FP32) return (double)((const float*)raw.data())[j];
@@ -827,7 +843,7 @@ int32_t lbm_write_fields(lbm_ctx* c, int32_t inst, int32_t field, int32_t dtype,
             else if (I.storage == LBM_FP16_DEV) ((uint16_t*)raw.data())[j] = float_to_half((float)(d * I.scale));
             else ((uint16_t*)raw.data())[j] = float_to_bf16((float)d);
         }
-    HIP_OK(hipMemcpy(I.pop[p], raw.data(), raw.size(), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy2D(I.pop[p], I.ps * sb, raw.data(), N * sb, N * sb, Q, hipMemcpyHostToDevice));
     return LBM_OK;
 }
 
@@ -855,6 +871,6 @@ __global__ __launch_bounds__(256) void k_copy_state(Inst I, int from) {
     const size_t sb = I.storage == LBM_FP32 ? 4 : 2;
     const char* s = (const char*)I.pop[from];
     char* d = (char*)I.pop[from ^ 1];
-    for (int i = 0; i < Q; ++i) memcpy(d + ((size_t)i * N + id) * sb, s + ((size_t)i * N + id) * sb, sb);
+    for (int i = 0; i < Q; ++i) memcpy(d + ((size_t)i * I.ps + id) * sb, s + ((size_t)i * I.ps + id) * sb, sb);
     I.phi[from ^ 1][id] = I.phi[from][id];
 }

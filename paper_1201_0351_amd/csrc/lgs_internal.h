@@ -4,7 +4,8 @@
 // Layout of one lattice instance in device memory (all arrays x fastest,
 // cell index id = x + nx (y + ny z), N cells):
 //   pop[2]    two population lattices (ping-pong), structure of arrays
-//             [19][N] of the storage type, holding the deviation f_i - w_i
+//             [19][ps] of the storage type (planes ps >= N elements apart,
+//             first N used), holding the deviation f_i - w_i
 //             (FP32) or (f_i - w_i) * scale (FP16) / (f_i - w_i) (BF16)
 //   flags     u8[N]: bits 0-1 type, bits 2-5 body of an obstacle cell,
 //             bit 6 "filled" and bit 7 "emptied" marks (transient, between
@@ -110,6 +111,7 @@ struct DevBody {
 // Everything a kernel needs about one instance (passed by value).
 struct Inst {
     int nx, ny, nz, N;
+    size_t ps;  // elements between two population planes (>= N)
     uint32_t periodic;
     int recon_mode;
     int storage;

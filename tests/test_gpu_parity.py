@@ -119,6 +119,35 @@ def test_basin_steps_without_body(lbm, storage, tol):
     assert (Mg - lg) == pytest.approx(Mo - lo, rel=1e-6 if storage == "fp32" else 1e-3)
 
 
+@pytest.mark.parametrize("n,periodic,storage", [((130, 20, 18), 0, "fp16"), ((64, 24, 20), 1, "bf16"),
+                                                   ((96, 22, 20), 3, "fp16"), ((4, 10, 12), 0, "bf16")])
+def test_bulk_sweep_16bit_shapes(lbm, n, periodic, storage):
+    """16-bit storage on row lengths that leave partial tiles (130 = 2 x 64 +
+    2, 96) or one tile (64, 4), with periodic x and y: 12 steps against the
+    oracle, with a tolerance on the deviations f - w (the signal the storage
+    keeps)."""
+    cfg = W.basin(n, n[2] * 0.55, 0.6, 1e-5, seed=11, noise_amp=1e-4, storage=storage, periodic=periodic)
+    say("bulk 16-bit %s %s periodic %d" % (storage, n, periodic))
+    L, o = pair(lbm, cfg)
+    from oracle.oracle import lattice
+
+    w = lattice()[1][:, None, None, None]
+    # the deviations f - w carry the signal; a wrong source would be an O(1)
+    # error on them (FP16 keeps 11 significant bits, BF16 8)
+    dtol = 4e-3 if storage == "fp16" else 2e-2
+    for k in (1, 11):
+        L.step(k)
+        o.step(k)
+        compare_pop(L, o, 2e-3, label="16-bit %s %s +%d" % (storage, n, k))
+        tg, to = L.types(), o.types()
+        agree = (tg == to) & ((to == 1) | (to == 2))
+        dg, do = (L.pop() - w)[:, agree], (o.get_f() - w)[:, agree]
+        rel = np.linalg.norm(dg - do) / np.linalg.norm(do)
+        say("  deviation rel err %.3e" % rel)
+        assert rel <= dtol, rel
+    assert np.array_equal(L.flags() & 3, o.get_flags() & 3)
+
+
 def _injected(lbm, n=(40, 36, 32), H=14.3, amp=3.0, seed=3, threshold_frac=0.0, storage="fp32", periodic=0,
               bodies=()):
     """Both sides: a wavy liquid surface with random populations, fill levels
