@@ -289,24 +289,44 @@ __device__ __forceinline__ void remap_commit_cell(const Inst& I, int parity, int
     atomicAdd(&I.ctl->ledger, m);
 }
 
+// workgroup b of nb working on body k's region
 template <typename S>
-__global__ __launch_bounds__(256) void k_remap_eval(Inst I, int parity) {
-    const int k = blockIdx.y;
+__device__ __forceinline__ void remap_eval(const Inst& I, int parity, int k, int b, int nb) {
+    if (k >= I.nbodies) return;
     const DevBody& B = I.bodies[k];
     if (!B.active || !B.moved) return;
     const Region R = body_region(B, I.nx, I.ny, I.nz, I.periodic);
-    for (int local = blockIdx.x * 256 + threadIdx.x; local < R.cells; local += gridDim.x * 256)
-        remap_eval_cell<S>(I, parity, R, local);
+    for (int local = b * 256 + threadIdx.x; local < R.cells; local += nb * 256) remap_eval_cell<S>(I, parity, R, local);
 }
 
 template <typename S>
-__global__ __launch_bounds__(256) void k_remap_commit(Inst I, int parity) {
-    const int k = blockIdx.y;
+__device__ __forceinline__ void remap_commit(const Inst& I, int parity, int k, int b, int nb) {
+    if (k >= I.nbodies) return;
     const DevBody& B = I.bodies[k];
     if (!B.active || !B.moved) return;
     const Region R = body_region(B, I.nx, I.ny, I.nz, I.periodic);
-    for (int local = blockIdx.x * 256 + threadIdx.x; local < R.cells; local += gridDim.x * 256)
+    for (int local = b * 256 + threadIdx.x; local < R.cells; local += nb * 256)
         remap_commit_cell<S>(I, parity, k, B, R, local);
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_remap_eval(Inst I, int parity) {
+    remap_eval<S>(I, parity, blockIdx.y, blockIdx.x, gridDim.x);
+}
+template <typename S>
+__global__ __launch_bounds__(256) void k_remap_commit(Inst I, int parity) {
+    remap_commit<S>(I, parity, blockIdx.y, blockIdx.x, gridDim.x);
+}
+// a batch: instance blockIdx.z
+template <typename S>
+__global__ __launch_bounds__(256) void kb_remap_eval(const Inst* __restrict__ tab, int parity) {
+    const Inst I = tab[blockIdx.z];
+    remap_eval<S>(I, parity, blockIdx.y, blockIdx.x, gridDim.x);
+}
+template <typename S>
+__global__ __launch_bounds__(256) void kb_remap_commit(const Inst* __restrict__ tab, int parity) {
+    const Inst I = tab[blockIdx.z];
+    remap_commit<S>(I, parity, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
 void launch_remap(const Inst& I, int parity, int blocks_per_body, hipStream_t s) {
@@ -324,6 +344,26 @@ void launch_remap(const Inst& I, int parity, int blocks_per_body, hipStream_t s)
     default:
         hipLaunchKernelGGL(k_remap_eval<float>, g, b, 0, s, I, parity);
         hipLaunchKernelGGL(k_remap_commit<float>, g, b, 0, s, I, parity);
+        break;
+    }
+}
+
+void launch_remap_batch(const Inst* tab, int n, int max_bodies, int storage, int parity, int blocks_per_body,
+                        hipStream_t s) {
+    if (n == 0 || max_bodies == 0 || blocks_per_body <= 0) return;
+    const dim3 g(blocks_per_body, max_bodies, n), b(256);
+    switch (storage) {
+    case LBM_FP16_DEV:
+        hipLaunchKernelGGL(kb_remap_eval<__half>, g, b, 0, s, tab, parity);
+        hipLaunchKernelGGL(kb_remap_commit<__half>, g, b, 0, s, tab, parity);
+        break;
+    case LBM_BF16_DEV:
+        hipLaunchKernelGGL(kb_remap_eval<__hip_bfloat16>, g, b, 0, s, tab, parity);
+        hipLaunchKernelGGL(kb_remap_commit<__hip_bfloat16>, g, b, 0, s, tab, parity);
+        break;
+    default:
+        hipLaunchKernelGGL(kb_remap_eval<float>, g, b, 0, s, tab, parity);
+        hipLaunchKernelGGL(kb_remap_commit<float>, g, b, 0, s, tab, parity);
         break;
     }
 }

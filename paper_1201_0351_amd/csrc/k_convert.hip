@@ -495,9 +495,9 @@ __device__ __forceinline__ void bodies_wave(const Inst& I, int parity, bool reti
 // One step's conversions.  The last wavefront updates the bodies while the
 // others claim; the later phases use all groups.
 template <typename S>
-__global__ __launch_bounds__(CONV_THREADS) void k_convert(Inst I, int parity, int retire_moves, int integrate) {
+__device__ __forceinline__ void convert(const Inst& I, int parity, bool retire_moves, bool integrate) {
     phase_forces(I, parity);
-    if ((int)(threadIdx.x >> 6) == CONV_THREADS / 64 - 1) bodies_wave(I, parity, retire_moves != 0, integrate != 0);
+    if ((int)(threadIdx.x >> 6) == CONV_THREADS / 64 - 1) bodies_wave(I, parity, retire_moves, integrate);
     else phase_claim<S>(I, parity, threadIdx.x >> 5, CONV_THREADS / 32 - 2);
     __syncthreads();
     phase_newgas<S>(I, parity);
@@ -509,12 +509,40 @@ __global__ __launch_bounds__(CONV_THREADS) void k_convert(Inst I, int parity, in
     phase_finish(I, parity);
 }
 
+template <typename S>
+__global__ __launch_bounds__(CONV_THREADS) void k_convert(Inst I, int parity, int retire_moves, int integrate) {
+    convert<S>(I, parity, retire_moves != 0, integrate != 0);
+}
+
+// one workgroup per instance of a batch (at most 64: bit k of the masks
+// belongs to instance k)
+template <typename S>
+__global__ __launch_bounds__(CONV_THREADS) void kb_convert(const Inst* __restrict__ tab, int parity,
+                                                          unsigned long long retire_mask,
+                                                          unsigned long long integrate_mask) {
+    const int k = blockIdx.x;
+    const Inst I = tab[k];
+    convert<S>(I, parity, (retire_mask >> k) & 1ull, (integrate_mask >> k) & 1ull);
+}
+
 // End of a step without conversions (phase-isolated calls).
 __global__ __launch_bounds__(CONV_THREADS) void k_finish(Inst I, int parity, int reduce, int zero_other,
                                                          int retire_moves) {
     if (reduce) phase_forces(I, parity);
     if (threadIdx.x < 64) bodies_wave(I, parity, retire_moves != 0, false);
     if (zero_other) phase_finish(I, parity);
+}
+
+void launch_convert_batch(const Inst* tab, int n, int storage, int parity, unsigned long long retire_mask,
+                          unsigned long long integrate_mask, hipStream_t s) {
+    const dim3 g(n), b(CONV_THREADS);
+    switch (storage) {
+    case LBM_FP16_DEV: hipLaunchKernelGGL(kb_convert<__half>, g, b, 0, s, tab, parity, retire_mask, integrate_mask); break;
+    case LBM_BF16_DEV:
+        hipLaunchKernelGGL(kb_convert<__hip_bfloat16>, g, b, 0, s, tab, parity, retire_mask, integrate_mask);
+        break;
+    default: hipLaunchKernelGGL(kb_convert<float>, g, b, 0, s, tab, parity, retire_mask, integrate_mask); break;
+    }
 }
 
 void launch_convert(const Inst& I, int parity, bool retire_moves, bool integrate, hipStream_t s) {

@@ -188,14 +188,16 @@ __device__ __forceinline__ bool bulk_cell(const Inst& I, const S* __restrict__ s
     return false;
 }
 
+// Workgroup b of nb (nb a multiple of 8, b % 8 the XCD it runs on) of one
+// instance's bulk grid.
 template <typename S, int TX>
-__global__ __launch_bounds__(256) void k_sweep_bulk(Inst I, int parity, int tiles_x, int tiles_y) {
+__device__ __forceinline__ void sweep_bulk(const Inst& I, int parity, int b, int nb) {
     constexpr int TY = 256 / TX;
+    const int tiles_x = (I.nx + TX - 1) / TX, tiles_y = (I.ny + TY - 1) / TY;
     // XCD-aware tile order: workgroup b runs on XCD b % 8.  Whole z-layers
     // (chunks of tiles_x * tiles_y tiles) go round-robin to the XCDs, so a
     // layer's y-halo rows and flags stay in one L2 while liquid and gas layers
     // spread evenly over all eight XCDs.
-    const int nb = gridDim.x, b = blockIdx.x;
     const int CH = tiles_x * tiles_y;
     const int full = nb / (8 * CH) * (8 * CH);
     int t = b;
@@ -203,6 +205,7 @@ __global__ __launch_bounds__(256) void k_sweep_bulk(Inst I, int parity, int tile
         const int xcd = b & 7, kk = b >> 3;
         t = ((kk / CH) * 8 + xcd) * CH + kk % CH;
     }
+    if (t >= CH * I.nz) return;  // padding of the grid to a multiple of 8
     const int tx = t % tiles_x;
     const int rest = t / tiles_x;
     const int ty = rest % tiles_y;
@@ -226,6 +229,31 @@ __global__ __launch_bounds__(256) void k_sweep_bulk(Inst I, int parity, int tile
     wave_append(defer, id, I.bnd, &C.n_bnd, I.list_cap, &C.overflow);
 }
 
+// instance k of a batch: off[k] <= block < off[k + 1]
+__device__ __forceinline__ int batch_instance(const int* __restrict__ off, int n, int block) {
+    int lo = 0, hi = n;  // off[lo] <= block < off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= block) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <typename S, int TX>
+__global__ __launch_bounds__(256) void k_sweep_bulk(Inst I, int parity) {
+    sweep_bulk<S, TX>(I, parity, blockIdx.x, gridDim.x);
+}
+
+// all instances of a batch in one launch (instance table in device memory)
+template <typename S, int TX>
+__global__ __launch_bounds__(256) void kb_sweep_bulk(const Inst* __restrict__ tab, const int* __restrict__ off, int n,
+                                                     int parity) {
+    const int k = batch_instance(off, n, blockIdx.x);
+    const Inst I = tab[k];
+    sweep_bulk<S, TX>(I, parity, blockIdx.x - off[k], off[k + 1] - off[k]);
+}
+
 // ---------------------------------------------------------------------------
 // boundary sweep: interface cells, liquid cells next to gas or a body.
 // One group of 8 lanes per listed cell; lane l owns links l, l+8, l+16.
@@ -246,8 +274,10 @@ __device__ __forceinline__ float osum(float v) {
 }
 }  // namespace
 
+// Workgroup wg of nwg of one instance's boundary grid (wg is its
+// force-record slot).
 template <typename S>
-__global__ __launch_bounds__(256) void k_sweep_boundary(Inst I, int parity) {
+__device__ __forceinline__ void sweep_boundary(const Inst& I, int parity, int wg, int nwg) {
     const S* __restrict__ src = (const S*)I.pop[parity];
     S* __restrict__ dst = (S*)I.pop[parity ^ 1];
     const float isc = I.inv_scale;
@@ -276,7 +306,7 @@ __global__ __launch_bounds__(256) void k_sweep_boundary(Inst I, int parity) {
         bom[b][a] = (float)B.omega[a];
     }
 
-    for (int base = blockIdx.x * BCELLS; base < nlist; base += gridDim.x * BCELLS) {
+    for (int base = wg * BCELLS; base < nlist; base += nwg * BCELLS) {
         const int k = base + cell;
         const bool active = k < nlist;
         const int id = active ? I.bnd[k] : I.bnd[base];
@@ -571,41 +601,71 @@ __global__ __launch_bounds__(256) void k_sweep_boundary(Inst I, int parity) {
                 for (int q = 0; q < 6; ++q) atomicAdd(&C.acc[b][q], sv[w][q]);
             }
         }
-        I.frec_body[blockIdx.x] = body;
+        I.frec_body[wg] = body;
 #pragma unroll
-        for (int q = 0; q < 6; ++q) I.frec_v[q * BND_BLOCKS_MAX + blockIdx.x] = acc[q];
+        for (int q = 0; q < 6; ++q) I.frec_v[q * BND_BLOCKS_MAX + wg] = acc[q];
     }
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_sweep_boundary(Inst I, int parity) {
+    sweep_boundary<S>(I, parity, blockIdx.x, gridDim.x);
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void kb_sweep_boundary(const Inst* __restrict__ tab, const int* __restrict__ off,
+                                                         int n, int parity) {
+    const int k = batch_instance(off, n, blockIdx.x);
+    const Inst I = tab[k];
+    const int b = blockIdx.x - off[k];
+    if (b >= boundary_blocks(I)) return;  // padding of the grid to a multiple of 8
+    sweep_boundary<S>(I, parity, b, boundary_blocks(I));
 }
 
 // The sweep kernels go through the extended launch, which records the
 // optional start / stop events with the dispatch itself (the kernel's own
 // execution, without separate marker packets).
-template <typename S, int TX>
-static void launch_bulk_t(const Inst& I, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    constexpr int TY = 256 / TX;
-    const int tiles_x = (I.nx + TX - 1) / TX;
-    const int tiles_y = (I.ny + TY - 1) / TY;
-    const int nblk = tiles_x * tiles_y * I.nz;
-    hipExtLaunchKernelGGL((k_sweep_bulk<S, TX>), dim3(nblk), dim3(256), 0, s, e0, e1, 0, I, parity, tiles_x,
-                          tiles_y);
+int bulk_blocks(const Inst& I, int tile_x) {
+    const int ty = 256 / tile_x;
+    const int n = ((I.nx + tile_x - 1) / tile_x) * ((I.ny + ty - 1) / ty) * I.nz;
+    return (n + 7) / 8 * 8;
 }
 
-void launch_sweep_bulk(const Inst& I, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    const bool wide = I.nx >= 64;
-    switch (I.storage) {
-    case LBM_FP16_DEV:
-        if (wide) launch_bulk_t<__half, 64>(I, parity, s, e0, e1);
-        else launch_bulk_t<__half, 32>(I, parity, s, e0, e1);
-        break;
-    case LBM_BF16_DEV:
-        if (wide) launch_bulk_t<__hip_bfloat16, 64>(I, parity, s, e0, e1);
-        else launch_bulk_t<__hip_bfloat16, 32>(I, parity, s, e0, e1);
-        break;
-    default:
-        if (wide) launch_bulk_t<float, 64>(I, parity, s, e0, e1);
-        else launch_bulk_t<float, 32>(I, parity, s, e0, e1);
-        break;
+namespace {
+template <typename S, int TX>
+void bulk_one(const Inst& I, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    hipExtLaunchKernelGGL((k_sweep_bulk<S, TX>), dim3(bulk_blocks(I, TX)), dim3(256), 0, s, e0, e1, 0, I, parity);
+}
+template <typename S, int TX>
+void bulk_batch(const BatchGrid& G, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    hipExtLaunchKernelGGL((kb_sweep_bulk<S, TX>), dim3(G.blocks), dim3(256), 0, s, e0, e1, 0, G.tab, G.off, G.n,
+                          parity);
+}
+template <typename S>
+void bulk_tx(int tile_x, const Inst* I, const BatchGrid* G, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    switch (tile_x) {
+    case 32: I ? bulk_one<S, 32>(*I, parity, s, e0, e1) : bulk_batch<S, 32>(*G, parity, s, e0, e1); break;
+    case 128: I ? bulk_one<S, 128>(*I, parity, s, e0, e1) : bulk_batch<S, 128>(*G, parity, s, e0, e1); break;
+    default: I ? bulk_one<S, 64>(*I, parity, s, e0, e1) : bulk_batch<S, 64>(*G, parity, s, e0, e1); break;
     }
+}
+void bulk_dispatch(int storage, int tile_x, const Inst* I, const BatchGrid* G, int parity, hipStream_t s,
+                   hipEvent_t e0, hipEvent_t e1) {
+    switch (storage) {
+    case LBM_FP16_DEV: bulk_tx<__half>(tile_x, I, G, parity, s, e0, e1); break;
+    case LBM_BF16_DEV: bulk_tx<__hip_bfloat16>(tile_x, I, G, parity, s, e0, e1); break;
+    default: bulk_tx<float>(tile_x, I, G, parity, s, e0, e1); break;
+    }
+}
+}  // namespace
+
+void launch_sweep_bulk(const Inst& I, int parity, int tile_x, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    bulk_dispatch(I.storage, tile_x, &I, nullptr, parity, s, e0, e1);
+}
+
+void launch_sweep_bulk_batch(const BatchGrid& G, int storage, int tile_x, int parity, hipStream_t s, hipEvent_t e0,
+                             hipEvent_t e1) {
+    bulk_dispatch(storage, tile_x, nullptr, &G, parity, s, e0, e1);
 }
 
 void launch_sweep_boundary(const Inst& I, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
@@ -616,6 +676,20 @@ void launch_sweep_boundary(const Inst& I, int parity, hipStream_t s, hipEvent_t 
         hipExtLaunchKernelGGL(k_sweep_boundary<__hip_bfloat16>, g, b, 0, s, e0, e1, 0, I, parity);
         break;
     default: hipExtLaunchKernelGGL(k_sweep_boundary<float>, g, b, 0, s, e0, e1, 0, I, parity); break;
+    }
+}
+
+void launch_sweep_boundary_batch(const BatchGrid& G, int storage, int parity, hipStream_t s, hipEvent_t e0,
+                                 hipEvent_t e1) {
+    const dim3 g(G.blocks), b(256);
+    switch (storage) {
+    case LBM_FP16_DEV:
+        hipExtLaunchKernelGGL(kb_sweep_boundary<__half>, g, b, 0, s, e0, e1, 0, G.tab, G.off, G.n, parity);
+        break;
+    case LBM_BF16_DEV:
+        hipExtLaunchKernelGGL(kb_sweep_boundary<__hip_bfloat16>, g, b, 0, s, e0, e1, 0, G.tab, G.off, G.n, parity);
+        break;
+    default: hipExtLaunchKernelGGL(kb_sweep_boundary<float>, g, b, 0, s, e0, e1, 0, G.tab, G.off, G.n, parity); break;
     }
 }
 

@@ -160,9 +160,20 @@ struct lbm_ctx {
     bool have_forces = false;
     std::vector<InstHost> inst;
     bool timing = false;
-    std::vector<hipEvent_t> ev_pool;  // begin/end pairs of timed sweeps
+    std::vector<hipEvent_t> ev_pool;  // start/stop events of timed sweeps
     size_t ev_used = 0;
+    int tile_x = 64;  // bulk-sweep tile width (cells along x)
+    // batches: all instances of the context step with one launch per kernel
+    // (instance table and workgroup offsets at the head of the workspace)
+    bool batched = false;
+    Inst* d_tab = nullptr;
+    int* d_bulk_off = nullptr;
+    int* d_bnd_off = nullptr;
+    int bulk_total = 0, bnd_total = 0;
 };
+
+// Workspace head of a context: the instance table and two offset arrays.
+size_t ctx_head_bytes(int n) { return align256(sizeof(Inst) * n) + 2 * align256(sizeof(int) * (n + 1)); }
 
 static hipEvent_t next_event(lbm_ctx* c) {
     if (c->ev_used == c->ev_pool.size()) {
@@ -177,11 +188,33 @@ static hipEvent_t next_event(lbm_ctx* c) {
 
 extern "C" {
 
+// Instance table and workgroup offsets of a batched context (synchronous;
+// called at creation and whenever a descriptor or the tile width changes).
+static int upload_batch(lbm_ctx* c) {
+    if (!c->batched) return LBM_OK;
+    const int n = c->n_inst;
+    std::vector<Inst> tab(n);
+    std::vector<int> bo(n + 1), bb(n + 1);
+    bo[0] = bb[0] = 0;
+    for (int k = 0; k < n; ++k) {
+        tab[k] = c->inst[k].dev;
+        bo[k + 1] = bo[k] + bulk_blocks(tab[k], c->tile_x);
+        bb[k + 1] = bb[k] + (boundary_blocks(tab[k]) + 7) / 8 * 8;
+    }
+    c->bulk_total = bo[n];
+    c->bnd_total = bb[n];
+    HIP_OK(hipStreamSynchronize(c->stream));
+    HIP_OK(hipMemcpy(c->d_tab, tab.data(), sizeof(Inst) * n, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(c->d_bulk_off, bo.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(c->d_bnd_off, bb.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
+    return LBM_OK;
+}
+
 const char* lbm_last_error(void) { return g_err.c_str(); }
 
 int32_t lbm_workspace_size(const lbm_config* cfgs, int32_t n_inst, size_t* bytes) {
     if (!cfgs || n_inst <= 0 || !bytes) return fail(LBM_ERR_INVALID, "workspace_size: bad arguments");
-    size_t tot = 0;
+    size_t tot = ctx_head_bytes(n_inst);
     for (int k = 0; k < n_inst; ++k) {
         int rc = validate(cfgs[k], k);
         if (rc) return rc;
@@ -222,7 +255,10 @@ int32_t lbm_create(const lbm_config* cfgs, int32_t n_inst, void* d_workspace, si
         c->own_ws = true;
     }
     c->inst.resize(n_inst);
-    size_t off = 0;
+    c->d_tab = (Inst*)c->ws;
+    c->d_bulk_off = (int*)(c->ws + align256(sizeof(Inst) * n_inst));
+    c->d_bnd_off = (int*)(c->ws + align256(sizeof(Inst) * n_inst) + align256(sizeof(int) * (n_inst + 1)));
+    size_t off = ctx_head_bytes(n_inst);
     for (int k = 0; k < n_inst; ++k) {
         InstHost& h = c->inst[k];
         memset(&h, 0, sizeof(InstHost));
@@ -258,6 +294,14 @@ int32_t lbm_create(const lbm_config* cfgs, int32_t n_inst, void* d_workspace, si
         launch_init(I, h.cfg, c->stream);
         HIP_OK(hipGetLastError());
     }
+    c->tile_x = 64;
+    for (int k = 0; k < n_inst; ++k)
+        if (c->inst[k].cfg.nx < 64) c->tile_x = 32;
+    c->batched = n_inst > 1;
+    for (int k = 1; k < n_inst; ++k)
+        if (c->inst[k].cfg.storage != c->inst[0].cfg.storage) c->batched = false;
+    rc = upload_batch(c);
+    if (rc) return rc;
     *out = c;
     return LBM_OK;
 }
@@ -386,11 +430,13 @@ int32_t lbm_set_body(lbm_ctx* c, int32_t inst, int32_t k, const lbm_body* b) {
     h.desc[k] = *b;
     for (int a = 0; a < 3; ++a) h.desc[k].pos[a] = d.pos[a];
     h.bodies[k] = d;
-    if (k + 1 > h.dev.nbodies) h.dev.nbodies = k + 1;
+    const bool grown = k + 1 > h.dev.nbodies;
+    if (grown) h.dev.nbodies = k + 1;
     h.need_remap = true;
     refresh_instance_flags(h);
     launch_set_body(h.dev, k, h.bodies[k], c->stream);
     HIP_OK(hipGetLastError());
+    if (grown) return upload_batch(c);  // the descriptor changed
     return LBM_OK;
 }
 
@@ -466,7 +512,72 @@ static int couple_on_host(lbm_ctx* c, InstHost& h, int p) {
     return LBM_OK;
 }
 
+static int timing_events(lbm_ctx* c, hipEvent_t e[4]) {
+    for (int q = 0; q < 4; ++q) e[q] = nullptr;
+    if (!c->timing) return LBM_OK;
+    for (int q = 0; q < 4; ++q) {
+        e[q] = next_event(c);
+        if (!e[q]) return fail(LBM_ERR_DEVICE, "kernel timing: event creation failed");
+    }
+    return LBM_OK;
+}
+
+// A full step of a batched context: every kernel runs once for all
+// instances (remap and conversions in groups of 64 instances).
+static int run_step_batched(lbm_ctx* c) {
+    const int p = c->parity;
+    const int n = c->n_inst;
+    const int storage = c->inst[0].cfg.storage;
+    std::vector<unsigned char> remapped(n, 0), integrate(n, 0);
+    for (int g = 0; g < n; g += 64) {
+        const int ng = std::min(64, n - g);
+        int bpb = 0, maxb = 0;
+        bool any = false;
+        for (int k = g; k < g + ng; ++k) {
+            InstHost& h = c->inst[k];
+            if (!h.need_remap) continue;
+            any = true;
+            bpb = std::max(bpb, h.remap_blocks);
+            maxb = std::max(maxb, h.dev.nbodies);
+            remapped[k] = 1;
+            h.need_remap = false;
+        }
+        if (any) launch_remap_batch(c->d_tab + g, ng, maxb, storage, p, bpb, c->stream);
+    }
+    hipEvent_t e[4];
+    int rc = timing_events(c, e);
+    if (rc) return rc;
+    launch_sweep_bulk_batch(BatchGrid{c->d_tab, c->d_bulk_off, n, c->bulk_total}, storage, c->tile_x, p, c->stream, e[0],
+                            e[1]);
+    launch_sweep_boundary_batch(BatchGrid{c->d_tab, c->d_bnd_off, n, c->bnd_total}, storage, p, c->stream, e[2], e[3]);
+    for (int g = 0; g < n; g += 64) {
+        const int ng = std::min(64, n - g);
+        unsigned long long rm = 0, im = 0;
+        for (int k = g; k < g + ng; ++k) {
+            InstHost& h = c->inst[k];
+            integrate[k] = h.any_free && h.cfg.host_body_update == 0;
+            if (remapped[k]) rm |= 1ull << (k - g);
+            if (integrate[k]) im |= 1ull << (k - g);
+        }
+        launch_convert_batch(c->d_tab + g, ng, storage, p, rm, im, c->stream);
+    }
+    for (int k = 0; k < n; ++k)
+        if (integrate[k]) c->inst[k].need_remap = true;  // the device moved free bodies
+    HIP_OK(hipGetLastError());
+    c->last_parity = p;
+    c->have_forces = true;
+    c->parity ^= 1;
+    for (int k = 0; k < n; ++k) {
+        InstHost& h = c->inst[k];
+        if (!h.any_free || h.cfg.host_body_update == 0) continue;
+        rc = couple_on_host(c, h, p);
+        if (rc) return rc;
+    }
+    return LBM_OK;
+}
+
 static int run_step(lbm_ctx* c, int mask) {
+    if (c->batched && mask == LBM_PHASE_ALL) return run_step_batched(c);
     const int p = c->parity;
     const bool advances = (mask & (LBM_PHASE_SWEEP | LBM_PHASE_CONVERT)) != 0;
     for (int k = 0; k < c->n_inst; ++k) {
@@ -478,13 +589,10 @@ static int run_step(lbm_ctx* c, int mask) {
             remapped = true;
         }
         if (mask & LBM_PHASE_SWEEP) {
-            hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
-            if (c->timing)
-                for (int q = 0; q < 4; ++q) {
-                    e[q] = next_event(c);
-                    if (!e[q]) return fail(LBM_ERR_DEVICE, "kernel timing: event creation failed");
-                }
-            launch_sweep_bulk(h.dev, p, c->stream, e[0], e[1]);
+            hipEvent_t e[4];
+            int rc = timing_events(c, e);
+            if (rc) return rc;
+            launch_sweep_bulk(h.dev, p, c->tile_x, c->stream, e[0], e[1]);
             launch_sweep_boundary(h.dev, p, c->stream, e[2], e[3]);
         } else if (mask & LBM_PHASE_CONVERT) {
             hipLaunchKernelGGL(k_copy_state, dim3((h.dev.N + 255) / 256), dim3(256), 0, c->stream, h.dev, p);

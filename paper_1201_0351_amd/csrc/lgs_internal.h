@@ -529,14 +529,39 @@ __device__ __forceinline__ float g_bcastf(float v, int src) { return __shfl(v, g
 // kernel launchers (implemented in the .hip files)
 // --------------------------------------------------------------------------
 void launch_init(const Inst& I, const lbm_config& c, hipStream_t s);
+// A batch: instance descriptors in device memory and, per instance, the
+// first workgroup of its share of a grid (off[0..n], each share a multiple
+// of 8 workgroups so that a workgroup's XCD is its index modulo 8 in the
+// share as in the whole grid).
+struct BatchGrid {
+    const Inst* tab;
+    const int* off;
+    int n;
+    int blocks;  // off[n]
+};
+
+// workgroups of one instance's bulk grid for a tile width (32, 64 or 128
+// cells along x, 256 / width rows), padded to a multiple of 8
+int bulk_blocks(const Inst& I, int tile_x);
+
 // e0 / e1: optional events recorded at the start / end of the kernel itself
-void launch_sweep_bulk(const Inst& I, int parity, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+void launch_sweep_bulk(const Inst& I, int parity, int tile_x, hipStream_t s, hipEvent_t e0 = nullptr,
+                       hipEvent_t e1 = nullptr);
 void launch_sweep_boundary(const Inst& I, int parity, hipStream_t s, hipEvent_t e0 = nullptr,
                            hipEvent_t e1 = nullptr);
+void launch_sweep_bulk_batch(const BatchGrid& G, int storage, int tile_x, int parity, hipStream_t s,
+                             hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+void launch_sweep_boundary_batch(const BatchGrid& G, int storage, int parity, hipStream_t s, hipEvent_t e0 = nullptr,
+                                 hipEvent_t e1 = nullptr);
 void launch_mark(const Inst& I, int parity, hipStream_t s);
 void launch_convert(const Inst& I, int parity, bool retire_moves, bool integrate, hipStream_t s);
 void launch_finish(const Inst& I, int parity, bool reduce, bool zero_other, bool retire_moves, hipStream_t s);
 void launch_remap(const Inst& I, int parity, int blocks_per_body, hipStream_t s);
+// batches of at most 64 instances (bit k of a mask belongs to instance k)
+void launch_remap_batch(const Inst* tab, int n, int max_bodies, int storage, int parity, int blocks_per_body,
+                        hipStream_t s);
+void launch_convert_batch(const Inst* tab, int n, int storage, int parity, unsigned long long retire_mask,
+                          unsigned long long integrate_mask, hipStream_t s);
 void launch_set_body(const Inst& I, int slot, const DevBody& b, hipStream_t s);
 void launch_mass_total(const Inst& I, int parity, hipStream_t s);
 void launch_contacts(const Inst& I, hipStream_t s);

@@ -423,6 +423,48 @@ def test_multi_instance_independent(lbm):
     compare_pop(L, o, 1e-5, inst=0, label="multi inst0")
 
 
+def test_batched_instances_match_single(lbm):
+    """A context of four instances steps all of them with one launch per
+    kernel (instance table, per-instance workgroup ranges).  Each instance
+    must advance as it does alone in its own context: held and free bodies,
+    device and host update, uneven sizes, FP32.  Populations and flags are
+    compared exactly for held bodies; free bodies to round-off."""
+    cfgs = [W.basin((48, 40, 36), 18.0, 0.6, 1e-5, seed=21, noise_amp=1e-4),
+            W.basin((64, 48, 40), 20.0, 0.55, 5e-6, seed=22, noise_amp=1e-4),
+            W.basin((40, 40, 32), 16.0, 0.7, 1e-5, seed=23, noise_amp=1e-4),
+            dict(W.basin((72, 36, 36), 18.0, 0.6, 1e-5, seed=24, noise_amp=1e-4), host_body_update=1)]
+    bodies = [W.box((12, 12, 6), (24, 20, 18), 15.0, 0.5),
+              dict(W.box((16, 16, 8), (32, 24, 20), 0.0, 0.5), fixed=0, dof=0x3F),
+              None,
+              dict(W.box((12, 8, 6), (36, 18, 18), 10.0, 0.7), fixed=0, dof=0x08)]
+    B = lbm.Lattice([dict(c, max_bodies=1) for c in cfgs])
+    singles = []
+    for k, (c, b) in enumerate(zip(cfgs, bodies)):
+        S = lbm.Lattice(dict(c, max_bodies=1))
+        if b is not None:
+            S.set_body(0, b)
+            B.set_body(0, b, inst=k)
+        singles.append(S)
+    say("batch of 4 vs single contexts, 60 steps")
+    B.step(60)
+    for S in singles:
+        S.step(60)
+    for k, S in enumerate(singles):
+        held = bodies[k] is None or bodies[k].get("fixed", 1) == 1
+        assert np.array_equal(B.flags(k), S.flags(0)), k
+        if held:
+            assert np.array_equal(B.pop(k), S.pop(0)), k
+        else:
+            np.testing.assert_allclose(B.pop(k), S.pop(0), rtol=0, atol=1e-9)
+            bb, bs = B.get_body(0, inst=k), S.get_body(0)
+            np.testing.assert_allclose(bb["pos"], bs["pos"], rtol=0, atol=1e-9)
+        if bodies[k] is not None:
+            Fb, Tb = B.body_forces(0, inst=k)
+            Fs, Ts = S.body_forces(0)
+            assert_force_close(Fb, Fs, 1e-9, atol=1e-15)
+            assert_force_close(Tb, Ts, 1e-9, atol=1e-15)
+
+
 def test_free_body_update_rejected_on_device(lbm):
     """A dense free box falling through gas (no liquid) toward the floor of a
     24^3 box, g 1e-4: about 77 steps in, the device update would put its
