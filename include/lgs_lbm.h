@@ -212,6 +212,25 @@ int32_t lbm_sync(lbm_ctx* ctx);
 int32_t lbm_enable_kernel_timing(lbm_ctx* ctx, int32_t enable);
 int32_t lbm_kernel_time(lbm_ctx* ctx, int32_t kernel, double* total_ms, int64_t* launches);
 
+/* Launch configuration of a context (not a quantity of the method).
+ * tile_x: width along x of the bulk-sweep tiles, 32, 64 or 128 cells
+ * (256 / tile_x rows).  batched: step all instances with one launch per
+ * kernel (all instances must share one storage type; no effect with one
+ * instance; the default for several instances of one storage type).
+ * use_graph: lbm_step replays pairs of full steps from a captured HIP graph
+ * when no instance updates free bodies on the host; the capture is redone
+ * when the step parity or the set of instances that remap changes.
+ * Synchronises.  Errors: LBM_ERR_INVALID for a bad width or mixed storage. */
+int32_t lbm_set_tuning(lbm_ctx* ctx, int32_t tile_x, int32_t batched, int32_t use_graph);
+int32_t lbm_get_tuning(lbm_ctx* ctx, int32_t* tile_x, int32_t* batched, int32_t* use_graph);
+
+/* Autotuner: times reps launches of the bulk sweep on the current state for
+ * every tile width and keeps the fastest.  The state does not change (the
+ * sweep writes the lattice the next step overwrites; the boundary-list count
+ * it appends to is reset).  Outputs (nullable): the chosen width and its
+ * average launch time in ms.  Synchronises.  reps: 1..64. */
+int32_t lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* tile_x, double* best_ms);
+
 /* Number of cells the last sweep of an instance handled in the boundary
  * kernel (synchronises). */
 int32_t lbm_boundary_cells(lbm_ctx* ctx, int32_t inst, int64_t* n);

@@ -170,6 +170,12 @@ struct lbm_ctx {
     int* d_bulk_off = nullptr;
     int* d_bnd_off = nullptr;
     int bulk_total = 0, bnd_total = 0;
+    // graph replay of two full steps (captured on a private stream)
+    bool use_graph = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int gparity = 0;
+    std::vector<unsigned char> gremap;  // need_remap of every instance at the start of the graph
 };
 
 // Workspace head of a context: the instance table and two offset arrays.
@@ -187,6 +193,11 @@ static hipEvent_t next_event(lbm_ctx* c) {
 }
 
 extern "C" {
+
+static void drop_graph(lbm_ctx* c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+}
 
 // Instance table and workgroup offsets of a batched context (synchronous;
 // called at creation and whenever a descriptor or the tile width changes).
@@ -312,6 +323,8 @@ int32_t lbm_destroy(lbm_ctx* c) {
     else (void)hipDeviceSynchronize();
     if (c->own_ws) (void)hipFree(c->ws);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
     return LBM_OK;
 }
@@ -393,6 +406,7 @@ int32_t lbm_set_body(lbm_ctx* c, int32_t inst, int32_t k, const lbm_body* b) {
         return fail(LBM_ERR_INVALID, "set_body: body index out of range (raise max_bodies)");
     rc = pull_bodies(c, h);
     if (rc) return rc;
+    drop_graph(c);
     const double n[3] = {(double)h.cfg.nx, (double)h.cfg.ny, (double)h.cfg.nz};
     const DevBody& old = h.bodies[k];
     const bool was_mapped = old.active && old.mapped;
@@ -621,14 +635,168 @@ static int run_step(lbm_ctx* c, int mask) {
     return LBM_OK;
 }
 
+// Two full steps can be replayed from a graph when no instance needs the
+// host between steps and the host-side state the launches depend on (parity
+// and which instances remap) repeats after two steps: free bodies remap
+// every step, held ones never after their first.
+static bool graph_replayable(lbm_ctx* c) {
+    if (!c->use_graph || c->timing) return false;
+    for (const InstHost& h : c->inst) {
+        if (h.any_free && h.cfg.host_body_update != 0) return false;
+        if (h.need_remap != (h.any_free && h.cfg.host_body_update == 0)) return false;
+    }
+    return true;
+}
+
+static int graph_two_steps(lbm_ctx* c) {
+    std::vector<unsigned char> rm(c->n_inst);
+    for (int k = 0; k < c->n_inst; ++k) rm[k] = c->inst[k].need_remap;
+    if (!c->gexec || c->gparity != c->parity || c->gremap != rm) {
+        drop_graph(c);
+        if (!c->cap_stream) HIP_OK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        // the two steps are launched into the capture; the host-side state
+        // advances as if they ran, and the graph launch below runs them
+        const int p0 = c->parity;
+        hipStream_t user = c->stream;
+        c->stream = c->cap_stream;
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+        int rc = e == hipSuccess ? run_step(c, LBM_PHASE_ALL) : LBM_OK;
+        if (e == hipSuccess && rc == LBM_OK) rc = run_step(c, LBM_PHASE_ALL);
+        hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(c->cap_stream, &g) : e;
+        c->stream = user;
+        if (e != hipSuccess || e2 != hipSuccess)
+            return fail(LBM_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+        if (rc) {
+            (void)hipGraphDestroy(g);
+            return rc;
+        }
+        e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            c->gexec = nullptr;
+            return fail(LBM_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+        }
+        c->gparity = p0;
+        c->gremap = rm;
+    } else {
+        // replay: the host-side state after two steps
+        c->last_parity = c->parity ^ 1;
+        c->have_forces = true;
+    }
+    HIP_OK(hipGraphLaunch(c->gexec, c->stream));
+    return LBM_OK;
+}
+
 int32_t lbm_step(lbm_ctx* c, int32_t nsteps) {
     if (!c) return fail(LBM_ERR_INVALID, "context is NULL");
     if (nsteps < 0) return fail(LBM_ERR_INVALID, "step: nsteps < 0");
-    for (int s = 0; s < nsteps; ++s) {
-        int rc = run_step(c, LBM_PHASE_ALL);
+    int s = 0;
+    while (s < nsteps) {
+        int rc;
+        if (nsteps - s >= 2 && graph_replayable(c)) {
+            rc = graph_two_steps(c);
+            s += 2;
+        } else {
+            rc = run_step(c, LBM_PHASE_ALL);
+            s += 1;
+        }
         if (rc) return rc;
     }
     return LBM_OK;
+}
+
+// zero the boundary-list count (and overflow flag) of the current parity
+__global__ void k_reset_bnd(Ctl* ctl, int parity) {
+    if (threadIdx.x == 0) {
+        ctl->cnt[parity].n_bnd = 0;
+        ctl->cnt[parity].overflow = 0;
+    }
+}
+
+int32_t lbm_set_tuning(lbm_ctx* c, int32_t tile_x, int32_t batched, int32_t use_graph) {
+    if (!c) return fail(LBM_ERR_INVALID, "context is NULL");
+    if (tile_x != 32 && tile_x != 64 && tile_x != 128) return fail(LBM_ERR_INVALID, "set_tuning: tile_x must be 32, 64 or 128");
+    if (batched) {
+        for (int k = 1; k < c->n_inst; ++k)
+            if (c->inst[k].cfg.storage != c->inst[0].cfg.storage)
+                return fail(LBM_ERR_INVALID, "set_tuning: a batch needs one storage type");
+    }
+    HIP_OK(hipStreamSynchronize(c->stream));
+    drop_graph(c);
+    c->tile_x = tile_x;
+    c->batched = batched != 0 && c->n_inst > 1;
+    c->use_graph = use_graph != 0;
+    return upload_batch(c);
+}
+
+int32_t lbm_get_tuning(lbm_ctx* c, int32_t* tile_x, int32_t* batched, int32_t* use_graph) {
+    if (!c) return fail(LBM_ERR_INVALID, "context is NULL");
+    if (tile_x) *tile_x = c->tile_x;
+    if (batched) *batched = c->batched ? 1 : 0;
+    if (use_graph) *use_graph = c->use_graph ? 1 : 0;
+    return LBM_OK;
+}
+
+int32_t lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* tile_x, double* best_ms) {
+    if (!c) return fail(LBM_ERR_INVALID, "context is NULL");
+    if (reps <= 0 || reps > 64) return fail(LBM_ERR_INVALID, "autotune: reps must be 1..64");
+    HIP_OK(hipStreamSynchronize(c->stream));
+    drop_graph(c);
+    const int p = c->parity;
+    const int cand[3] = {32, 64, 128};
+    int best = c->tile_x;
+    double best_t = 1e30;
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    int rc = LBM_OK;
+    // Each candidate sweeps the current state (reads parity p, writes the
+    // other lattice, which the next step overwrites); the boundary-list
+    // counts it appends to are reset after every launch.
+    auto reset = [&]() {
+        for (InstHost& h : c->inst) hipLaunchKernelGGL(k_reset_bnd, dim3(1), dim3(64), 0, c->stream, h.dev.ctl, p);
+    };
+    auto sweep = [&]() {
+        if (c->batched)
+            launch_sweep_bulk_batch(BatchGrid{c->d_tab, c->d_bulk_off, c->n_inst, c->bulk_total},
+                                    c->inst[0].cfg.storage, c->tile_x, p, c->stream);
+        else
+            for (InstHost& h : c->inst) launch_sweep_bulk(h.dev, p, c->tile_x, c->stream);
+    };
+    for (int t : cand) {
+        c->tile_x = t;
+        rc = upload_batch(c);
+        if (rc) break;
+        sweep();
+        reset();
+        float total = 0.f;
+        for (int r = 0; r < reps; ++r) {
+            if (hipEventRecord(e0, c->stream) != hipSuccess) break;
+            sweep();
+            if (hipEventRecord(e1, c->stream) != hipSuccess) break;
+            reset();
+            float ms = 0.f;
+            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) break;
+            total += ms;
+        }
+        if (hipGetLastError() != hipSuccess) {
+            rc = fail(LBM_ERR_DEVICE, "autotune: launch failed");
+            break;
+        }
+        const double avg = total / reps;
+        if (avg < best_t) {
+            best_t = avg;
+            best = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->tile_x = best;
+    if (rc == LBM_OK) rc = upload_batch(c);
+    if (rc == LBM_OK && tile_x) *tile_x = best;
+    if (rc == LBM_OK && best_ms) *best_ms = best_t;
+    return rc;
 }
 
 int32_t lbm_step_phases(lbm_ctx* c, int32_t mask) {

@@ -465,6 +465,66 @@ def test_batched_instances_match_single(lbm):
             assert_force_close(Tb, Ts, 1e-9, atol=1e-15)
 
 
+def _graph_pair(lbm):
+    cfgs = [W.basin((48, 40, 36), 18.0, 0.6, 1e-5, seed=31, noise_amp=1e-4),
+            W.basin((40, 48, 40), 20.0, 0.6, 1e-5, seed=32, noise_amp=1e-4)]
+    bodies = [W.box((12, 12, 6), (24, 20, 18), 15.0, 0.5), dict(W.box((12, 12, 6), (20, 24, 20), 0.0, 0.5),
+                                                               fixed=0, dof=0x3F)]
+    out = []
+    for _ in range(2):
+        L = lbm.Lattice([dict(c, max_bodies=1) for c in cfgs])
+        for k, b in enumerate(bodies):
+            L.set_body(0, b, inst=k)
+        out.append(L)
+    return out
+
+
+def test_graph_replay_matches_eager(lbm):
+    """Pairs of steps replayed from a captured HIP graph advance exactly like
+    eager steps: several replays with eager work of the program in between
+    (force reads, mass totals, odd step counts that end eagerly), every
+    replay compared with the eager context (held instance bit for bit, free
+    body to round-off)."""
+    G, E = _graph_pair(lbm)
+    G.set_tuning(use_graph=1)
+    say("graph replay vs eager, 2 instances")
+    for n in (2, 4, 5, 6, 3, 8):
+        G.step(n)
+        E.step(n)
+        G.body_forces(0, inst=0)
+        G.mass_total(inst=1)
+        assert np.array_equal(G.flags(0), E.flags(0)), n
+        assert np.array_equal(G.pop(0), E.pop(0)), n
+        assert np.array_equal(G.flags(1), E.flags(1)), n
+        np.testing.assert_allclose(G.pop(1), E.pop(1), rtol=0, atol=1e-9)
+        np.testing.assert_allclose(G.get_body(0, inst=1)["pos"], E.get_body(0, inst=1)["pos"], rtol=0, atol=1e-9)
+        Fg, _ = G.body_forces(0, inst=0)
+        Fe, _ = E.body_forces(0, inst=0)
+        assert_force_close(Fg, Fe, 1e-9, atol=1e-15)
+
+
+def test_autotune_keeps_state(lbm):
+    """The autotuner sweeps the current state for every tile width without
+    changing it: afterwards the context advances exactly like an untouched
+    one (held bodies, bit for bit)."""
+    cfgs = [W.basin((64, 40, 36), 18.0, 0.6, 1e-5, seed=41, noise_amp=1e-4),
+            W.basin((96, 32, 30), 15.0, 0.6, 1e-5, seed=42, noise_amp=1e-4)]
+    A = lbm.Lattice([dict(c, max_bodies=1) for c in cfgs])
+    B = lbm.Lattice([dict(c, max_bodies=1) for c in cfgs])
+    for L in (A, B):
+        L.set_body(0, W.box((12, 12, 6), (32, 20, 18), 12.0, 0.5), inst=0)
+        L.step(7)
+    tx, ms = A.autotune(reps=3)
+    say("autotune: tile %d, %.4f ms" % (tx, ms))
+    assert tx in (32, 64, 128) and ms > 0
+    assert A.get_tuning()["tile_x"] == tx
+    A.step(9)
+    B.step(9)
+    for k in range(2):
+        assert np.array_equal(A.pop(k), B.pop(k)), k
+        assert np.array_equal(A.flags(k), B.flags(k)), k
+
+
 def test_free_body_update_rejected_on_device(lbm):
     """A dense free box falling through gas (no liquid) toward the floor of a
     24^3 box, g 1e-4: about 77 steps in, the device update would put its
