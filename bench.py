@@ -154,6 +154,73 @@ def righting_moment(storage):
     return out
 
 
+def _timed(L, steps, warmup):
+    import torch
+
+    L.step(max(1, warmup))
+    L.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L.step(steps)
+    L.sync()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def run_batch(storage, steps, warmup, batched=True, graph=False):
+    """48 heeled-box instances of uneven size (64^3 .. 160x128x128), held, in
+    one context: one launch per kernel for all of them (or one per instance
+    with batched=False)."""
+    from paper_1201_0351_amd import lbm
+    from paper_1201_0351_amd import workloads as W
+
+    w = W.config4(storage=storage)
+    insts = w["instances"]
+    L = lbm.Lattice([dict(i["lattice"], max_bodies=1) for i in insts])
+    for k, i in enumerate(insts):
+        L.set_body(0, i["bodies"][0], inst=k)
+    L.set_tuning(batched=int(batched), use_graph=int(graph))
+    L.step(2)
+    tile, tune_ms = L.autotune(4)
+    dt = _timed(L, steps, warmup)
+    cells = sum(L.ncells(k) for k in range(len(insts)))
+    L.close()
+    return dict(instances=len(insts), cells=cells, steps=steps, ms_per_step=round(1e3 * dt / steps, 4),
+                aggregate_mlups=round(cells * steps / dt / 1e6, 1),
+                instance_steps_per_s=round(len(insts) * steps / dt, 1),
+                instances_per_s=round(len(insts) / (w["steps"] * dt / steps), 3),
+                note="instances_per_s: the %d-step heel sweep of all instances per second" % w["steps"],
+                batched=batched, graph=graph, autotuned_tile_x=tile)
+
+
+def run_single(workload, steps, warmup, free=False):
+    from paper_1201_0351_amd import lbm
+
+    L = lbm.Lattice(dict(workload["lattice"], max_bodies=1))
+    b = dict(workload["bodies"][0])
+    if free:
+        b.update(fixed=0, dof=workload["dof"])
+    L.set_body(0, b)
+    dt = _timed(L, steps, warmup)
+    n = L.ncells()
+    L.close()
+    return dict(cells=n, steps=steps, ms_per_step=round(1e3 * dt / steps, 4), mlups=round(n * steps / dt / 1e6, 1))
+
+
+def other_configs(steps, warmup):
+    from paper_1201_0351_amd import workloads as W
+
+    out = {}
+    out["batch48_heel_sweep"] = {st: run_batch(st, steps, warmup) for st in ("fp32", "fp16")}
+    out["batch48_heel_sweep"]["fp32_one_launch_per_instance"] = run_batch("fp32", steps, warmup, batched=False)
+    out["batch48_heel_sweep"]["fp32_graph"] = run_batch("fp32", steps, warmup, graph=True)
+    out["basin256x192x192_box64x64x32_heel20_held"] = {st: run_single(W.config3(20.0, st), steps, warmup)
+                                                      for st in ("fp32", "fp16", "bf16")}
+    out["channel512x256x256_box48x24x24_free"] = {st: run_single(W.config5(st), steps, warmup, free=True)
+                                                  for st in ("fp32", "fp16")}
+    return out
+
+
 def cpu_baseline(target_s=15.0):
     """The FP64 oracle on the host cores: the same workload (128^3, box held at
     20 deg), timed over as many steps as fit in about target_s seconds."""
@@ -275,6 +342,8 @@ def main():
             out["righting_moment"] = dict(rm, reference="FP64 oracle, held box, tests/golden/righting_moment_128.json",
                                           max_rel_err={k: round(max(x["rel_err"] for x in v), 5)
                                                        for k, v in rm.items()})
+        out["other_configs"] = other_configs(max(50, args.steps // 10), 20)
+        print("other configs done", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -95,8 +95,8 @@ __global__ __launch_bounds__(256) void k_init(Inst I, InitParams P) {
             }
         }
     }
-    S* p0 = (S*)I.pop[0];
-    S* p1 = (S*)I.pop[1];
+    S* p0 = (S*)pop_of(I, 0);
+    S* p1 = (S*)pop_of(I, 1);
     I.flags[id] = (uint8_t)t;
     if (t == GAS) {
         for (int i = 0; i < Q; ++i) {
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(256) void k_init(Inst I, InitParams P) {
             Store<S>::st(p1, (size_t)i * I.ps + id, 0.f, I.scale);
         }
         I.m_hi[id] = I.m_lo[id] = 0.f;
-        I.phi[0][id] = I.phi[1][id] = 0.f;
+        phi_of(I, 0)[id] = phi_of(I, 1)[id] = 0.f;
         return;
     }
     const double zc = z + 0.5;
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void k_init(Inst I, InitParams P) {
     split_mass(ph * rho, hi, lo);
     I.m_hi[id] = hi;
     I.m_lo[id] = lo;
-    I.phi[0][id] = I.phi[1][id] = (float)ph;
+    phi_of(I, 0)[id] = phi_of(I, 1)[id] = (float)ph;
 }
 
 void launch_init(const Inst& I, const lbm_config& c, hipStream_t s) {
@@ -173,7 +173,7 @@ __device__ __forceinline__ void remap_eval_cell(const Inst& I, int parity, const
     if ((fl & TYPE_MASK) == OBS) {
         const int owner = (fl >> 2) & 15;
         if (!inside_body(I, I.bodies[owner], x, y, z) && body_at(I, x, y, z) < 0) {
-            const S* pop = (const S*)I.pop[parity];
+            const S* pop = (const S*)pop_of(I, parity);
             int nL = 0, nG = 0, nI = 0;
             float rs = 0.f, ps = 0.f;
             for (int i = 1; i < Q; ++i) {
@@ -192,7 +192,7 @@ __device__ __forceinline__ void remap_eval_cell(const Inst& I, int parity, const
                         ++nL;
                     } else {
                         ++nI;
-                        ps += I.phi[parity][nb];
+                        ps += phi_of(I, parity)[nb];
                     }
                 }
             }
@@ -220,7 +220,7 @@ __device__ __forceinline__ void remap_commit_cell(const Inst& I, int parity, int
     const int id = x + I.nx * (y + I.ny * z);
     const uint8_t fl = I.flags[id];
     const int t = fl & TYPE_MASK;
-    S* pop = (S*)I.pop[parity];
+    S* pop = (S*)pop_of(I, parity);
     if (t != OBS) {
         if (!inside_body(I, B, x, y, z)) return;
         double lost = 0.0;
@@ -229,7 +229,7 @@ __device__ __forceinline__ void remap_commit_cell(const Inst& I, int parity, int
         if (lost != 0.0) atomicAdd(&I.ctl->ledger, -lost);
         I.flags[id] = (uint8_t)(OBS | (k << 2));
         I.m_hi[id] = I.m_lo[id] = 0.f;
-        I.phi[parity][id] = 0.f;
+        phi_of(I, parity)[id] = 0.f;
         return;
     }
     if (((fl >> 2) & 15) != k) return;
@@ -247,7 +247,7 @@ __device__ __forceinline__ void remap_commit_cell(const Inst& I, int parity, int
     if (r == 1) {
         I.flags[id] = GAS;
         I.m_hi[id] = I.m_lo[id] = 0.f;
-        I.phi[parity][id] = 0.f;
+        phi_of(I, parity)[id] = 0.f;
         return;
     }
     // velocity of the closest point of the body surface
@@ -276,13 +276,13 @@ __device__ __forceinline__ void remap_commit_cell(const Inst& I, int parity, int
         hi = 1.f;
         lo = (float)drb;
         m = rho;
-        I.phi[parity][id] = 1.f;
+        phi_of(I, parity)[id] = 1.f;
     } else {
         const double ph = (double)I.aux[id];
         I.flags[id] = IFC;
         m = ph * rho;
         split_mass(m, hi, lo);
-        I.phi[parity][id] = (float)ph;
+        phi_of(I, parity)[id] = (float)ph;
     }
     I.m_hi[id] = hi;
     I.m_lo[id] = lo;
@@ -382,7 +382,7 @@ template <typename S>
 __global__ __launch_bounds__(256) void k_mass(Inst I, int parity) {
     __shared__ double red[256];
     double acc = 0.0;
-    const S* pop = (const S*)I.pop[parity];
+    const S* pop = (const S*)pop_of(I, parity);
     for (int id = blockIdx.x * 256 + threadIdx.x; id < I.N; id += gridDim.x * 256) {
         const int t = I.flags[id] & TYPE_MASK;
         if (t == LIQ) acc += 1.0 + (double)cell_drho<S>(I, pop, id);

@@ -157,8 +157,8 @@ template <typename S>
 __device__ __forceinline__ void phase_claim(const Inst& I, int parity, int g0, int ngroups) {
     StepCounters& C = I.ctl->cnt[parity];
     const int n = min(load_count(&C.n_cand), I.list_cap);
-    S* pop = (S*)I.pop[parity ^ 1];
-    float* phi = I.phi[parity ^ 1];
+    S* pop = (S*)pop_of(I, parity ^ 1);
+    float* phi = phi_of(I, parity ^ 1);
     const int i = g_lane();
     for (int k = g0; k < n; k += ngroups) {
         const int id = I.cand[k];
@@ -196,8 +196,8 @@ template <typename S>
 __device__ __forceinline__ void phase_newgas(const Inst& I, int parity) {
     StepCounters& C = I.ctl->cnt[parity];
     const int n = min(load_count(&C.n_newg), I.list_cap);
-    S* pop = (S*)I.pop[parity ^ 1];
-    float* phi = I.phi[parity ^ 1];
+    S* pop = (S*)pop_of(I, parity ^ 1);
+    float* phi = phi_of(I, parity ^ 1);
     const int j = g_lane();
     const int grp = threadIdx.x >> 5, ngrp = blockDim.x >> 5;
     for (int k = grp; k < n; k += ngrp) {
@@ -276,8 +276,8 @@ __device__ __forceinline__ void phase_commit(const Inst& I, int parity) {
     StepCounters& C = I.ctl->cnt[parity];
     const int nc = min(load_count(&C.n_cand), I.list_cap), ng = min(load_count(&C.n_newg), I.list_cap);
     const int nl = min(load_count(&C.n_newl), I.list_cap), nr = min(load_count(&C.n_recv), I.list_cap);
-    S* pop = (S*)I.pop[parity ^ 1];
-    float* phi = I.phi[parity ^ 1];
+    S* pop = (S*)pop_of(I, parity ^ 1);
+    float* phi = phi_of(I, parity ^ 1);
     // single-thread items
     BLOCK_LOOP(k, nc + ng + nl) {
         if (k < nc) {

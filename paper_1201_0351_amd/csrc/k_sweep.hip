@@ -213,8 +213,8 @@ __device__ __forceinline__ void sweep_bulk(const Inst& I, int parity, int b, int
     const int x = tx * TX + (threadIdx.x % TX);
     const int y = ty * TY + (threadIdx.x / TX);
 
-    const S* __restrict__ src = (const S*)I.pop[parity];
-    S* __restrict__ dst = (S*)I.pop[parity ^ 1];
+    const S* __restrict__ src = (const S*)pop_of(I, parity);
+    S* __restrict__ dst = (S*)pop_of(I, parity ^ 1);
     StepCounters& C = I.ctl->cnt[parity];
 
     const bool inb = (x < I.nx) && (y < I.ny);
@@ -278,13 +278,13 @@ __device__ __forceinline__ float osum(float v) {
 // force-record slot).
 template <typename S>
 __device__ __forceinline__ void sweep_boundary(const Inst& I, int parity, int wg, int nwg) {
-    const S* __restrict__ src = (const S*)I.pop[parity];
-    S* __restrict__ dst = (S*)I.pop[parity ^ 1];
+    const S* __restrict__ src = (const S*)pop_of(I, parity);
+    S* __restrict__ dst = (S*)pop_of(I, parity ^ 1);
     const float isc = I.inv_scale;
     StepCounters& C = I.ctl->cnt[parity];
     const int nlist = min(C.n_bnd, I.list_cap);
     const bool px = I.periodic & 1, py = I.periodic & 2, pz = I.periodic & 4;
-    const float* __restrict__ phi_t = I.phi[parity];
+    const float* __restrict__ phi_t = phi_of(I, parity);
     const int l = threadIdx.x & (BL - 1);
     const int cell = threadIdx.x / BL;
     // this lane's momentum-exchange partial sum (first body it meets)
@@ -506,7 +506,7 @@ __device__ __forceinline__ void sweep_boundary(const Inst& I, int parity, int wg
             else if (phd <= -I.eps) mark = MARK_EMPTY;
             I.m_hi[id] = mhi;
             I.m_lo[id] = mlo;
-            I.phi[parity ^ 1][id] = ph;
+            phi_of(I, parity ^ 1)[id] = ph;
             if (mark) {
                 I.flags[id] = (fl & KEEP_MASK) | mark;
                 const int p = atomicAdd(&C.n_cand, 1);
@@ -702,7 +702,7 @@ __global__ __launch_bounds__(256) void k_mark(Inst I, int parity) {
         const uint8_t fl = I.flags[id];
         uint8_t mark = 0;
         if ((fl & TYPE_MASK) == IFC) {
-            const double ph = (double)I.phi[parity ^ 1][id];
+            const double ph = (double)phi_of(I, parity ^ 1)[id];
             if (ph >= 1.0 + I.eps) mark = MARK_FILL;
             else if (ph <= -I.eps) mark = MARK_EMPTY;
         }

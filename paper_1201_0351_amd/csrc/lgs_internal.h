@@ -150,6 +150,12 @@ struct Inst {
     DevBody* bodies;
 };
 
+// Lattice of a parity by selection, not by indexing: a descriptor copied into
+// a kernel's registers stays there (a run-time index into its arrays would
+// move it to scratch memory).
+__device__ __forceinline__ void* pop_of(const Inst& I, int p) { return p ? I.pop[1] : I.pop[0]; }
+__device__ __forceinline__ float* phi_of(const Inst& I, int p) { return p ? I.phi[1] : I.phi[0]; }
+
 // --------------------------------------------------------------------------
 // storage types
 // --------------------------------------------------------------------------
