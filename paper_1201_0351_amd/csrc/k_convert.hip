@@ -9,9 +9,11 @@
 // Each phase is a function of the state before it, so the result does not
 // depend on the order of the (atomically appended) lists:
 //   forces  the boundary sweep's per-workgroup momentum-exchange records are
-//           summed per body in slot order (fixed-order FP64 reduction)
-//   bodies  (last wavefront, beside claim) retire the step's body moves; free
-//           bodies take the rigid-body update from the reduced force/torque
+//           summed per body in slot order (fixed-order FP64 reduction); the
+//           records are loaded before the claims and summed after them
+//   bodies  (last wavefront, beside new-gas) retire the step's body moves;
+//           free bodies take the rigid-body update from the reduced force
+//           and torque
 //   claim   per candidate: a filled cell (phi >= 1+eps) records its excess
 //           m - rho and claims its gas neighbours as new interface cells; an
 //           emptied cell (phi <= -eps) touching a filled one stays interface
@@ -193,14 +195,13 @@ __device__ __forceinline__ void phase_claim(const Inst& I, int parity, int g0, i
 // velocity of their liquid / interface neighbours that are not emptying
 // (one group per new cell, lane j looks at neighbour j); m = 0.
 template <typename S>
-__device__ __forceinline__ void phase_newgas(const Inst& I, int parity) {
+__device__ __forceinline__ void phase_newgas(const Inst& I, int parity, int g0, int ngroups) {
     StepCounters& C = I.ctl->cnt[parity];
     const int n = min(load_count(&C.n_newg), I.list_cap);
     S* pop = (S*)pop_of(I, parity ^ 1);
     float* phi = phi_of(I, parity ^ 1);
     const int j = g_lane();
-    const int grp = threadIdx.x >> 5, ngrp = blockDim.x >> 5;
-    for (int k = grp; k < n; k += ngrp) {
+    for (int k = g0; k < n; k += ngroups) {
         const int g = I.newg[k];
         int gx, gy, gz;
         cell_coords(I, g, gx, gy, gz);
@@ -339,52 +340,71 @@ __device__ __forceinline__ double wave_sum_d(double v) {
     return v;
 }
 
-// Fixed-order FP64 sum of the boundary sweep's force records, per body.
-// Every thread loads its records (slots tid + j * CONV_THREADS) with
-// independent loads, sums them in slot order, then wavefront butterflies and
-// the wavefronts' partials in wavefront order.
-__device__ __forceinline__ void phase_forces(const Inst& I, int parity) {
-    constexpr int PER = BND_BLOCKS_MAX / CONV_THREADS;
-    constexpr int NW = CONV_THREADS / 64;
-    static_assert(PER * CONV_THREADS == BND_BLOCKS_MAX, "force records per thread");
-    __shared__ double part[NW][6];
-    StepCounters& C = I.ctl->cnt[parity];
-    const int nrec = boundary_blocks(I);
+// Fixed-order FP64 sum of the boundary sweep's force records, per body, in
+// three parts so that its memory round trip overlaps the claim phase:
+//   load     every thread loads its records (slots tid + j * CONV_THREADS)
+//            and threads t < 6 nbodies the accumulator entry they finish
+//   partial  per body: the thread's records in slot order, wavefront
+//            butterflies, one partial per wavefront in LDS
+//   final    (after a barrier) acc = loaded entry + partials in wavefront order
+struct ForceLoad {
+    static constexpr int PER = BND_BLOCKS_MAX / CONV_THREADS;
     int rb[PER];
     double rv[PER][6];
+    double acc0;
+};
+static_assert(ForceLoad::PER * CONV_THREADS == BND_BLOCKS_MAX, "force records per thread");
+constexpr int CONV_WAVES = CONV_THREADS / 64;
+
+__device__ __forceinline__ void forces_load(const Inst& I, int parity, ForceLoad& F) {
+    const int nrec = boundary_blocks(I);
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
+    for (int j = 0; j < ForceLoad::PER; ++j) {
         const int k = threadIdx.x + j * CONV_THREADS;
-        rb[j] = k < nrec ? I.frec_body[k] : -1;
-    }
-    // values loaded without waiting for the body ids: one round trip
+        F.rb[j] = k < nrec ? I.frec_body[k] : -1;
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        const int k = threadIdx.x + j * CONV_THREADS;
-#pragma unroll
-        for (int q = 0; q < 6; ++q) rv[j][q] = k < nrec ? I.frec_v[q * BND_BLOCKS_MAX + k] : 0.0;
+        for (int q = 0; q < 6; ++q) F.rv[j][q] = k < nrec ? I.frec_v[q * BND_BLOCKS_MAX + k] : 0.0;
     }
+    const int t = threadIdx.x;
+    F.acc0 = t < 6 * I.nbodies ? I.ctl->cnt[parity].acc[t / 6][t % 6] : 0.0;
+}
+
+__device__ __forceinline__ void forces_partial(const Inst& I, const ForceLoad& F, double (*part)[MAXB][6]) {
     for (int b = 0; b < I.nbodies; ++b) {
         double v[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
-        for (int j = 0; j < PER; ++j)
-            if (rb[j] == b)
+        for (int j = 0; j < ForceLoad::PER; ++j)
+            if (F.rb[j] == b)
 #pragma unroll
-                for (int q = 0; q < 6; ++q) v[q] += rv[j][q];
+                for (int q = 0; q < 6; ++q) v[q] += F.rv[j][q];
 #pragma unroll
         for (int q = 0; q < 6; ++q) v[q] = wave_sum_d(v[q]);
         if ((threadIdx.x & 63) == 0)
 #pragma unroll
-            for (int q = 0; q < 6; ++q) part[threadIdx.x >> 6][q] = v[q];
-        __syncthreads();
-        if (threadIdx.x < 6) {
-            double t = 0.0;
-#pragma unroll
-            for (int w = 0; w < NW; ++w) t += part[w][threadIdx.x];
-            C.acc[b][threadIdx.x] += t;
-        }
-        __syncthreads();
+            for (int q = 0; q < 6; ++q) part[threadIdx.x >> 6][b][q] = v[q];
     }
+}
+
+__device__ __forceinline__ void forces_final(const Inst& I, int parity, const ForceLoad& F,
+                                             const double (*part)[MAXB][6]) {
+    const int t = threadIdx.x;
+    if (t < 6 * I.nbodies) {
+        double s = F.acc0;
+#pragma unroll
+        for (int w = 0; w < CONV_WAVES; ++w) s += part[w][t / 6][t % 6];
+        I.ctl->cnt[parity].acc[t / 6][t % 6] = s;
+    }
+}
+
+// the whole sum at once (phase-isolated calls)
+__device__ __forceinline__ void phase_forces(const Inst& I, int parity) {
+    __shared__ double part[CONV_WAVES][MAXB][6];
+    ForceLoad F;
+    forces_load(I, parity, F);
+    forces_partial(I, F, part);
+    __syncthreads();
+    forces_final(I, parity, F, part);
+    __syncthreads();
 }
 
 // clear the other parity's counters
@@ -494,13 +514,23 @@ __device__ __forceinline__ void bodies_wave(const Inst& I, int parity, bool reti
 
 // One step's conversions.  The last wavefront updates the bodies while the
 // others claim; the later phases use all groups.
+// The force records are loaded first and reduced after the claims, so their
+// round trip overlaps the claim phase; the body update (last wavefront)
+// overlaps the new-gas phase (the other wavefronts).
 template <typename S>
 __device__ __forceinline__ void convert(const Inst& I, int parity, bool retire_moves, bool integrate) {
-    phase_forces(I, parity);
-    if ((int)(threadIdx.x >> 6) == CONV_THREADS / 64 - 1) bodies_wave(I, parity, retire_moves, integrate);
-    else phase_claim<S>(I, parity, threadIdx.x >> 5, CONV_THREADS / 32 - 2);
+    __shared__ double part[CONV_WAVES][MAXB][6];
+    const bool last = (int)(threadIdx.x >> 6) == CONV_WAVES - 1;
+    constexpr int WORK_GROUPS = CONV_THREADS / 32 - 2;  // the 32-lane groups of all but the last wavefront
+    ForceLoad F;
+    forces_load(I, parity, F);
+    if (!last) phase_claim<S>(I, parity, threadIdx.x >> 5, WORK_GROUPS);
+    forces_partial(I, F, part);
     __syncthreads();
-    phase_newgas<S>(I, parity);
+    forces_final(I, parity, F, part);
+    __syncthreads();
+    if (last) bodies_wave(I, parity, retire_moves, integrate);
+    else phase_newgas<S>(I, parity, threadIdx.x >> 5, WORK_GROUPS);
     __syncthreads();
     phase_share(I, parity);
     __syncthreads();

@@ -525,6 +525,33 @@ def test_autotune_keeps_state(lbm):
         assert np.array_equal(A.flags(k), B.flags(k)), k
 
 
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+def test_righting_moment_vs_oracle(lbm, storage):
+    """The benchmark box held at 10, 20 and 30 deg on the 128^3 basin: the
+    righting moment -T_x averaged over the last 1000 of 5000 steps (every 10
+    steps) agrees with the FP64 oracle's (tests/golden/righting_moment_128.json)
+    within 1%, in FP32 and in FP16 deviation storage."""
+    import json
+
+    with open(os.path.join(os.path.dirname(__file__), "golden", "righting_moment_128.json")) as f:
+        gold = json.load(f)
+    for run in gold["runs"]:
+        w = W.config2(run["heel_deg"], released=False, storage=storage)
+        L = lbm.Lattice(dict(w["lattice"], max_bodies=1))
+        L.set_body(0, w["bodies"][0])
+        done, samples = 0, []
+        while done < run["steps"]:
+            L.step(run["every"])
+            done += run["every"]
+            if done > run["steps"] - run["window"]:
+                samples.append(-L.body_forces(0)[1][0])
+        L.close()
+        ms = float(np.mean(samples))
+        err = abs(ms - run["m_s"]) / abs(run["m_s"])
+        say("  %s heel %g: m_s %.6e oracle %.6e rel err %.2e" % (storage, run["heel_deg"], ms, run["m_s"], err))
+        assert err <= 1e-2
+
+
 def test_free_body_update_rejected_on_device(lbm):
     """A dense free box falling through gas (no liquid) toward the floor of a
     24^3 box, g 1e-4: about 77 steps in, the device update would put its
