@@ -120,19 +120,22 @@ def wall_sided_limit(b, h, rho_s=0.5):
     return math.atan(min(2 * d, 2 * (h - d)) / b)
 
 
-def stable_heel_angles(b, h, rho_s, n=180):
-    """Heel angles in [0, 90) degrees at which a free-floating b x h section of
-    density rho_s is in stable rotational equilibrium (m_s changes sign from
-    negative to positive with increasing alpha)."""
+def stable_heel_angles(b, h, rho_s, n=180, zw=None):
+    """Heel angles in [0, 90) degrees at which a b x h section of density
+    rho_s is in stable rotational equilibrium (m_s changes sign from negative
+    to positive with increasing alpha).  zw=None: free floating (the water
+    plane moves so that buoyancy balances the weight at every heel); a number:
+    the centre of gravity is held at that depth below the water plane (the box
+    may only turn about its long axis)."""
     al = np.linspace(0.0, math.pi / 2, n + 1)
-    ms = np.array([righting_moment_polygon(b, h, 1.0, a, 1.0, rho_s) for a in al])
+    ms = np.array([righting_moment_polygon(b, h, 1.0, a, 1.0, rho_s, zw=zw) for a in al])
     out = []
     for k in range(n):
         if ms[k] <= 0.0 < ms[k + 1] or (ms[k] < 0.0 <= ms[k + 1]):
             lo, hi = al[k], al[k + 1]
             for _ in range(50):
                 mid = 0.5 * (lo + hi)
-                if righting_moment_polygon(b, h, 1.0, mid, 1.0, rho_s) < 0.0:
+                if righting_moment_polygon(b, h, 1.0, mid, 1.0, rho_s, zw=zw) < 0.0:
                     lo = mid
                 else:
                     hi = mid

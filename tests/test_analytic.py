@@ -73,3 +73,38 @@ def test_integrator_dof_mask_roll_only():
     M = 0.5 * 8 * 16 * 16 * 8
     # roll about the world x axis: I_xx of the body rotated about x is its body I_xx
     assert nb["omega"][0] == pytest.approx(0.5 / (M / 3 * (16 ** 2 + 8 ** 2)), rel=1e-12)
+
+
+@pytest.mark.parametrize("zw", [-4.0, 0.0, 4.0, 4.5])
+@pytest.mark.parametrize("alpha_deg", [5.0, 20.7, 40.0])
+def test_offset_waterline_moment_matches_grid_integral(zw, alpha_deg):
+    """Brute force: the immersed area and buoyancy lever of a heeled 16 x 16
+    section with the water plane zw above G, summed over a fine grid of
+    sample points, agree with the clipped-polygon moment."""
+    n, b, h, g = 1000, 16.0, 16.0, 7.5e-4
+    a = math.radians(alpha_deg)
+    u = (np.arange(n) + 0.5) / n
+    yb, zb = np.meshgrid((u - 0.5) * b, (u - 0.5) * h, indexing="ij")
+    y = yb * math.cos(a) - zb * math.sin(a)
+    z = yb * math.sin(a) + zb * math.cos(a)
+    wet = z <= zw
+    area = wet.sum() * (b / n) * (h / n)
+    cy = y[wet].mean()
+    brute = -g * area * 32.0 * cy
+    exact = A.righting_moment_polygon(b, h, 32.0, a, g, zw=zw)
+    assert exact == pytest.approx(brute, rel=2e-3, abs=2e-3 * g * b * h * 32.0 * 0.05)
+
+
+def test_fixed_centre_stable_heel_of_cubes():
+    """A cube held at its upright equilibrium draft and free to turn only
+    about its long axis: 45 deg at density 1/2 (the half-immersed square is
+    symmetric about its diagonal), the same angle for densities 1/4 and 3/4
+    (the wet part of one is the point reflection of the dry part of the
+    other through G), and that angle lies below the free-floating 26.565 deg."""
+    s = 16.0
+    half = A.stable_heel_angles(s, s, 0.5, zw=0.5 * s - s / 2)
+    assert min(abs(x - 45.0) for x in half) < 1e-3
+    lo = A.stable_heel_angles(s, s, 0.25, zw=0.25 * s - s / 2)
+    hi = A.stable_heel_angles(s, s, 0.75, zw=0.75 * s - s / 2)
+    assert lo[0] == pytest.approx(hi[0], abs=1e-6)
+    assert 15.0 < lo[0] < 26.0

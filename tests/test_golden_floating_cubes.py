@@ -1,0 +1,68 @@
+"""The oracle's floating-cubes trajectory (tests/golden/
+floating_cubes_130x40x40.json, written by make_floating_cubes.py, which
+calls only the oracle) checked against what Archimedes and the cell mapping
+fix (Sec. 4, equilibrium of floating cubes).
+
+Each box of density rho_s and side s must float with a draft of rho_s s
+below the undisturbed surface z = H.  Its mapped volume changes by a whole
+row of cells when the bottom face crosses a row of cell centres (z = k + 1/2),
+so heave comes to rest with the bottom face on the row of centres next to
+the continuous draft (H - rho_s s lies on a cell boundary for these
+densities: both neighbouring rows are candidates).
+
+Mass: the moving-wall bounce-back (Eq. noslip) returns 6 w_i rho c_i.u_w
+with every link into a body, so a body translating by dz moves mass across
+its faces.  For vertical motion only the links with c_z != 0 count: each cell
+under the bottom face has links with sum(w_i c_z) = 1/6, and each cell along
+the bottom edge one diagonal of weight 1/36, so the fluid loses
+rho (A + P/6) dz, with A the footprint, P its perimeter and rho the
+hydrostatic density at the bottom face.  The ledger records only cells that
+are covered or uncovered, so liquid mass minus ledger changes by that
+amount (rotation sweeps as much volume in as out)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+PATH = os.path.join(os.path.dirname(__file__), "golden", "floating_cubes_130x40x40.json")
+
+
+def _gold():
+    with open(PATH) as f:
+        return json.load(f)
+
+
+def test_golden_file_complete():
+    g = _gold()
+    assert (g["nx"], g["ny"], g["nz"], g["side"]) == (130, 40, 40, 16)
+    assert g["densities"] == [0.75, 0.5, 0.25] and g["heel0_deg"] == 2.86
+    r = g["heave_roll"]
+    assert r["dof"] == 0x0C and r["every"] == 250 and r["steps"] == 3000
+    steps = [row[0] for row in r["trace"]]
+    assert steps == list(range(250, 3001, 250))
+
+
+def test_golden_drafts_match_archimedes():
+    g = _gold()
+    H, s = g["fill_height"], g["side"]
+    last = np.array(g["heave_roll"]["trace"][-1])
+    for k, rs in enumerate(g["densities"]):
+        bottom = last[2 + 2 * k] - s / 2
+        continuous = H - rs * s
+        assert abs(bottom - continuous) <= 0.5 + 0.01, (rs, bottom, continuous)
+        assert abs((bottom - 0.5) - round(bottom - 0.5)) <= 0.01, (rs, bottom)  # on a row of cell centres
+
+
+def test_golden_mass_balance_of_moving_walls():
+    g = _gold()
+    H, s, grav = g["fill_height"], g["side"], g["g"]
+    last = g["heave_roll"]["trace"][-1]
+    area, perim = 2 * s * s, 2 * (2 * s + s)
+    want = 0.0
+    for k, rs in enumerate(g["densities"]):
+        z0 = H + s / 2 - rs * s
+        rho = 1.0 + 3.0 * grav * (H - (z0 - s / 2))
+        want -= rho * (area + perim / 6.0) * (last[2 + 2 * k] - z0)
+    m0, m1 = g["heave_roll"]["mass_minus_ledger"]
+    assert m1 - m0 == pytest.approx(want, rel=0.015)
