@@ -386,25 +386,37 @@ __device__ __forceinline__ void forces_partial(const Inst& I, const ForceLoad& F
 }
 
 __device__ __forceinline__ void forces_final(const Inst& I, int parity, const ForceLoad& F,
-                                             const double (*part)[MAXB][6]) {
+                                             const double (*part)[MAXB][6], double (*sacc)[6]) {
     const int t = threadIdx.x;
     if (t < 6 * I.nbodies) {
         double s = F.acc0;
 #pragma unroll
         for (int w = 0; w < CONV_WAVES; ++w) s += part[w][t / 6][t % 6];
         I.ctl->cnt[parity].acc[t / 6][t % 6] = s;
+        sacc[t / 6][t % 6] = s;  // the body update reads it from here
     }
 }
 
 // the whole sum at once (phase-isolated calls)
-__device__ __forceinline__ void phase_forces(const Inst& I, int parity) {
+__device__ __forceinline__ void phase_forces(const Inst& I, int parity, double (*sacc)[6]) {
     __shared__ double part[CONV_WAVES][MAXB][6];
     ForceLoad F;
     forces_load(I, parity, F);
     forces_partial(I, F, part);
     __syncthreads();
-    forces_final(I, parity, F, part);
+    forces_final(I, parity, F, part, sacc);
     __syncthreads();
+}
+
+// Copy of the body records in LDS, written by one wavefront (32-bit words),
+// so that the body update does not wait on global memory after the force
+// reduction.
+__device__ __forceinline__ void stage_bodies(const Inst& I, DevBody* sb) {
+    static_assert(sizeof(DevBody) % 4 == 0, "body record in 32-bit words");
+    const int nw = I.nbodies * (int)(sizeof(DevBody) / 4);
+    const uint32_t* src = (const uint32_t*)I.bodies;
+    uint32_t* dst = (uint32_t*)sb;
+    for (int w = threadIdx.x & 63; w < nw; w += 64) dst[w] = src[w];
 }
 
 // clear the other parity's counters
@@ -425,45 +437,55 @@ __device__ __forceinline__ void phase_finish(const Inst& I, int parity) {
 // the surface, jump a cell from the mapped pose or bring two bodies closer
 // than three cells is rejected: the body keeps its pose and Ctl::body_err
 // records why.
-__device__ __forceinline__ void bodies_wave(const Inst& I, int parity, bool retire_moves, bool integrate) {
+// The inputs come from the LDS copies of the body records (sb, staged at the
+// kernel's start) and of the reduced force and torque (sacc); the results go
+// to the records in global memory.
+__device__ __forceinline__ void bodies_wave(const Inst& I, bool retire_moves, bool integrate, const DevBody* sb,
+                                            const double (*sacc)[6]) {
     const int b = threadIdx.x & 63;
     const bool mine = b < I.nbodies;
     double pos[3] = {0, 0, 0}, quat[4] = {1, 0, 0, 0}, vel[3] = {0, 0, 0}, om[3] = {0, 0, 0}, ext[3] = {0, 0, 0};
     double R[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
-    bool upd = false, act = false;
+    double prev[3] = {0, 0, 0};
+    bool upd = false, act = false, mapped = false;
     if (mine) {
+        const DevBody& S = sb[b];
         DevBody& B = I.bodies[b];
-        act = B.active != 0;
-        if (retire_moves && B.moved) {
+        act = S.active != 0;
+        mapped = S.mapped != 0;
+        for (int a = 0; a < 3; ++a) prev[a] = S.prev_pos[a];
+        if (retire_moves && S.moved) {
             B.moved = 0;
             B.mapped = 1;
+            mapped = true;
             for (int a = 0; a < 3; ++a) {
-                B.prev_pos[a] = B.pos[a];
-                B.prev_ext[a] = B.ext[a];
+                B.prev_pos[a] = S.pos[a];
+                B.prev_ext[a] = S.ext[a];
+                prev[a] = S.pos[a];
             }
         }
         for (int a = 0; a < 3; ++a) {
-            pos[a] = B.pos[a];
-            ext[a] = B.ext[a];
+            pos[a] = S.pos[a];
+            ext[a] = S.ext[a];
         }
-        if (integrate && B.active && B.free_body && B.dof) {
-            const double* acc = I.ctl->cnt[parity].acc[b];
+        if (integrate && S.active && S.free_body && S.dof) {
+            const double* acc = sacc[b];
             double F[3], T[3];
             for (int a = 0; a < 3; ++a) {
-                F[a] = B.have_prev ? 0.5 * (acc[a] + B.fprev[a]) : acc[a];
-                T[a] = B.have_prev ? 0.5 * (acc[3 + a] + B.fprev[3 + a]) : acc[3 + a];
+                F[a] = S.have_prev ? 0.5 * (acc[a] + S.fprev[a]) : acc[a];
+                T[a] = S.have_prev ? 0.5 * (acc[3 + a] + S.fprev[3 + a]) : acc[3 + a];
             }
             for (int a = 0; a < 6; ++a) B.fprev[a] = acc[a];
             B.have_prev = 1;
             const double accel[3] = {(double)I.ax, (double)I.ay, (double)I.az};
-            upd = integrate_rigid(B.half, B.pos, B.quat, B.vel, B.omega, B.density, F, T, accel, B.dof, pos, quat,
+            upd = integrate_rigid(S.half, S.pos, S.quat, S.vel, S.omega, S.density, F, T, accel, S.dof, pos, quat,
                                   vel, om);
             if (upd) {
                 const double n[3] = {(double)I.nx, (double)I.ny, (double)I.nz};
                 for (int a = 0; a < 3; ++a)
                     if (I.periodic & (1u << a)) pos[a] = pos[a] - n[a] * floor(pos[a] / n[a]);
                 quat_to_R(quat, R);
-                box_extent(R, B.half, ext);
+                box_extent(R, S.half, ext);
             }
         }
     }
@@ -481,20 +503,21 @@ __device__ __forceinline__ void bodies_wave(const Inst& I, int parity, bool reti
         if (j != b && aj && !sep) close = true;
     }
     if (upd) {
+        const DevBody& S = sb[b];
         DevBody& B = I.bodies[b];
         int err = close ? BODY_ERR_CLOSE : 0;
-        const double Rc = sqrt(B.half[0] * B.half[0] + B.half[1] * B.half[1] + B.half[2] * B.half[2]);
+        const double Rc = sqrt(S.half[0] * S.half[0] + S.half[1] * S.half[1] + S.half[2] * S.half[2]);
         const double speed = sqrt(vel[0] * vel[0] + vel[1] * vel[1] + vel[2] * vel[2]) +
                              sqrt(om[0] * om[0] + om[1] * om[1] + om[2] * om[2]) * Rc;
         if (!(speed < 1.0)) err |= BODY_ERR_SPEED;
         for (int a = 0; a < 3; ++a) {
             const bool per = I.periodic & (1u << a);
             if (per) {
-                if (2.0 * ext[a] >= n[a] && !(B.half[a] >= 0.5 * n[a] && ext[a] == B.half[a])) err |= BODY_ERR_WALL;
+                if (2.0 * ext[a] >= n[a] && !(S.half[a] >= 0.5 * n[a] && ext[a] == S.half[a])) err |= BODY_ERR_WALL;
             } else if (!(pos[a] - ext[a] >= 1.0 && pos[a] + ext[a] <= n[a] - 1.0)) {
                 err |= BODY_ERR_WALL;
             }
-            if (B.mapped && !(fabs(wrap_rel(pos[a] - B.prev_pos[a], n[a], per)) < 1.0)) err |= BODY_ERR_JUMP;
+            if (mapped && !(fabs(wrap_rel(pos[a] - prev[a], n[a], per)) < 1.0)) err |= BODY_ERR_JUMP;
         }
         if (err) {
             atomicOr(&I.ctl->body_err, err);
@@ -520,16 +543,19 @@ __device__ __forceinline__ void bodies_wave(const Inst& I, int parity, bool reti
 template <typename S>
 __device__ __forceinline__ void convert(const Inst& I, int parity, bool retire_moves, bool integrate) {
     __shared__ double part[CONV_WAVES][MAXB][6];
+    __shared__ double sacc[MAXB][6];
+    __shared__ DevBody sb[MAXB];
     const bool last = (int)(threadIdx.x >> 6) == CONV_WAVES - 1;
     constexpr int WORK_GROUPS = CONV_THREADS / 32 - 2;  // the 32-lane groups of all but the last wavefront
     ForceLoad F;
     forces_load(I, parity, F);
     if (!last) phase_claim<S>(I, parity, threadIdx.x >> 5, WORK_GROUPS);
+    else stage_bodies(I, sb);
     forces_partial(I, F, part);
     __syncthreads();
-    forces_final(I, parity, F, part);
+    forces_final(I, parity, F, part, sacc);
     __syncthreads();
-    if (last) bodies_wave(I, parity, retire_moves, integrate);
+    if (last) bodies_wave(I, retire_moves, integrate, sb, sacc);
     else phase_newgas<S>(I, parity, threadIdx.x >> 5, WORK_GROUPS);
     __syncthreads();
     phase_share(I, parity);
@@ -558,8 +584,12 @@ __global__ __launch_bounds__(CONV_THREADS) void kb_convert(const Inst* __restric
 // End of a step without conversions (phase-isolated calls).
 __global__ __launch_bounds__(CONV_THREADS) void k_finish(Inst I, int parity, int reduce, int zero_other,
                                                          int retire_moves) {
-    if (reduce) phase_forces(I, parity);
-    if (threadIdx.x < 64) bodies_wave(I, parity, retire_moves != 0, false);
+    __shared__ double sacc[MAXB][6];
+    __shared__ DevBody sb[MAXB];
+    if (threadIdx.x < 64) stage_bodies(I, sb);
+    if (reduce) phase_forces(I, parity, sacc);
+    __syncthreads();
+    if (threadIdx.x < 64) bodies_wave(I, retire_moves != 0, false, sb, sacc);
     if (zero_other) phase_finish(I, parity);
 }
 
