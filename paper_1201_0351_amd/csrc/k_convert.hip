@@ -51,7 +51,16 @@ __device__ __forceinline__ bool claimed(const uint32_t* bits, int id) {
 __device__ __forceinline__ int load_count(int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void unclaim(uint32_t* bits, int id) { atomicAnd(bits + (id >> 5), ~(1u << (id & 31))); }
+// Clear the whole bitmap word of a claimed cell with a plain store: for use
+// only where every bit set in the bitmap is being cleared in the same phase
+// and none is read or set there.
+__device__ __forceinline__ void unclaim_word(uint32_t* bits, int id) { bits[id >> 5] = 0u; }
+// add the number of calling lanes with `on` set to *cnt (one atomic per
+// wavefront)
+__device__ __forceinline__ void wave_count(bool on, int* cnt) {
+    const unsigned long long m = __ballot(on);
+    if (m && (threadIdx.x & 63) == __ffsll((long long)m) - 1) atomicAdd(cnt, __popcll(m));
+}
 
 __device__ __forceinline__ void push(int* list, int* cnt, int cap, int* overflow, int id) {
     const int p = atomicAdd(cnt, 1);
@@ -147,13 +156,6 @@ __device__ __forceinline__ int lane_nbr(const Inst& I, int x, int y, int z) {
     return nbr_index(I, x, y, z, lane_c(CXP, i), lane_c(CYP, i), lane_c(CZP, i));
 }
 
-// (rho - 1) of cell id summed over the group: lane q contributes f_q
-template <typename S>
-__device__ __forceinline__ float g_drho(const Inst& I, const S* pop, int id) {
-    const int q = g_lane();
-    return gsum(q < Q ? Store<S>::ld(pop, (size_t)q * I.ps + id, I.inv_scale) : 0.f);
-}
-
 // claim: one 32-lane group per candidate, lane i looks at neighbour x + c_i.
 template <typename S>
 __device__ __forceinline__ void phase_claim(const Inst& I, int parity, int g0, int ngroups) {
@@ -170,8 +172,10 @@ __device__ __forceinline__ void phase_claim(const Inst& I, int parity, int g0, i
         const int nb = lane_nbr(I, x, y, z);
         const uint8_t nf = nb >= 0 ? I.flags[nb] : 0;
         if (fl & MARK_FILL) {
-            const float dr = g_drho<S>(I, pop, id);
-            if (i == 0) I.share[id] = (float)(((double)I.m_hi[id] - 1.0) + ((double)I.m_lo[id] - (double)dr));
+            if (i == 0) {
+                const float dr = I.aux[id];  // rho - 1 left by the sweep
+                I.share[id] = (float)(((double)I.m_hi[id] - 1.0) + ((double)I.m_lo[id] - (double)dr));
+            }
             const bool take = nb >= 0 && (nf & TYPE_MASK) == GAS && claim(I.claim, nb);
             g_push(take, nb, I.newg, &C.n_newg, I.list_cap, &C.overflow);
         } else if (fl & MARK_EMPTY) {
@@ -183,8 +187,10 @@ __device__ __forceinline__ void phase_claim(const Inst& I, int parity, int g0, i
             const bool take = nb >= 0 && (nf & TYPE_MASK) == LIQ && claim(I.claim, nb);
             g_push(take, nb, I.newl, &C.n_newl, I.list_cap, &C.overflow);
             if (take) {
+                const float dr = drho_of<S>(I, pop, nb);
                 I.m_hi[nb] = 1.f;
-                I.m_lo[nb] = drho_of<S>(I, pop, nb);
+                I.m_lo[nb] = dr;
+                I.aux[nb] = dr;
                 phi[nb] = 1.f;
             }
         }
@@ -234,6 +240,7 @@ __device__ __forceinline__ void phase_newgas(const Inst& I, int parity, int g0, 
         if (j == 0) {
             I.m_hi[g] = 0.f;
             I.m_lo[g] = 0.f;
+            I.aux[g] = drb;
             phi[g] = 0.f;
         }
     }
@@ -269,9 +276,8 @@ __device__ __forceinline__ void phase_share(const Inst& I, int parity) {
 }
 
 // commit: converted and new cells take their new types; receivers add the
-// shares of their converted neighbours in link order i = 1..18 (lane i
-// fetches the share of neighbour i, lane 0 accumulates) and recompute
-// phi = m / rho.  One group per item.
+// shares of their converted neighbours in link order i = 1..18 and
+// recompute phi = m / rho.
 template <typename S>
 __device__ __forceinline__ void phase_commit(const Inst& I, int parity) {
     StepCounters& C = I.ctl->cnt[parity];
@@ -279,8 +285,11 @@ __device__ __forceinline__ void phase_commit(const Inst& I, int parity) {
     const int nl = min(load_count(&C.n_newl), I.list_cap), nr = min(load_count(&C.n_recv), I.list_cap);
     S* pop = (S*)pop_of(I, parity ^ 1);
     float* phi = phi_of(I, parity ^ 1);
-    // single-thread items
-    BLOCK_LOOP(k, nc + ng + nl) {
+    // single-thread items; the claim bits of the new cells are the only
+    // bits set in I.claim, and all of them are cleared here
+    for (int k0 = 0; k0 < nc + ng + nl; k0 += blockDim.x) {
+        const int k = k0 + (int)threadIdx.x;
+        bool f = false, e = false, g = false, l = false;
         if (k < nc) {
             const int id = I.cand[k];
             const uint8_t fl = I.flags[id];
@@ -289,47 +298,73 @@ __device__ __forceinline__ void phase_commit(const Inst& I, int parity) {
                 I.m_hi[id] = 0.f;
                 I.m_lo[id] = 0.f;
                 phi[id] = 1.f;
-                atomicAdd(&C.filled, 1);
+                f = true;
             } else if (fl & MARK_EMPTY) {
                 I.flags[id] = GAS | MARK_EMPTY;
                 I.m_hi[id] = 0.f;
                 I.m_lo[id] = 0.f;
                 phi[id] = 0.f;
-                atomicAdd(&C.emptied, 1);
+                e = true;
             }
-        } else {
-            const bool g = k < nc + ng;
+        } else if (k < nc + ng + nl) {
+            g = k < nc + ng;
+            l = !g;
             const int id = g ? I.newg[k - nc] : I.newl[k - nc - ng];
             I.flags[id] = IFC;
-            unclaim(I.claim, id);
-            atomicAdd(g ? &C.newg : &C.newl, 1);
+            unclaim_word(I.claim, id);
         }
+        wave_count(f, &C.filled);
+        wave_count(e, &C.emptied);
+        wave_count(g, &C.newg);
+        wave_count(l, &C.newl);
     }
-    // receivers: one group each (the flags read here are not among those
-    // written above: receivers and their converted neighbours keep their
-    // marks, and new cells are never converted cells)
-    const int grp = threadIdx.x >> 5, ngrp = blockDim.x >> 5;
-    const int i = g_lane();
-    for (int k = grp; k < nr; k += ngrp) {
-        const int id = I.recv[k];
+    // receivers (the flags read here are not among those written above:
+    // receivers and their converted neighbours keep their marks, and new
+    // cells are never converted cells); the receivers' claim bits are the
+    // only bits set in I.claim2, and all of them are cleared here
+    // Four lanes per receiver: lane r of a quad fetches the neighbours over
+    // links l = r + 4j, lane 0 adds the shares in link order.  rho - 1 of
+    // every receiver is in I.aux (left by the sweep for interface cells, by
+    // the claim and new-gas phases for new ones).
+    const int r = threadIdx.x & 3;
+    const int qbase = threadIdx.x & 63 & ~3;
+    for (int k0 = 0; k0 < nr; k0 += (int)blockDim.x / 4) {
+        const int k = k0 + (int)(threadIdx.x >> 2);
+        const bool act = k < nr;
+        const int id = I.recv[act ? k : k0];
         int x, y, z;
         cell_coords(I, id, x, y, z);
-        const int nb = lane_nbr(I, x, y, z);
-        // share loaded without waiting for the flags (one round trip)
-        const float sh = nb >= 0 ? I.share[nb] : 0.f;
-        const bool has = nb >= 0 && (I.flags[nb] & (MARK_FILL | MARK_EMPTY));
-        const unsigned m = g_ballot(has);
-        const float dr = g_drho<S>(I, pop, id);
-        float hi = I.m_hi[id], lo = I.m_lo[id];
-        for (int l = 1; l < Q; ++l) {
-            const float v = g_bcastf(sh, l);
-            if ((m >> l) & 1u) add_comp(hi, lo, v);
+        float sh[5];
+        unsigned has = 0;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            const int l = r + 4 * j;
+            sh[j] = 0.f;
+            if (l > 0 && l < Q) {
+                const int nb = nbr_index(I, x, y, z, lane_c(CXP, l), lane_c(CYP, l), lane_c(CZP, l));
+                if (nb >= 0) {
+                    sh[j] = I.share[nb];
+                    if (I.flags[nb] & (MARK_FILL | MARK_EMPTY)) has |= 1u << j;
+                }
+            }
         }
-        if (i == 0) {
+        float hi = 0.f, lo = 0.f, dr = 0.f;
+        if (r == 0 && act) {
+            hi = I.m_hi[id];
+            lo = I.m_lo[id];
+            dr = I.aux[id];
+        }
+#pragma unroll
+        for (int l = 1; l < Q; ++l) {
+            const float v = __shfl(sh[l >> 2], qbase + (l & 3));
+            const unsigned hb = (unsigned)__shfl((int)has, qbase + (l & 3));
+            if ((hb >> (l >> 2)) & 1u) add_comp(hi, lo, v);
+        }
+        if (r == 0 && act) {
             I.m_hi[id] = hi;
             I.m_lo[id] = lo;
             phi[id] = (float)(((double)hi + (double)lo) / (1.0 + (double)dr));
-            unclaim(I.claim2, id);
+            unclaim_word(I.claim2, id);
         }
     }
 }

@@ -507,6 +507,7 @@ __device__ __forceinline__ void sweep_boundary(const Inst& I, int parity, int wg
             I.m_hi[id] = mhi;
             I.m_lo[id] = mlo;
             phi_of(I, parity ^ 1)[id] = ph;
+            I.aux[id] = drho;  // rho - 1 of this interface cell, for the conversion phase
             if (mark) {
                 I.flags[id] = (fl & KEEP_MASK) | mark;
                 const int p = atomicAdd(&C.n_cand, 1);
@@ -702,6 +703,24 @@ __global__ __launch_bounds__(256) void k_mark(Inst I, int parity) {
         const uint8_t fl = I.flags[id];
         uint8_t mark = 0;
         if ((fl & TYPE_MASK) == IFC) {
+            // rho - 1 for the conversion phase (as the sweep leaves it)
+            float dr = 0.f;
+            switch (I.storage) {
+            case LBM_FP16_DEV:
+                for (int i = 0; i < Q; ++i)
+                    dr += Store<__half>::ld((const __half*)pop_of(I, parity ^ 1), (size_t)i * I.ps + id, I.inv_scale);
+                break;
+            case LBM_BF16_DEV:
+                for (int i = 0; i < Q; ++i)
+                    dr += Store<__hip_bfloat16>::ld((const __hip_bfloat16*)pop_of(I, parity ^ 1), (size_t)i * I.ps + id,
+                                                    I.inv_scale);
+                break;
+            default:
+                for (int i = 0; i < Q; ++i)
+                    dr += Store<float>::ld((const float*)pop_of(I, parity ^ 1), (size_t)i * I.ps + id, I.inv_scale);
+                break;
+            }
+            I.aux[id] = dr;
             const double ph = (double)phi_of(I, parity ^ 1)[id];
             if (ph >= 1.0 + I.eps) mark = MARK_FILL;
             else if (ph <= -I.eps) mark = MARK_EMPTY;
