@@ -270,7 +270,9 @@ __device__ __forceinline__ void phase_share(const Inst& I, int parity) {
             continue;
         }
         if (g_lane() == 0) I.share[id] = (float)((double)I.share[id] / nr);
-        const bool first = rcv && claim(I.claim2, nb);
+        // the receiver notes this converted neighbour (its link opp(i));
+        // the first note puts it on the list
+        const bool first = rcv && atomicOr(&I.cmask[nb], 1u << lane_opp(g_lane())) == 0u;
         g_push(first, nb, I.recv, &C.n_recv, I.list_cap, &C.overflow);
     }
 }
@@ -283,7 +285,6 @@ __device__ __forceinline__ void phase_commit(const Inst& I, int parity) {
     StepCounters& C = I.ctl->cnt[parity];
     const int nc = min(load_count(&C.n_cand), I.list_cap), ng = min(load_count(&C.n_newg), I.list_cap);
     const int nl = min(load_count(&C.n_newl), I.list_cap), nr = min(load_count(&C.n_recv), I.list_cap);
-    S* pop = (S*)pop_of(I, parity ^ 1);
     float* phi = phi_of(I, parity ^ 1);
     // single-thread items; the claim bits of the new cells are the only
     // bits set in I.claim, and all of them are cleared here
@@ -318,54 +319,30 @@ __device__ __forceinline__ void phase_commit(const Inst& I, int parity) {
         wave_count(g, &C.newg);
         wave_count(l, &C.newl);
     }
-    // receivers (the flags read here are not among those written above:
-    // receivers and their converted neighbours keep their marks, and new
-    // cells are never converted cells); the receivers' claim bits are the
-    // only bits set in I.claim2, and all of them are cleared here
-    // Four lanes per receiver: lane r of a quad fetches the neighbours over
-    // links l = r + 4j, lane 0 adds the shares in link order.  rho - 1 of
-    // every receiver is in I.aux (left by the sweep for interface cells, by
-    // the claim and new-gas phases for new ones).
-    const int r = threadIdx.x & 3;
-    const int qbase = threadIdx.x & 63 & ~3;
-    for (int k0 = 0; k0 < nr; k0 += (int)blockDim.x / 4) {
-        const int k = k0 + (int)(threadIdx.x >> 2);
-        const bool act = k < nr;
-        const int id = I.recv[act ? k : k0];
+    // receivers, one thread each: the note mask names the converted
+    // neighbours, whose shares are added in link order; rho - 1 of every
+    // receiver is in I.aux (left by the sweep for interface cells, by the
+    // claim and new-gas phases for new ones)
+    BLOCK_LOOP(k, nr) {
+        const int id = I.recv[k];
+        const uint32_t m = I.cmask[id];
         int x, y, z;
         cell_coords(I, id, x, y, z);
-        float sh[5];
-        unsigned has = 0;
-#pragma unroll
-        for (int j = 0; j < 5; ++j) {
-            const int l = r + 4 * j;
-            sh[j] = 0.f;
-            if (l > 0 && l < Q) {
-                const int nb = nbr_index(I, x, y, z, lane_c(CXP, l), lane_c(CYP, l), lane_c(CZP, l));
-                if (nb >= 0) {
-                    sh[j] = I.share[nb];
-                    if (I.flags[nb] & (MARK_FILL | MARK_EMPTY)) has |= 1u << j;
-                }
-            }
-        }
-        float hi = 0.f, lo = 0.f, dr = 0.f;
-        if (r == 0 && act) {
-            hi = I.m_hi[id];
-            lo = I.m_lo[id];
-            dr = I.aux[id];
-        }
+        float sh[Q];
 #pragma unroll
         for (int l = 1; l < Q; ++l) {
-            const float v = __shfl(sh[l >> 2], qbase + (l & 3));
-            const unsigned hb = (unsigned)__shfl((int)has, qbase + (l & 3));
-            if ((hb >> (l >> 2)) & 1u) add_comp(hi, lo, v);
+            sh[l] = 0.f;
+            if ((m >> l) & 1u) sh[l] = I.share[nbr_index(I, x, y, z, cx(l), cy(l), cz(l))];
         }
-        if (r == 0 && act) {
-            I.m_hi[id] = hi;
-            I.m_lo[id] = lo;
-            phi[id] = (float)(((double)hi + (double)lo) / (1.0 + (double)dr));
-            unclaim_word(I.claim2, id);
-        }
+        float hi = I.m_hi[id], lo = I.m_lo[id];
+        const float dr = I.aux[id];
+#pragma unroll
+        for (int l = 1; l < Q; ++l)
+            if ((m >> l) & 1u) add_comp(hi, lo, sh[l]);
+        I.m_hi[id] = hi;
+        I.m_lo[id] = lo;
+        phi[id] = (float)(((double)hi + (double)lo) / (1.0 + (double)dr));
+        I.cmask[id] = 0u;
     }
 }
 

@@ -83,7 +83,7 @@ size_t layout(const lbm_config& c, Inst* I, char* base) {
     char* ax = take(4 * N);
     char* ru = take(N);
     char* cl = take(4 * (N / 32 + 1));
-    char* cl2 = take(4 * (N / 32 + 1));
+    char* cm = take(4 * N);
     char* l0 = take(4 * N);
     char* l1 = take(4 * N);
     char* l2 = take(4 * N);
@@ -105,7 +105,7 @@ size_t layout(const lbm_config& c, Inst* I, char* base) {
         I->aux = (float*)ax;
         I->rule = (uint8_t*)ru;
         I->claim = (uint32_t*)cl;
-        I->claim2 = (uint32_t*)cl2;
+        I->cmask = (uint32_t*)cm;
         I->cand = (int*)l0;
         I->newg = (int*)l1;
         I->newl = (int*)l2;
@@ -300,7 +300,7 @@ int32_t lbm_create(const lbm_config* cfgs, int32_t n_inst, void* d_workspace, si
         HIP_OK(hipMemsetAsync(I.ctl, 0, sizeof(Ctl), c->stream));
         HIP_OK(hipMemsetAsync(I.bodies, 0, sizeof(DevBody) * MAXB, c->stream));
         HIP_OK(hipMemsetAsync(I.claim, 0, 4 * (N / 32 + 1), c->stream));
-        HIP_OK(hipMemsetAsync(I.claim2, 0, 4 * (N / 32 + 1), c->stream));
+        HIP_OK(hipMemsetAsync(I.cmask, 0, 4 * N, c->stream));
         HIP_OK(hipMemsetAsync(I.rule, 0, N, c->stream));
         launch_init(I, h.cfg, c->stream);
         HIP_OK(hipGetLastError());

@@ -130,7 +130,7 @@ struct Inst {
     float* aux;
     uint8_t* rule;
     uint32_t* claim;   // new-interface claims
-    uint32_t* claim2;  // receiver claims
+    uint32_t* cmask;   // per cell: bit l set when the neighbour over link l converted this step
     int* cand;
     int* newg;
     int* newl;
