@@ -72,3 +72,17 @@ def test_host_integrator_matches_oracle(dof):
     want = oracle_integrate(half, body["pos"], q, body["vel"], body["omega"], 0.6, F, T, a, dof)
     for k in ("pos", "vel", "omega", "quat"):
         np.testing.assert_allclose(got[k], want[k], rtol=1e-13, atol=1e-18)
+
+
+def test_host_integrator_matches_oracle_fast_spin():
+    """A rotation of 0.27 rad per step: the half-angle comes from sin and cos
+    rather than from the small-angle series."""
+    half = np.array([3.0, 5.0, 7.0])
+    q = np.array([math.cos(0.2), math.sin(0.2), 0.0, 0.0])
+    body = dict(half=half, pos=np.array([15.0, 16.0, 17.0]), quat=q, vel=np.zeros(3),
+                omega=np.array([0.15, -0.1, 0.2]), density=0.6)
+    F, T, a = np.zeros(3), np.array([0.5, -0.2, 0.1]), np.array([0, 0, -5e-6])
+    got = lbm.integrate_body(body, F, T, a, 0x38)
+    want = oracle_integrate(half, body["pos"], q, body["vel"], body["omega"], 0.6, F, T, a, 0x38)
+    for k in ("pos", "vel", "omega", "quat"):
+        np.testing.assert_allclose(got[k], want[k], rtol=1e-13, atol=1e-18)
