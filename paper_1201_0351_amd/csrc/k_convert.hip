@@ -161,8 +161,6 @@ template <typename S>
 __device__ __forceinline__ void phase_claim(const Inst& I, int parity, int g0, int ngroups) {
     StepCounters& C = I.ctl->cnt[parity];
     const int n = min(load_count(&C.n_cand), I.list_cap);
-    S* pop = (S*)pop_of(I, parity ^ 1);
-    float* phi = phi_of(I, parity ^ 1);
     const int i = g_lane();
     for (int k = g0; k < n; k += ngroups) {
         const int id = I.cand[k];
@@ -186,20 +184,14 @@ __device__ __forceinline__ void phase_claim(const Inst& I, int parity, int g0, i
             if (i == 0) I.share[id] = (float)((double)I.m_hi[id] + (double)I.m_lo[id]);
             const bool take = nb >= 0 && (nf & TYPE_MASK) == LIQ && claim(I.claim, nb);
             g_push(take, nb, I.newl, &C.n_newl, I.list_cap, &C.overflow);
-            if (take) {
-                const float dr = drho_of<S>(I, pop, nb);
-                I.m_hi[nb] = 1.f;
-                I.m_lo[nb] = dr;
-                I.aux[nb] = dr;
-                phi[nb] = 1.f;
-            }
         }
     }
 }
 
 // New interface cells from gas: equilibrium of the mean density and
 // velocity of their liquid / interface neighbours that are not emptying
-// (one group per new cell, lane j looks at neighbour j); m = 0.
+// (one group per new cell, lane j looks at neighbour j); m = 0.  New
+// interface cells from liquid (one thread each): m = rho, phi = 1.
 template <typename S>
 __device__ __forceinline__ void phase_newgas(const Inst& I, int parity, int g0, int ngroups) {
     StepCounters& C = I.ctl->cnt[parity];
@@ -243,6 +235,15 @@ __device__ __forceinline__ void phase_newgas(const Inst& I, int parity, int g0, 
             I.aux[g] = drb;
             phi[g] = 0.f;
         }
+    }
+    const int nl = min(load_count(&C.n_newl), I.list_cap);
+    for (int k = g0 * 32 + g_lane(); k < nl; k += ngroups * 32) {
+        const int id = I.newl[k];
+        const float dr = drho_of<S>(I, pop, id);
+        I.m_hi[id] = 1.f;
+        I.m_lo[id] = dr;
+        I.aux[id] = dr;
+        phi[id] = 1.f;
     }
 }
 
