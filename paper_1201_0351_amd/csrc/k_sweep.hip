@@ -609,12 +609,12 @@ __device__ __forceinline__ void sweep_boundary(const Inst& I, int parity, int wg
 }
 
 template <typename S>
-__global__ __launch_bounds__(256) void k_sweep_boundary(Inst I, int parity) {
+__global__ __launch_bounds__(256, 3) void k_sweep_boundary(Inst I, int parity) {
     sweep_boundary<S>(I, parity, blockIdx.x, gridDim.x);
 }
 
 template <typename S>
-__global__ __launch_bounds__(256) void kb_sweep_boundary(const Inst* __restrict__ tab, const int* __restrict__ off,
+__global__ __launch_bounds__(256, 3) void kb_sweep_boundary(const Inst* __restrict__ tab, const int* __restrict__ off,
                                                          int n, int parity) {
     const int k = batch_instance(off, n, blockIdx.x);
     const Inst I = tab[k];
