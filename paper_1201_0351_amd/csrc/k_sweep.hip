@@ -312,13 +312,17 @@ __device__ __forceinline__ void sweep_boundary(const Inst& I, int parity, int wg
         const int id = active ? I.bnd[k] : I.bnd[base];
         int x, y, z;
         cell_coords(I, id, x, y, z);
+        // the cell's own values are loaded before its type is known, so that
+        // they travel with the link loads below
         const uint8_t fl = I.flags[id];
+        const float phiraw = phi_t[id];
+        const float mhiraw = I.m_hi[id], mloraw = I.m_lo[id];
         const int type = fl & TYPE_MASK;
-        const float phix = type == IFC ? phi_t[id] : 1.f;
+        const float phix = type == IFC ? phiraw : 1.f;
         float mhi = 0.f, mlo = 0.f;
         if (type == IFC && l == 0) {
-            mhi = I.m_hi[id];
-            mlo = I.m_lo[id];
+            mhi = mhiraw;
+            mlo = mloraw;
         }
         // this lane's links: sources s_i = x - c_i (a wall reads as an
         // obstacle at rest) and everything read from them
