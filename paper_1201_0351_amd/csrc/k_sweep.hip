@@ -19,8 +19,9 @@
 //                     static wall is only a different load address) are
 //                     streamed and collided here at low register pressure.
 //                     Interface cells and liquid cells next to gas or a body
-//                     are appended to a boundary list (wavefront ballot +
-//                     prefix sum).  Gas and obstacle cells cost a flag byte.
+//                     are appended to a boundary list (wavefront ballots,
+//                     offsets combined in LDS, one atomic per workgroup).
+//                     Gas and obstacle cells cost a flag byte.
 //   k_sweep_boundary  one thread per listed cell: the full rule set, the
 //                     interface mass and fill level, the conversion marks and
 //                     the momentum exchange (Eqs. momentumexchange,
@@ -56,6 +57,35 @@ __device__ __forceinline__ void wave_append(bool pred, int id, int* list, int* c
     base = __shfl(base, leader);
     if (pred) {
         int pos = base + __popcll(mask & ((1ull << lane_id()) - 1ull));
+        if (pos < cap) list[pos] = id;
+        else atomicOr(overflow, 1);
+    }
+}
+
+// Workgroup-aggregated append of `id` to a list: one atomic per workgroup
+// (blockDim.x = 64 NW).  Every wavefront of the workgroup must call it.  A
+// single counter takes the appends of the whole grid, and device-scope
+// atomics on one address serialise, so fewer of them shorten the sweep.
+template <int NW>
+__device__ __forceinline__ void block_append(bool pred, int id, int* list, int* counter, int cap, int* overflow) {
+    __shared__ int wc[NW + 1];
+    const int w = threadIdx.x >> 6;
+    const unsigned long long mask = __ballot(pred);
+    if (lane_id() == 0) wc[w] = __popcll(mask);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            const int c = wc[k];
+            wc[k] = tot;
+            tot += c;
+        }
+        wc[NW] = tot ? atomicAdd(counter, tot) : 0;
+    }
+    __syncthreads();
+    if (pred) {
+        const int pos = wc[NW] + wc[w] + __popcll(mask & ((1ull << lane_id()) - 1ull));
         if (pos < cap) list[pos] = id;
         else atomicOr(overflow, 1);
     }
@@ -226,7 +256,7 @@ __device__ __forceinline__ void sweep_bulk(const Inst& I, int parity, int b, int
 
     bool defer = (type == IFC);
     if (type == LIQ) defer = bulk_cell<S>(I, src, dst, x, y, z, id);
-    wave_append(defer, id, I.bnd, &C.n_bnd, I.list_cap, &C.overflow);
+    block_append<4>(defer, id, I.bnd, &C.n_bnd, I.list_cap, &C.overflow);
 }
 
 // instance k of a batch: off[k] <= block < off[k + 1]
@@ -240,14 +270,15 @@ __device__ __forceinline__ int batch_instance(const int* __restrict__ off, int n
     return lo;
 }
 
+// At most 64 VGPRs, so that eight wavefronts fit per SIMD.
 template <typename S, int TX>
-__global__ __launch_bounds__(256) void k_sweep_bulk(Inst I, int parity) {
+__global__ __launch_bounds__(256, 8) void k_sweep_bulk(Inst I, int parity) {
     sweep_bulk<S, TX>(I, parity, blockIdx.x, gridDim.x);
 }
 
 // all instances of a batch in one launch (instance table in device memory)
 template <typename S, int TX>
-__global__ __launch_bounds__(256) void kb_sweep_bulk(const Inst* __restrict__ tab, const int* __restrict__ off, int n,
+__global__ __launch_bounds__(256, 8) void kb_sweep_bulk(const Inst* __restrict__ tab, const int* __restrict__ off, int n,
                                                      int parity) {
     const int k = batch_instance(off, n, blockIdx.x);
     const Inst I = tab[k];

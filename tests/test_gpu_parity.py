@@ -232,6 +232,86 @@ def test_sweep_on_injected_state(lbm, periodic):
     assert_force_close(Tg, To, 1e-4)
 
 
+def _with_liquid_gas_contacts(t, every=3):
+    """Copy of the types t with every `every`-th interface cell that touches a
+    liquid cell turned to gas: holes in the interface layer, so that liquid
+    cells see gas (non-periodic neighbourhood)."""
+    liq = np.pad(t == 1, 1)
+    nz, ny, nx = t.shape
+    near = np.zeros(t.shape, bool)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if 0 < abs(dx) + abs(dy) + abs(dz) <= 2:
+                    near |= liq[1 + dz:1 + dz + nz, 1 + dy:1 + dy + ny, 1 + dx:1 + dx + nx]
+    idx = np.flatnonzero((t == 2) & near)[::every]
+    out = t.copy()
+    out.flat[idx] = 0
+    return out
+
+
+def test_open_interface_checks_every_liquid_cell(lbm):
+    """Written types with holes in the interface layer (liquid next to gas,
+    which the conversions and the remap never produce): the bulk sweep must
+    leave the liquid cells that touch gas to the boundary sweep, which
+    reconstructs their links from the gas side.  One sweep, then three full
+    steps, against the oracle."""
+    n, H, seed = (40, 36, 32), 14.3, 3
+    cfg = W.basin(n, H, 0.7, 2e-5)
+    L, o = pair(lbm, cfg)
+    t = _with_liquid_gas_contacts(W.wavy_surface_types(n, H, 3.0, seed))
+    f, phi, m = W.random_state(n, t, seed + 1)
+    L.write(lbm.FIELD_FLAGS, t)
+    L.write(lbm.FIELD_POP, f)
+    L.write(lbm.FIELD_PHI, phi)
+    L.write(lbm.FIELD_MASS, m)
+    o.set_flags(t)
+    o.set_f(f)
+    o.set_phi(phi)
+    o.set_mass(m)
+    nc = o.liq_gas_contacts()
+    say("open interface: %d liquid cells touch gas" % nc)
+    assert nc > 0 and L.liq_gas_contacts() == nc
+    L.step_phases(lbm.PH_SWEEP)
+    o.step(1, PH_SWEEP)
+    tt = o.types()
+    assert np.array_equal(L.types(), tt)
+    fl = fluid_mask(tt)
+    assert np.abs(L.pop() - o.get_f())[:, fl].max() < 1e-6
+    L.step(3)
+    o.step(3)
+    _, mism = compare_pop(L, o, 1e-5, label="open interface +3")
+    assert mism == 0
+
+
+def test_body_moving_across_periodic_faces(lbm):
+    """A fixed, heeled box moved 0.3 cells in -x and 0.2 in +y per step across
+    the periodic x and y faces of a 48x32x24 channel: the remap wraps, and
+    the sweep must find the obstacle cells on both sides of each face for the
+    bounce-back and the momentum exchange.  Twelve full steps against the
+    oracle."""
+    n = (48, 32, 24)
+    cfg = W.basin(n, 12.0, 0.6, 1e-5, periodic=3)
+    b = W.box((10, 8, 8), (1.0, 30.5, 12.2), 15.0, 0.5, vel=(-0.05, 0.03, 0.0))
+    L, o = pair(lbm, cfg, [b])
+    say("box across the periodic faces, 12 steps")
+    for k in range(12):
+        L.step(1)
+        o.step(1)
+        b = dict(b, pos=((b["pos"][0] - 0.3) % n[0], (b["pos"][1] + 0.2) % n[1], b["pos"][2]))
+        L.set_body(0, b)
+        oracle_body(o, 0, b)
+    L.step(1)
+    o.step(1)
+    assert np.array_equal(L.flags() & 3, o.get_flags() & 3)
+    compare_pop(L, o, 1e-5, label="periodic box +13")
+    Fg, Tg = L.body_forces(0)
+    Fo, To = o.body_forces(0)
+    say("  F gpu %s oracle %s" % (Fg, Fo))
+    assert_force_close(Fg, Fo, 1e-3, atol=1e-7)
+    assert_force_close(Tg, To, 1e-3, atol=1e-6)
+
+
 @pytest.mark.parametrize("seed", [11, 12, 13])
 def test_conversions_bit_exact(lbm, seed):
     """Conversion phase alone on identical injected fill levels (a fifth of
