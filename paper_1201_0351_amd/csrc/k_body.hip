@@ -230,11 +230,17 @@ __device__ __forceinline__ void remap_commit_cell(const Inst& I, int parity, int
         I.flags[id] = (uint8_t)(OBS | (k << 2));
         I.m_hi[id] = I.m_lo[id] = 0.f;
         phi_of(I, parity)[id] = 0.f;
+        // every neighbour now has an obstacle neighbour
+        for (int i = 1; i < Q; ++i) {
+            const int nb = nbr_index(I, x, y, z, cx(i), cy(i), cz(i));
+            if (nb >= 0) I.nearo[nb] = 1;
+        }
         return;
     }
     if (((fl >> 2) & 15) != k) return;
     int r = I.rule[id];
     if (r == 0) return;
+    I.nearo[id] = 1;  // an uncovered cell borders the body (the bulk sweep clears it otherwise)
     if (r == 2) {
         for (int i = 1; i < Q; ++i) {
             const int nb = nbr_index(I, x, y, z, cx(i), cy(i), cz(i));

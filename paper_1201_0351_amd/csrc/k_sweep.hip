@@ -21,7 +21,11 @@
 //                     Interface cells and liquid cells next to gas or a body
 //                     are appended to a boundary list (wavefront ballots,
 //                     offsets combined in LDS, one atomic per workgroup).
-//                     Gas and obstacle cells cost a flag byte.
+//                     Gas and obstacle cells cost a flag byte.  Only liquid
+//                     cells with a near mark (Inst::nearo) read the types of
+//                     their 18 sources: the conversions keep an interface
+//                     layer between liquid and gas, and the remap marks the
+//                     neighbours of every obstacle cell it creates.
 //   k_sweep_boundary  one thread per listed cell: the full rule set, the
 //                     interface mass and fill level, the conversion marks and
 //                     the momentum exchange (Eqs. momentumexchange,
@@ -170,50 +174,62 @@ __device__ __forceinline__ void collide_store(const Inst& I, const float (&d)[Q]
 // bulk sweep
 // ---------------------------------------------------------------------------
 // One liquid cell: true if a source is gas or an obstacle (the cell is left
-// to the boundary sweep), else pull, collide and store.
+// to the boundary sweep), else pull, collide and store.  chk (the cell's near
+// mark): read the 18 source types, and clear the mark if none is gas or an
+// obstacle; without it every source is known to be liquid, interface or a
+// static wall.  The population loads go out first.
 template <typename S>
 __device__ __forceinline__ bool bulk_cell(const Inst& I, const S* __restrict__ src, S* __restrict__ dst, int x, int y,
-                                          int z, int id) {
-    // all 37 loads are issued without branches; per-link array bases are
-    // wavefront-uniform and the per-cell offset is 32-bit
+                                          int z, int id, bool chk) {
+    // per-link array bases are wavefront-uniform and the per-cell offset is
+    // 32-bit
     float d[Q];
-    uint8_t sf[Q];
     d[0] = Store<S>::load(src, id, I.inv_scale);
     const bool interior = x > 0 && x < I.nx - 1 && y > 0 && y < I.ny - 1 && z > 0 && z < I.nz - 1;
+    const int sxy = I.nx, sz = I.nx * I.ny;
+    const bool px = I.periodic & 1, py = I.periodic & 2, pz = I.periodic & 4;
+    const int xm = step_axis(x, -1, I.nx, px), xp = step_axis(x, 1, I.nx, px);
+    const int ym = step_axis(y, -1, I.ny, py), yp = step_axis(y, 1, I.ny, py);
+    const int zm = step_axis(z, -1, I.nz, pz), zp = step_axis(z, 1, I.nz, pz);
+    const int nx = I.nx, ny = I.ny;
+    // source of link i next to a face: its periodic image, or -1 (a wall)
+    // (captures plain values: a reference to the descriptor would move it
+    // to scratch memory in the batched kernel)
+    auto face_src = [=](int i) {
+        const int X = cx(i) == 1 ? xm : (cx(i) == -1 ? xp : x);
+        const int Y = cy(i) == 1 ? ym : (cy(i) == -1 ? yp : y);
+        const int Z = cz(i) == 1 ? zm : (cz(i) == -1 ? zp : z);
+        return (X | Y | Z) >= 0 ? X + nx * (Y + ny * Z) : -1;
+    };
     if (interior) {
-        const int sxy = I.nx, sz = I.nx * I.ny;
 #pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            const int s = id - (cx(i) + sxy * cy(i) + sz * cz(i));
-            d[i] = Store<S>::load(src + (size_t)i * I.ps, (unsigned)s, I.inv_scale);
-            sf[i] = I.flags[(unsigned)s];
-        }
+        for (int i = 1; i < Q; ++i)
+            d[i] = Store<S>::load(src + (size_t)i * I.ps, (unsigned)(id - (cx(i) + sxy * cy(i) + sz * cz(i))),
+                                  I.inv_scale);
     } else {
-        const bool px = I.periodic & 1, py = I.periodic & 2, pz = I.periodic & 4;
-        const int xm = step_axis(x, -1, I.nx, px), xp = step_axis(x, 1, I.nx, px);
-        const int ym = step_axis(y, -1, I.ny, py), yp = step_axis(y, 1, I.ny, py);
-        const int zm = step_axis(z, -1, I.nz, pz), zp = step_axis(z, 1, I.nz, pz);
-        // a wall source reads this cell's own flag (liquid) and, for the
-        // halfway bounce-back, its own f_ibar
+        // a wall source is the halfway bounce-back: this cell's own f_ibar
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-            const int X = cx(i) == 1 ? xm : (cx(i) == -1 ? xp : x);
-            const int Y = cy(i) == 1 ? ym : (cy(i) == -1 ? yp : y);
-            const int Z = cz(i) == 1 ? zm : (cz(i) == -1 ? zp : z);
-            const bool ok = (X | Y | Z) >= 0;
-            const int s = ok ? X + I.nx * (Y + I.ny * Z) : id;
-            const int arr = ok ? i : opp(i);
-            d[i] = Store<S>::load(src + (size_t)arr * I.ps, (unsigned)s, I.inv_scale);
-            sf[i] = I.flags[(unsigned)s];
+            const int s = face_src(i);
+            d[i] = Store<S>::load(src + (size_t)(s >= 0 ? i : opp(i)) * I.ps, (unsigned)(s >= 0 ? s : id),
+                                  I.inv_scale);
         }
     }
-    uint32_t bad = 0;
+    if (chk) {
+        uint32_t bad = 0;
 #pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        const uint32_t st = sf[i] & TYPE_MASK;
-        bad |= (uint32_t)(st == GAS) | (uint32_t)(st == OBS);
+        for (int i = 1; i < Q; ++i) {
+            int s = id - (cx(i) + sxy * cy(i) + sz * cz(i));
+            if (!interior) {
+                s = face_src(i);
+                s = s >= 0 ? s : id;  // a wall source reads this cell's own (liquid) type
+            }
+            const uint32_t st = I.flags[(unsigned)s] & TYPE_MASK;
+            bad |= (uint32_t)(st == GAS) | (uint32_t)(st == OBS);
+        }
+        if (bad) return true;
+        I.nearo[id] = 0;
     }
-    if (bad) return true;
     collide_store<S>(I, d, dst, I.ps, id);
     return false;
 }
@@ -250,12 +266,13 @@ __device__ __forceinline__ void sweep_bulk(const Inst& I, int parity, int b, int
     const bool inb = (x < I.nx) && (y < I.ny);
     const int id = inb ? x + I.nx * (y + I.ny * z) : 0;
     const uint8_t fl = inb ? I.flags[id] : (uint8_t)GAS;
+    const bool near = inb && I.nearo[id] != 0;
     const int type = fl & TYPE_MASK;
     // drop the marks a previous conversion phase left on this cell
     if (inb && (fl & ~KEEP_MASK)) I.flags[id] = fl & KEEP_MASK;
 
     bool defer = (type == IFC);
-    if (type == LIQ) defer = bulk_cell<S>(I, src, dst, x, y, z, id);
+    if (type == LIQ) defer = bulk_cell<S>(I, src, dst, x, y, z, id, near);
     block_append<4>(defer, id, I.bnd, &C.n_bnd, I.list_cap, &C.overflow);
 }
 
@@ -276,9 +293,10 @@ __global__ __launch_bounds__(256, 8) void k_sweep_bulk(Inst I, int parity) {
     sweep_bulk<S, TX>(I, parity, blockIdx.x, gridDim.x);
 }
 
-// all instances of a batch in one launch (instance table in device memory)
+// all instances of a batch in one launch (instance table in device memory;
+// the copied descriptor needs registers of its own, so no 64-VGPR bound)
 template <typename S, int TX>
-__global__ __launch_bounds__(256, 8) void kb_sweep_bulk(const Inst* __restrict__ tab, const int* __restrict__ off, int n,
+__global__ __launch_bounds__(256) void kb_sweep_bulk(const Inst* __restrict__ tab, const int* __restrict__ off, int n,
                                                      int parity) {
     const int k = batch_instance(off, n, blockIdx.x);
     const Inst I = tab[k];

@@ -82,6 +82,7 @@ size_t layout(const lbm_config& c, Inst* I, char* base) {
     char* sh = take(4 * N);
     char* ax = take(4 * N);
     char* ru = take(N);
+    char* no = take(N);
     char* cl = take(4 * (N / 32 + 1));
     char* cm = take(4 * N);
     char* l0 = take(4 * N);
@@ -104,6 +105,7 @@ size_t layout(const lbm_config& c, Inst* I, char* base) {
         I->share = (float*)sh;
         I->aux = (float*)ax;
         I->rule = (uint8_t*)ru;
+        I->nearo = (uint8_t*)no;
         I->claim = (uint32_t*)cl;
         I->cmask = (uint32_t*)cm;
         I->cand = (int*)l0;
@@ -302,6 +304,7 @@ int32_t lbm_create(const lbm_config* cfgs, int32_t n_inst, void* d_workspace, si
         HIP_OK(hipMemsetAsync(I.claim, 0, 4 * (N / 32 + 1), c->stream));
         HIP_OK(hipMemsetAsync(I.cmask, 0, 4 * N, c->stream));
         HIP_OK(hipMemsetAsync(I.rule, 0, N, c->stream));
+        HIP_OK(hipMemsetAsync(I.nearo, 0, N, c->stream));  // no bodies and a closed layer
         launch_init(I, h.cfg, c->stream);
         HIP_OK(hipGetLastError());
     }
@@ -1044,6 +1047,33 @@ int32_t lbm_read_fields(lbm_ctx* c, int32_t inst, int32_t field, int32_t dtype, 
     return LBM_OK;
 }
 
+// Near marks of written cell types (a, masked): 1 for every cell with a gas
+// or obstacle cell among its 18 neighbours (periodic images included, walls
+// not).  Written types may leave liquid next to gas, which the conversions
+// never do; the bulk sweep checks the sources of exactly the marked cells.
+static std::vector<uint8_t> near_marks(const Inst& I, const std::vector<uint8_t>& a) {
+    const int n[3] = {I.nx, I.ny, I.nz};
+    std::vector<uint8_t> m(a.size(), 0);
+    for (int z = 0; z < n[2]; ++z)
+        for (int y = 0; y < n[1]; ++y)
+            for (int x = 0; x < n[0]; ++x) {
+                const size_t id = (size_t)x + (size_t)n[0] * ((size_t)y + (size_t)n[1] * z);
+                for (int i = 1; i < Q && !m[id]; ++i) {
+                    int c[3] = {x + cx(i), y + cy(i), z + cz(i)};
+                    bool wall = false;
+                    for (int k = 0; k < 3; ++k) {
+                        if (c[k] >= 0 && c[k] < n[k]) continue;
+                        if ((I.periodic >> k) & 1u) c[k] = (c[k] + n[k]) % n[k];
+                        else wall = true;
+                    }
+                    if (wall) continue;
+                    const int t = a[(size_t)c[0] + (size_t)n[0] * ((size_t)c[1] + (size_t)n[1] * c[2])] & TYPE_MASK;
+                    if (t == GAS || t == OBS) m[id] = 1;
+                }
+            }
+    return m;
+}
+
 int32_t lbm_write_fields(lbm_ctx* c, int32_t inst, int32_t field, int32_t dtype, const void* src, size_t bytes) {
     int rc = check_inst(c, inst);
     if (rc) return rc;
@@ -1073,6 +1103,8 @@ int32_t lbm_write_fields(lbm_ctx* c, int32_t inst, int32_t field, int32_t dtype,
             }
         }
         HIP_OK(hipMemcpy(I.flags, a.data(), N, hipMemcpyHostToDevice));
+        const std::vector<uint8_t> nm = near_marks(I, a);
+        HIP_OK(hipMemcpy(I.nearo, nm.data(), N, hipMemcpyHostToDevice));
         // the written obstacle cells are the bodies' mappings at their poses
         rc = pull_bodies(c, h);
         if (rc) return rc;

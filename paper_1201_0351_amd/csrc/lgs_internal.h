@@ -129,6 +129,12 @@ struct Inst {
     float* share;
     float* aux;
     uint8_t* rule;
+    // Per cell: 1 where the cell may have a gas or obstacle neighbour.  Set
+    // by the remap around covered and on uncovered cells, and by written
+    // types; cleared by the bulk sweep for a liquid cell whose 18 sources it
+    // found fluid or wall.  The conversions keep an interface layer between
+    // liquid and gas (Sec. 2.2), so a liquid cell with 0 here has neither.
+    uint8_t* nearo;
     uint32_t* claim;   // new-interface claims
     uint32_t* cmask;   // per cell: bit l set when the neighbour over link l converted this step
     int* cand;
