@@ -181,31 +181,51 @@ __device__ __forceinline__ void collide_store(const Inst& I, const float (&d)[Q]
 template <typename S>
 __device__ __forceinline__ bool bulk_cell(const Inst& I, const S* __restrict__ src, S* __restrict__ dst, int x, int y,
                                           int z, int id, bool chk) {
-    // per-link array bases are wavefront-uniform and the per-cell offset is
-    // 32-bit
     float d[Q];
-    d[0] = Store<S>::load(src, id, I.inv_scale);
-    const bool interior = x > 0 && x < I.nx - 1 && y > 0 && y < I.ny - 1 && z > 0 && z < I.nz - 1;
-    const int sxy = I.nx, sz = I.nx * I.ny;
+    const int nx = I.nx, ny = I.ny, sxy = nx, sz = nx * ny;
     const bool px = I.periodic & 1, py = I.periodic & 2, pz = I.periodic & 4;
-    const int xm = step_axis(x, -1, I.nx, px), xp = step_axis(x, 1, I.nx, px);
-    const int ym = step_axis(y, -1, I.ny, py), yp = step_axis(y, 1, I.ny, py);
+    // Wavefronts whose cells all lie away from the y and z faces (x faces
+    // included): one load per link and lane at a 32-bit offset from plane 0,
+    // an x-face lane taking its periodic image or (wall) its own f_ibar by a
+    // select.  Every 64-wide row segment holds an x-face cell; a separate
+    // path for those lanes made each wavefront wait for one set of loads
+    // before issuing the other.  Other wavefronts take the general sources
+    // for all their lanes.
+    const bool inner = y > 0 && y < ny - 1 && z > 0 && z < I.nz - 1 && (size_t)Q * I.ps * sizeof(S) <= 0xFFFFFFFFull;
+    // decided per wavefront, so that exactly one of the two load paths runs
+    const bool row = __builtin_amdgcn_readfirstlane((int)(__ballot(!inner) == 0ull)) != 0;
+    const bool xlo = x == 0, xhi = x == nx - 1;
+    // source cell of link i in such a row, -1 for a wall
+    auto row_src = [=](int i) {
+        int s = id - (cx(i) + sxy * cy(i) + sz * cz(i));
+        if (cx(i) == 1 && xlo) s = px ? s + nx : -1;
+        if (cx(i) == -1 && xhi) s = px ? s - nx : -1;
+        return s;
+    };
+    const int xm = step_axis(x, -1, nx, px), xp = step_axis(x, 1, nx, px);
+    const int ym = step_axis(y, -1, ny, py), yp = step_axis(y, 1, ny, py);
     const int zm = step_axis(z, -1, I.nz, pz), zp = step_axis(z, 1, I.nz, pz);
-    const int nx = I.nx, ny = I.ny;
-    // source of link i next to a face: its periodic image, or -1 (a wall)
-    // (captures plain values: a reference to the descriptor would move it
-    // to scratch memory in the batched kernel)
+    // source of link i next to a y or z face: its periodic image, or -1 (a
+    // wall) (captures plain values: a reference to the descriptor would move
+    // it to scratch memory in the batched kernel)
     auto face_src = [=](int i) {
         const int X = cx(i) == 1 ? xm : (cx(i) == -1 ? xp : x);
         const int Y = cy(i) == 1 ? ym : (cy(i) == -1 ? yp : y);
         const int Z = cz(i) == 1 ? zm : (cz(i) == -1 ? zp : z);
         return (X | Y | Z) >= 0 ? X + nx * (Y + ny * Z) : -1;
     };
-    if (interior) {
+    if (row) {
+        const uint32_t ps = (uint32_t)I.ps, uid = (uint32_t)id;
+        const uint32_t wrap = (uint32_t)nx;
 #pragma unroll
-        for (int i = 1; i < Q; ++i)
-            d[i] = Store<S>::load(src + (size_t)i * I.ps, (unsigned)(id - (cx(i) + sxy * cy(i) + sz * cz(i))),
-                                  I.inv_scale);
+        for (int i = 1; i < Q; ++i) {
+            // element offset of the source population from plane 0
+            uint32_t e = (uint32_t)i * ps + uid - (uint32_t)(cx(i) + sxy * cy(i) + sz * cz(i));
+            const uint32_t wall = (uint32_t)opp(i) * ps + uid;
+            if (cx(i) == 1) e = xlo ? (px ? e + wrap : wall) : e;
+            if (cx(i) == -1) e = xhi ? (px ? e - wrap : wall) : e;
+            d[i] = Store<S>::load((const S*)((const char*)src + e * (uint32_t)sizeof(S)), 0, I.inv_scale);
+        }
     } else {
         // a wall source is the halfway bounce-back: this cell's own f_ibar
 #pragma unroll
@@ -215,15 +235,13 @@ __device__ __forceinline__ bool bulk_cell(const Inst& I, const S* __restrict__ s
                                   I.inv_scale);
         }
     }
+    d[0] = Store<S>::load(src, id, I.inv_scale);
     if (chk) {
         uint32_t bad = 0;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-            int s = id - (cx(i) + sxy * cy(i) + sz * cz(i));
-            if (!interior) {
-                s = face_src(i);
-                s = s >= 0 ? s : id;  // a wall source reads this cell's own (liquid) type
-            }
+            int s = row ? row_src(i) : face_src(i);
+            s = s >= 0 ? s : id;  // a wall source reads this cell's own (liquid) type
             const uint32_t st = I.flags[(unsigned)s] & TYPE_MASK;
             bad |= (uint32_t)(st == GAS) | (uint32_t)(st == OBS);
         }
