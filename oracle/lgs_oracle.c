@@ -94,8 +94,14 @@ static double fterm(int i, double rho, const double u[3], const double a[3]) {
 /* ---------------------------------------------------------------------------
  * State
  * ------------------------------------------------------------------------- */
+/* body shapes: a cuboid of half extents half[0..2], or a sphere of radius
+ * half[0] */
+enum { OB_CUBOID = 0, OB_SPHERE = 1 };
+static const double OB_PI = 3.14159265358979323846;
+
 typedef struct {
     int active, moved;
+    int shape; /* OB_CUBOID or OB_SPHERE; kept when the pose is set again */
     double half[3], pos[3], quat[4], vel[3], omega[3], density;
     int fixed;
     double R[9]; /* body -> world rotation, row major */
@@ -168,6 +174,7 @@ static void cell_u(const ob_state *s, const double *f, long id, double rho, doub
  * Body geometry (Sec. 2.3: a cell is an obstacle cell of a body iff its cell
  * centre (x+.5, y+.5, z+.5) lies inside the body volume).  Cuboid bodies with
  * half extents h in the body frame; the test is closed: |R^T (x_c - o)|_k <= h_k.
+ * Spheres of radius r: |x_c - o|^2 <= r^2, the squares summed in axis order.
  * Periodic axes use the minimum image of x_c - o.
  * ------------------------------------------------------------------------- */
 static void quat_to_R(const double q[4], double R[9]) {
@@ -203,6 +210,7 @@ static void to_body(const ob_body *b, const double d[3], double r[3]) {
 static int inside(const ob_state *s, const ob_body *b, int x, int y, int z) {
     double p[3] = {x + 0.5, y + 0.5, z + 0.5}, d[3], r[3];
     rel(s, b, p, d);
+    if (b->shape == OB_SPHERE) return d[0] * d[0] + d[1] * d[1] + d[2] * d[2] <= b->half[0] * b->half[0];
     to_body(b, d, r);
     return fabs(r[0]) <= b->half[0] && fabs(r[1]) <= b->half[1] && fabs(r[2]) <= b->half[2];
 }
@@ -215,10 +223,18 @@ static void body_vel(const ob_body *b, const double d[3], double u[3]) {
 }
 
 /* Sec. 2.4: velocity of the point of the body surface closest to the cell
- * centre (for a cuboid and a centre outside it: clamp in the body frame). */
+ * centre (for a cuboid and a centre outside it: clamp in the body frame; for
+ * a sphere: the centre's offset scaled to the radius). */
 static void closest_surface_vel(const ob_state *s, const ob_body *b, int x, int y, int z, double u[3]) {
     double p[3] = {x + 0.5, y + 0.5, z + 0.5}, d[3], r[3], c[3], dw[3];
     rel(s, b, p, d);
+    if (b->shape == OB_SPHERE) {
+        double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        double sc = dn > b->half[0] ? b->half[0] / dn : 1.0;
+        for (int k = 0; k < 3; ++k) dw[k] = d[k] * sc;
+        body_vel(b, dw, u);
+        return;
+    }
     to_body(b, d, r);
     for (int k = 0; k < 3; ++k) c[k] = r[k] < -b->half[k] ? -b->half[k] : (r[k] > b->half[k] ? b->half[k] : r[k]);
     for (int k = 0; k < 3; ++k) dw[k] = b->R[k * 3 + 0] * c[0] + b->R[k * 3 + 1] * c[1] + b->R[k * 3 + 2] * c[2];
@@ -385,6 +401,15 @@ int ob_set_body(ob_state *s, int k, const double *half, const double *pos, const
     b->moved = 1;
     b->have_prev = 0;
     if (k + 1 > s->nb) s->nb = k + 1;
+    return 0;
+}
+
+/* Shape of body k (OB_CUBOID, OB_SPHERE with radius half[0]); kept by later
+ * ob_set_body calls. */
+int ob_set_body_shape(ob_state *s, int k, int shape) {
+    if (k < 0 || k >= OB_MAXB || (shape != OB_CUBOID && shape != OB_SPHERE)) return -1;
+    s->b[k].shape = shape;
+    s->b[k].moved = 1;
     return 0;
 }
 
@@ -918,7 +943,7 @@ int ob_step(ob_state *s, int nsteps, int phase_mask) {
 int ob_integrate_body(const double *half, const double *pos, const double *quat, const double *vel,
                       const double *omega, double density, const double *F, const double *T,
                       const double *a, int dof_mask, double *pos_out, double *quat_out, double *vel_out,
-                      double *omega_out);
+                      double *omega_out, int shape);
 
 int ob_step_coupled(ob_state *s, int nsteps, const int *dof_masks) {
     for (int n = 0; n < nsteps; ++n) {
@@ -936,7 +961,7 @@ int ob_step_coupled(ob_state *s, int nsteps, const int *dof_masks) {
             b->have_prev = 1;
             double p[3], q[4], v[3], w[3];
             if (ob_integrate_body(b->half, b->pos, b->quat, b->vel, b->omega, b->density, F, T, s->a, dof_masks[k], p,
-                                  q, v, w))
+                                  q, v, w, b->shape))
                 return -1;
             double fp[3] = {b->fprev[0], b->fprev[1], b->fprev[2]}, tp[3] = {b->tprev[0], b->tprev[1], b->tprev[2]};
             ob_set_body(s, k, b->half, p, q, v, w, b->density, b->fixed);
@@ -1030,8 +1055,10 @@ void ob_mark_mapped(ob_state *s) {
 int ob_integrate_body(const double *half, const double *pos, const double *quat, const double *vel,
                       const double *omega, double density, const double *F, const double *T,
                       const double *a, int dof_mask, double *pos_out, double *quat_out, double *vel_out,
-                      double *omega_out) {
-    double M = density * 8.0 * half[0] * half[1] * half[2];
+                      double *omega_out, int shape) {
+    /* mass of the body's own volume: cuboid 8 h0 h1 h2, sphere 4/3 pi r^3 */
+    const double r3 = half[0] * half[0] * half[0];
+    double M = shape == OB_SPHERE ? density * (4.0 / 3.0) * OB_PI * r3 : density * 8.0 * half[0] * half[1] * half[2];
     if (!(M > 0.0)) return -1;
     double v[3], w[3];
     for (int k = 0; k < 3; ++k) {
@@ -1041,9 +1068,12 @@ int ob_integrate_body(const double *half, const double *pos, const double *quat,
     }
     double R[9];
     quat_to_R(quat, R);
+    /* principal moments: cuboid M/3 (h_j^2 + h_k^2), sphere 2/5 M r^2 */
     double Ib[3] = {M / 3.0 * (half[1] * half[1] + half[2] * half[2]),
                     M / 3.0 * (half[0] * half[0] + half[2] * half[2]),
                     M / 3.0 * (half[0] * half[0] + half[1] * half[1])};
+    if (shape == OB_SPHERE)
+        for (int k = 0; k < 3; ++k) Ib[k] = 0.4 * M * half[0] * half[0];
     double I[9];
     for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 3; ++c) {

@@ -43,6 +43,7 @@ def lib():
         L.ob_set_threads.argtypes = [C.c_void_p, C.c_int]
         L.ob_init_basin.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_uint64, C.c_double]
         L.ob_set_body.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp, _dp, _dp, C.c_double, C.c_int]
+        L.ob_set_body_shape.argtypes = [C.c_void_p, C.c_int, C.c_int]
         L.ob_get_body.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp, _dp]
         L.ob_step.argtypes = [C.c_void_p, C.c_int, C.c_int]
         L.ob_body_forces.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
@@ -64,7 +65,7 @@ def lib():
         L.ob_force.argtypes = [C.c_double, _dp, _dp, _dp]
         L.ob_integrate_body.restype = C.c_int
         L.ob_integrate_body.argtypes = [_dp, _dp, _dp, _dp, _dp, C.c_double, _dp, _dp, _dp, C.c_int,
-                                        _dp, _dp, _dp, _dp]
+                                        _dp, _dp, _dp, _dp, C.c_int]
         _lib = L
     return _lib
 
@@ -93,13 +94,16 @@ def force_term(rho, u, a):
     return out
 
 
-def integrate_body(half, pos, quat, vel, omega, density, F, T, accel, dof_mask):
+CUBOID, SPHERE = 0, 1
+
+
+def integrate_body(half, pos, quat, vel, omega, density, F, T, accel, dof_mask, shape=CUBOID):
     outs = [np.zeros(3), np.zeros(4), np.zeros(3), np.zeros(3)]
     args = [_arr(v) for v in (half, pos, quat, vel, omega)]
     fa = [_arr(v) for v in (F, T, accel)]
     rc = lib().ob_integrate_body(args[0][1], args[1][1], args[2][1], args[3][1], args[4][1], float(density),
                                  fa[0][1], fa[1][1], fa[2][1], int(dof_mask),
-                                 *[o.ctypes.data_as(_dp) for o in outs])
+                                 *[o.ctypes.data_as(_dp) for o in outs], int(shape))
     if rc != 0:
         raise ValueError("integrate_body: invalid body")
     return dict(pos=outs[0], quat=outs[1], vel=outs[2], omega=outs[3])
@@ -143,11 +147,15 @@ class Oracle:
                             float(noise_amp))
 
     def set_body(self, k, half, pos, quat=(1.0, 0.0, 0.0, 0.0), vel=(0, 0, 0), omega=(0, 0, 0),
-                 density=1.0, fixed=1):
+                 density=1.0, fixed=1, shape=None):
+        """Pose and motion of body k; `shape` (CUBOID, or SPHERE of radius
+        half[0]) is kept by later calls that leave it None."""
         arrs = [_arr(v) for v in (half, pos, quat, vel, omega)]
         rc = lib().ob_set_body(self._h, int(k), *[p for _, p in arrs], float(density), int(fixed))
         if rc != 0:
             raise ValueError("bad body index")
+        if shape is not None and lib().ob_set_body_shape(self._h, int(k), int(shape)) != 0:
+            raise ValueError("bad body shape")
 
     def get_body(self, k):
         outs = [np.zeros(3), np.zeros(4), np.zeros(3), np.zeros(3)]
