@@ -107,11 +107,16 @@ typedef struct lbm_config {
                                   reads the forces and runs lbm_integrate_body */
 } lbm_config;
 
-/* A cuboid rigid body (Sec. 2.3).  A cell is an obstacle cell of the body iff
- * its centre c satisfies |R^T (c - pos)|_k <= half_ext[k] for k = 0..2, with R
- * the rotation of `quat` and the minimum image of c - pos on periodic axes
- * (evaluated in FP64 without fused multiply-add).  Moving-wall velocity at a
- * point p: vel + omega x (p - pos). */
+/* Body shapes (Sec. 2.3 maps any shape by its cell centres; the paper's
+ * experiments use cuboids and spheres). */
+enum { LBM_SHAPE_CUBOID = 0, LBM_SHAPE_SPHERE = 1 };
+
+/* A rigid body (Sec. 2.3).  A cell is an obstacle cell of the body iff its
+ * centre c satisfies, with d = c - pos (minimum image on periodic axes) and
+ * everything in FP64 without fused multiply-add:
+ *   cuboid: |R^T d|_k <= half_ext[k] for k = 0..2, R the rotation of `quat`;
+ *   sphere: d_x^2 + d_y^2 + d_z^2 <= r^2 (summed in that order), r = half_ext[0].
+ * Moving-wall velocity at a point p: vel + omega x (p - pos). */
 typedef struct lbm_body {
     double half_ext[3]; /* half extents in the body frame (cells)                  */
     double pos[3];      /* centre of gravity o, lattice coordinates               */
@@ -127,6 +132,8 @@ typedef struct lbm_body {
                            same FP64 operations, or on the host: see
                            lbm_config.host_body_update)                          */
     uint32_t dof_mask;  /* free bodies: bits 0-2 translation x,y,z, 3-5 rotation */
+    uint32_t shape;     /* LBM_SHAPE_CUBOID (0) or LBM_SHAPE_SPHERE (radius half_ext[0];
+                           half_ext[1..2] are ignored)                           */
 } lbm_body;
 
 typedef struct lbm_ctx lbm_ctx;
@@ -237,10 +244,11 @@ int32_t lbm_boundary_cells(lbm_ctx* ctx, int32_t inst, int64_t* n);
 
 /* Rigid-body update on the host (the paper couples to a rigid-body engine;
  * this is a plain semi-implicit Euler step, dt = 1), for callers that move
- * held bodies themselves: mass M = density * 8 hx hy hz,
- * V += (F + M a) / M on translational DOFs (dof_mask bits 0-2),
- * Omega += I_SS^-1 T_S on rotational DOFs S (bits 3-5; I the world-frame
- * cuboid inertia about the centre), pos += V, quat rotated by Omega. */
+ * held bodies themselves: mass M = density * 8 hx hy hz (cuboid) or
+ * density * 4/3 pi r^3 (sphere), V += (F + M a) / M on translational DOFs
+ * (dof_mask bits 0-2), Omega += I_SS^-1 T_S on rotational DOFs S (bits 3-5; I
+ * the world-frame inertia about the centre: cuboid M/3 (h_j^2 + h_k^2) on the
+ * body axes, sphere 2/5 M r^2), pos += V, quat rotated by Omega. */
 int32_t lbm_integrate_body(const lbm_body* in, const double force[3], const double torque[3],
                            const double accel[3], uint32_t dof_mask, lbm_body* out);
 

@@ -263,11 +263,23 @@ __device__ __forceinline__ void remap_commit_cell(const Inst& I, int parity, int
         double d0 = wrap_rel((x + 0.5) - B.pos[0], (double)I.nx, I.periodic & 1);
         double d1 = wrap_rel((y + 0.5) - B.pos[1], (double)I.ny, I.periodic & 2);
         double d2 = wrap_rel((z + 0.5) - B.pos[2], (double)I.nz, I.periodic & 4);
-        double rb[3] = {B.R[0] * d0 + B.R[3] * d1 + B.R[6] * d2, B.R[1] * d0 + B.R[4] * d1 + B.R[7] * d2,
-                        B.R[2] * d0 + B.R[5] * d1 + B.R[8] * d2};
-        for (int a = 0; a < 3; ++a) rb[a] = rb[a] < -B.half[a] ? -B.half[a] : (rb[a] > B.half[a] ? B.half[a] : rb[a]);
         double p[3];
-        for (int a = 0; a < 3; ++a) p[a] = B.R[a * 3 + 0] * rb[0] + B.R[a * 3 + 1] * rb[1] + B.R[a * 3 + 2] * rb[2];
+        if (B.shape == LBM_SHAPE_SPHERE) {
+            // the centre's offset scaled to the radius
+            const double dn = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            const double sc = dn > B.half[0] ? B.half[0] / dn : 1.0;
+            p[0] = d0 * sc;
+            p[1] = d1 * sc;
+            p[2] = d2 * sc;
+        } else {
+            // clamped to the cuboid in the body frame
+            double rb[3] = {B.R[0] * d0 + B.R[3] * d1 + B.R[6] * d2, B.R[1] * d0 + B.R[4] * d1 + B.R[7] * d2,
+                            B.R[2] * d0 + B.R[5] * d1 + B.R[8] * d2};
+            for (int a = 0; a < 3; ++a)
+                rb[a] = rb[a] < -B.half[a] ? -B.half[a] : (rb[a] > B.half[a] ? B.half[a] : rb[a]);
+            for (int a = 0; a < 3; ++a)
+                p[a] = B.R[a * 3 + 0] * rb[0] + B.R[a * 3 + 1] * rb[1] + B.R[a * 3 + 2] * rb[2];
+        }
         u[0] = B.vel[0] + (B.omega[1] * p[2] - B.omega[2] * p[1]);
         u[1] = B.vel[1] + (B.omega[2] * p[0] - B.omega[0] * p[2]);
         u[2] = B.vel[2] + (B.omega[0] * p[1] - B.omega[1] * p[0]);

@@ -491,14 +491,14 @@ __device__ __forceinline__ void bodies_wave(const Inst& I, bool retire_moves, bo
             for (int a = 0; a < 6; ++a) B.fprev[a] = acc[a];
             B.have_prev = 1;
             const double accel[3] = {(double)I.ax, (double)I.ay, (double)I.az};
-            upd = integrate_rigid(S.half, S.pos, S.quat, S.vel, S.omega, S.density, F, T, accel, S.dof, pos, quat,
-                                  vel, om);
+            upd = integrate_rigid(S.shape, S.half, S.pos, S.quat, S.vel, S.omega, S.density, F, T, accel, S.dof, pos,
+                                  quat, vel, om);
             if (upd) {
                 const double n[3] = {(double)I.nx, (double)I.ny, (double)I.nz};
                 for (int a = 0; a < 3; ++a)
                     if (I.periodic & (1u << a)) pos[a] = pos[a] - n[a] * floor(pos[a] / n[a]);
                 quat_to_R(quat, R);
-                box_extent(R, S.half, ext);
+                box_extent(S.shape, R, S.half, ext);
             }
         }
     }

@@ -415,12 +415,16 @@ int32_t lbm_set_body(lbm_ctx* c, int32_t inst, int32_t k, const lbm_body* b) {
     const bool was_mapped = old.active && old.mapped;
     DevBody d;
     memset(&d, 0, sizeof d);
+    if (b->shape != LBM_SHAPE_CUBOID && b->shape != LBM_SHAPE_SPHERE) return fail(LBM_ERR_INVALID, "set_body: unknown shape");
+    d.shape = (int)b->shape;
     for (int a = 0; a < 3; ++a) {
-        if (!(b->half_ext[a] > 0.0)) return fail(LBM_ERR_INVALID, "set_body: half extents must be positive");
+        // a sphere keeps its radius on every axis
+        const double hk = d.shape == LBM_SHAPE_SPHERE ? b->half_ext[0] : b->half_ext[a];
+        if (!(hk > 0.0)) return fail(LBM_ERR_INVALID, "set_body: half extents must be positive");
         double p = b->pos[a];
         if (h.cfg.periodic & (1 << a)) p = p - n[a] * std::floor(p / n[a]);
         d.pos[a] = p;
-        d.half[a] = b->half_ext[a];
+        d.half[a] = hk;
         d.vel[a] = b->vel[a];
         d.omega[a] = b->omega[a];
     }
@@ -429,7 +433,7 @@ int32_t lbm_set_body(lbm_ctx* c, int32_t inst, int32_t k, const lbm_body* b) {
     if (!(std::fabs(qn - 1.0) < 1e-6)) return fail(LBM_ERR_INVALID, "set_body: quaternion must be unit");
     for (int a = 0; a < 4; ++a) d.quat[a] = b->quat[a];
     quat_to_R(b->quat, d.R);
-    box_extent(d.R, d.half, d.ext);
+    box_extent(d.shape, d.R, d.half, d.ext);
     rc = check_pose(h, k, d, was_mapped, "set_body");
     if (rc) return rc;
     if (b->fixed == 0 && (b->dof_mask & ~0x3Fu)) return fail(LBM_ERR_INVALID, "set_body: dof_mask has unknown bits");
@@ -517,7 +521,7 @@ static int couple_on_host(lbm_ctx* c, InstHost& h, int p) {
         }
         for (int a = 0; a < 4; ++a) d.quat[a] = out.quat[a];
         quat_to_R(d.quat, d.R);
-        box_extent(d.R, d.half, d.ext);
+        box_extent(d.shape, d.R, d.half, d.ext);
         rc = check_pose(h, b, d, d.mapped != 0, "free-body update (host)");
         if (rc) return fail(LBM_ERR_UNSTABLE, lbm_last_error());
         d.moved = 1;
@@ -1162,8 +1166,10 @@ int32_t lbm_integrate_body(const lbm_body* in, const double F[3], const double T
                            uint32_t dof, lbm_body* out) {
     if (!in || !F || !T || !accel || !out) return fail(LBM_ERR_INVALID, "integrate_body: NULL argument");
     lbm_body o = *in;
-    if (!integrate_rigid(in->half_ext, in->pos, in->quat, in->vel, in->omega, in->density, F, T, accel, dof, o.pos,
-                         o.quat, o.vel, o.omega))
+    if (in->shape != LBM_SHAPE_CUBOID && in->shape != LBM_SHAPE_SPHERE)
+        return fail(LBM_ERR_INVALID, "integrate_body: unknown shape");
+    if (!integrate_rigid((int)in->shape, in->half_ext, in->pos, in->quat, in->vel, in->omega, in->density, F, T, accel,
+                         dof, o.pos, o.quat, o.vel, o.omega))
         return fail(LBM_ERR_INVALID, "integrate_body: body mass must be positive");
     *out = o;
     return LBM_OK;

@@ -101,6 +101,7 @@ struct DevBody {
     double fprev[6];  // previous step's force / torque (free bodies)
     double density;
     uint32_t dof;  // free bodies: DOF mask (bits 0-2 translation, 3-5 rotation)
+    int shape;     // LBM_SHAPE_CUBOID, or LBM_SHAPE_SPHERE of radius half[0] (= half[1] = half[2])
     int active;
     int moved;      // pose changed since the last remap
     int mapped;     // the obstacle cells of the body exist
@@ -284,6 +285,7 @@ __device__ inline bool inside_body(const Inst& I, const DevBody& b, int x, int y
     double d0 = wrap_rel((x + 0.5) - b.pos[0], (double)I.nx, I.periodic & 1);
     double d1 = wrap_rel((y + 0.5) - b.pos[1], (double)I.ny, I.periodic & 2);
     double d2 = wrap_rel((z + 0.5) - b.pos[2], (double)I.nz, I.periodic & 4);
+    if (b.shape == LBM_SHAPE_SPHERE) return d0 * d0 + d1 * d1 + d2 * d2 <= b.half[0] * b.half[0];
     double r0 = b.R[0] * d0 + b.R[3] * d1 + b.R[6] * d2;
     double r1 = b.R[1] * d0 + b.R[4] * d1 + b.R[7] * d2;
     double r2 = b.R[2] * d0 + b.R[5] * d1 + b.R[8] * d2;
@@ -344,11 +346,14 @@ __host__ __device__ inline void quat_to_R(const double q[4], double R[9]) {
     R[8] = 1.0 - 2.0 * (x * x + y * y);
 }
 
-// World-frame half extents of the bounding box of a cuboid.
-__host__ __device__ inline void box_extent(const double R[9], const double half[3], double ext[3]) {
+// World-frame half extents of the bounding box of a body: a cuboid's rotated
+// extents, a sphere's radius.
+__host__ __device__ inline void box_extent(int shape, const double R[9], const double half[3], double ext[3]) {
 #pragma clang fp contract(off)
     for (int a = 0; a < 3; ++a)
-        ext[a] = fabs(R[a * 3 + 0]) * half[0] + fabs(R[a * 3 + 1]) * half[1] + fabs(R[a * 3 + 2]) * half[2];
+        ext[a] = shape == LBM_SHAPE_SPHERE
+                     ? half[0]
+                     : fabs(R[a * 3 + 0]) * half[0] + fabs(R[a * 3 + 1]) * half[1] + fabs(R[a * 3 + 2]) * half[2];
 }
 
 // Rigid-body update of a cuboid of density rho_s (relative to the liquid)
@@ -379,13 +384,17 @@ __host__ __device__ inline void half_angle(double th, double& s_over_th, double&
     }
 }
 
-__host__ __device__ inline bool integrate_rigid(const double half[3], const double pos[3], const double quat[4],
-                                                const double vel[3], const double omega[3], double density,
-                                                const double F[3], const double T[3], const double accel[3],
-                                                uint32_t dof, double opos[3], double oquat[4], double ovel[3],
-                                                double oomega[3]) {
+__host__ __device__ inline bool integrate_rigid(int shape, const double half[3], const double pos[3],
+                                                const double quat[4], const double vel[3], const double omega[3],
+                                                double density, const double F[3], const double T[3],
+                                                const double accel[3], uint32_t dof, double opos[3], double oquat[4],
+                                                double ovel[3], double oomega[3]) {
 #pragma clang fp contract(off)
-    const double M = density * 8.0 * half[0] * half[1] * half[2];
+    // mass of the body's own volume: cuboid 8 h0 h1 h2, sphere 4/3 pi r^3
+    const bool sphere = shape == LBM_SHAPE_SPHERE;
+    const double r3 = half[0] * half[0] * half[0];
+    const double M = sphere ? density * (4.0 / 3.0) * 3.14159265358979323846 * r3
+                            : density * 8.0 * half[0] * half[1] * half[2];
     if (!(M > 0.0)) return false;
     for (int a = 0; a < 3; ++a) {
         ovel[a] = (dof & (1u << a)) ? vel[a] + (F[a] + M * accel[a]) / M : vel[a];
@@ -393,9 +402,11 @@ __host__ __device__ inline bool integrate_rigid(const double half[3], const doub
     }
     double R[9];
     quat_to_R(quat, R);
-    const double Ib[3] = {M / 3.0 * (half[1] * half[1] + half[2] * half[2]),
-                          M / 3.0 * (half[0] * half[0] + half[2] * half[2]),
-                          M / 3.0 * (half[0] * half[0] + half[1] * half[1])};
+    // principal moments: cuboid M/3 (h_j^2 + h_k^2), sphere 2/5 M r^2
+    const double Is = 0.4 * M * half[0] * half[0];
+    const double Ib[3] = {sphere ? Is : M / 3.0 * (half[1] * half[1] + half[2] * half[2]),
+                          sphere ? Is : M / 3.0 * (half[0] * half[0] + half[2] * half[2]),
+                          sphere ? Is : M / 3.0 * (half[0] * half[0] + half[1] * half[1])};
     double Iw[9];
     for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 3; ++c) {

@@ -19,6 +19,7 @@ STORAGE = {"fp32": FP32, "fp16": FP16_DEV, "bf16": BF16_DEV}
 PERIODIC_X, PERIODIC_Y, PERIODIC_Z = 1, 2, 4
 FIELD_POP, FIELD_FLAGS, FIELD_PHI, FIELD_MASS, FIELD_RHO, FIELD_VEL = 1, 2, 3, 4, 5, 6
 F64, F32, U8 = 0, 1, 2
+SHAPE_CUBOID, SHAPE_SPHERE = 0, 1
 PH_REMAP, PH_SWEEP, PH_CONVERT, PH_ALL = 1, 2, 4, 7
 MAX_BODIES = 16
 
@@ -34,7 +35,7 @@ class lbm_config(C.Structure):
 class lbm_body(C.Structure):
     _fields_ = [("half_ext", C.c_double * 3), ("pos", C.c_double * 3), ("quat", C.c_double * 4),
                 ("vel", C.c_double * 3), ("omega", C.c_double * 3), ("density", C.c_double),
-                ("fixed", C.c_uint32), ("dof_mask", C.c_uint32)]
+                ("fixed", C.c_uint32), ("dof_mask", C.c_uint32), ("shape", C.c_uint32)]
 
 
 class LBMError(RuntimeError):
@@ -130,13 +131,14 @@ def make_body(d):
     b.density = float(d.get("density", 1.0))
     b.fixed = int(d.get("fixed", 1))
     b.dof_mask = int(d.get("dof", 0x3F if b.fixed == 0 else 0))
+    b.shape = int(d.get("shape", SHAPE_CUBOID))
     return b
 
 
 def body_dict(b):
     return dict(half=np.array(b.half_ext[:]), pos=np.array(b.pos[:]), quat=np.array(b.quat[:]),
                 vel=np.array(b.vel[:]), omega=np.array(b.omega[:]), density=b.density, fixed=b.fixed,
-                dof=b.dof_mask)
+                dof=b.dof_mask, shape=b.shape)
 
 
 def integrate_body(body, F, T, accel, dof_mask):

@@ -9,6 +9,7 @@ import re
 import numpy as np
 import pytest
 
+from oracle.oracle import SPHERE
 from oracle.oracle import integrate_body as oracle_integrate
 from paper_1201_0351_amd import lbm
 
@@ -34,7 +35,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_sizes_match_header_layout():
     assert C.sizeof(lbm.lbm_config) == 4 * 4 + 8 + 24 + 8 * 4 + 4 + 4 + 8 + 8 + 8 + 4 + 4
-    assert C.sizeof(lbm.lbm_body) == 8 * (3 + 3 + 4 + 3 + 3 + 1) + 8
+    # 17 doubles, then fixed, dof_mask and shape (uint32), padded to 8 bytes
+    assert C.sizeof(lbm.lbm_body) == 8 * (3 + 3 + 4 + 3 + 3 + 1) + 4 * 3 + 4
 
 
 def _ws(cfg):
@@ -84,5 +86,23 @@ def test_host_integrator_matches_oracle_fast_spin():
     F, T, a = np.zeros(3), np.array([0.5, -0.2, 0.1]), np.array([0, 0, -5e-6])
     got = lbm.integrate_body(body, F, T, a, 0x38)
     want = oracle_integrate(half, body["pos"], q, body["vel"], body["omega"], 0.6, F, T, a, 0x38)
+    for k in ("pos", "vel", "omega", "quat"):
+        np.testing.assert_allclose(got[k], want[k], rtol=1e-13, atol=1e-18)
+
+
+@pytest.mark.parametrize("dof", [0x3F, 0x38, 0x07])
+def test_host_integrator_matches_oracle_sphere(dof):
+    """A sphere (radius half_ext[0]): mass 4/3 pi r^3 rho_s and the isotropic
+    inertia 2/5 M r^2 on both sides."""
+    rng = np.random.default_rng(100 + dof)
+    r = 6.5
+    ax = rng.normal(size=3)
+    ax /= np.linalg.norm(ax)
+    q = np.array([math.cos(0.3), *(math.sin(0.3) * ax)])
+    body = dict(half=np.array([r, 1.0, 2.0]), pos=rng.uniform(10, 20, 3), quat=q, vel=rng.normal(0, 1e-3, 3),
+                omega=rng.normal(0, 1e-4, 3), density=0.5, shape=lbm.SHAPE_SPHERE)
+    F, T, a = rng.normal(0, 1e-2, 3), rng.normal(0, 1e-1, 3), np.array([0, 0, -5e-6])
+    got = lbm.integrate_body(body, F, T, a, dof)
+    want = oracle_integrate((r, r, r), body["pos"], q, body["vel"], body["omega"], 0.5, F, T, a, dof, shape=SPHERE)
     for k in ("pos", "vel", "omega", "quat"):
         np.testing.assert_allclose(got[k], want[k], rtol=1e-13, atol=1e-18)

@@ -53,7 +53,7 @@ def oracle_for(cfg, threads=THREADS):
 
 def oracle_body(o, k, b):
     o.set_body(k, b["half"], b["pos"], b["quat"], b.get("vel", (0, 0, 0)), b.get("omega", (0, 0, 0)),
-               b.get("density", 1.0), b.get("fixed", 1))
+               b.get("density", 1.0), b.get("fixed", 1), shape=b.get("shape", 0))
 
 
 def pair(lbm, cfg, bodies=()):
@@ -310,6 +310,58 @@ def test_body_moving_across_periodic_faces(lbm):
     say("  F gpu %s oracle %s" % (Fg, Fo))
     assert_force_close(Fg, Fo, 1e-3, atol=1e-7)
     assert_force_close(Tg, To, 1e-3, atol=1e-6)
+
+
+def _sphere(r, pos, **kw):
+    return dict(half=(r, r, r), pos=tuple(float(p) for p in pos), quat=(1.0, 0.0, 0.0, 0.0), shape=1, **kw)
+
+
+def test_sphere_remap_on_injected_surface(lbm):
+    """A spinning sphere of radius 6 (Sec. 2.3 mapping by cell centres) is
+    mapped onto a wavy surface, then moved by 0.6 cells per remap: covered and
+    uncovered cells bit-exact; uncovered cells take f_eq at the velocity of
+    the closest point of the sphere's surface."""
+    b = _sphere(6.0, (20.3, 18.1, 14.2), vel=(0.01, -0.02, 0.005), omega=(2e-3, -1e-3, 3e-3), density=0.5)
+    L, o, _ = _injected(lbm, bodies=[b])
+    say("sphere remap 1 (insert)")
+    L.step_phases(lbm.PH_REMAP)
+    o.step(1, PH_REMAP)
+    assert np.array_equal(L.flags(), o.get_flags())
+    for k in range(4):
+        b = dict(b, pos=(b["pos"][0] + 0.6, b["pos"][1] - 0.35, b["pos"][2] + 0.45))
+        L.set_body(0, b)
+        oracle_body(o, 0, b)
+        say("sphere remap move %d" % k)
+        L.step_phases(lbm.PH_REMAP)
+        o.step(1, PH_REMAP)
+        fg, fo = L.flags(), o.get_flags()
+        assert np.array_equal(fg, fo), int((fg != fo).sum())
+        t = fo & 3
+        fl = fluid_mask(t)
+        assert np.abs(L.pop() - o.get_f())[:, fl].max() < 2e-7
+        iface = t == 2
+        np.testing.assert_allclose(L.mass()[iface], o.get_mass()[iface], atol=1e-6)
+
+
+def test_free_sphere_floats_with_the_oracle(lbm):
+    """A free sphere of radius 5 and density 0.5 released in a 32x32x32 basin
+    (tau 0.6, g 1e-5, depth 16), free in all six DOFs: 200 coupled steps on
+    both sides; types, populations, pose and force stay together."""
+    cfg = W.basin((32, 32, 32), 16.0, 0.6, 1e-5, seed=1, noise_amp=1e-4)
+    body = _sphere(5.0, (16.2, 15.7, 16.4), density=0.5, fixed=0, dof=0x3F)
+    L, o = pair(lbm, cfg, [body])
+    say("free sphere 200 coupled steps")
+    L.step(200)
+    o.step_coupled(200, [0x3F])
+    rel, mism = compare_pop(L, o, 1e-5, label="free sphere")
+    assert mism <= 5
+    bg, bo = L.get_body(0), o.get_body(0)
+    Fg, _ = L.body_forces(0)
+    Fo, _ = o.body_forces(0)
+    say("  Fz gpu %.6e oracle %.6e; z gpu %.9f oracle %.9f" % (Fg[2], Fo[2], bg["pos"][2], bo["pos"][2]))
+    assert_force_close(Fg, Fo, 1e-2, atol=1e-7)
+    np.testing.assert_allclose(bg["pos"], bo["pos"], atol=1e-5)
+    np.testing.assert_allclose(bg["vel"], bo["vel"], atol=1e-7)
 
 
 @pytest.mark.parametrize("seed", [11, 12, 13])
