@@ -114,6 +114,7 @@ typedef struct {
     int nx, ny, nz;
     long N;
     double tau, a[3], rho_g, eps;
+    double wall_u[3]; /* velocity of the non-periodic faces (moving no-slip walls) */
     int per[3];
     int recon_mode;
     double *f, *fn;          /* [Q][N] absolute PDFs: current and next */
@@ -310,6 +311,12 @@ void ob_destroy(ob_state *s) {
 }
 
 void ob_set_threads(ob_state *s, int n) { s->nthreads = n > 0 ? n : 1; }
+
+/* Velocity of the lattice's non-periodic faces: moving no-slip walls
+ * (Eq. noslip with u_w; the paper's channel is driven by its long sides). */
+void ob_set_wall_velocity(ob_state *s, const double *u) {
+    for (int k = 0; k < 3; ++k) s->wall_u[k] = u[k];
+}
 
 long ob_num_cells(const ob_state *s) { return s->N; }
 
@@ -633,6 +640,8 @@ static double nb_fill(const ob_state *s, int x, int y, int z, int dx, int dy, in
  * S2: stream + boundaries + collide for one LIQ/IF cell (Sec. 2.1-2.4).
  * Pull form of Eq. stream: f'_i(x) comes from s = x - c_i.
  *   s wall / obstacle : Eq. noslip  f'_i = f_ibar(x) + (2/cs2) w_i rho_x c_i.u_w
+ *                       (u_w: the body's velocity at the link midpoint, or
+ *                       the wall velocity for a source beyond a face)
  *   s gas             : Eq. reconstruct with the partner read as this cell's
  *                       own outgoing f_ibar(x,t):
  *                       f'_i = f_eq,i(rho_G,u_x) + f_eq,ibar(rho_G,u_x) - f_ibar(x)
@@ -693,7 +702,7 @@ static void sweep_cell(ob_state *s, int x, int y, int z) {
         int inb = nbr(s, x, y, z, -CX[i], -CY[i], -CZ[i], &src);
         int st = inb ? s->type[src] : T_OBS;
         if (st == T_OBS) {
-            double uw[3] = {0, 0, 0};
+            double uw[3] = {s->wall_u[0], s->wall_u[1], s->wall_u[2]};
             if (inb) {
                 const ob_body *b = &s->b[(int)s->bid[src]];
                 double pm[3] = {xc[0] - 0.5 * CX[i], xc[1] - 0.5 * CY[i], xc[2] - 0.5 * CZ[i]};

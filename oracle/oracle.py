@@ -44,6 +44,7 @@ def lib():
         L.ob_init_basin.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_uint64, C.c_double]
         L.ob_set_body.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp, _dp, _dp, C.c_double, C.c_int]
         L.ob_set_body_shape.argtypes = [C.c_void_p, C.c_int, C.c_int]
+        L.ob_set_wall_velocity.argtypes = [C.c_void_p, _dp]
         L.ob_get_body.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp, _dp]
         L.ob_step.argtypes = [C.c_void_p, C.c_int, C.c_int]
         L.ob_body_forces.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
@@ -156,6 +157,11 @@ class Oracle:
             raise ValueError("bad body index")
         if shape is not None and lib().ob_set_body_shape(self._h, int(k), int(shape)) != 0:
             raise ValueError("bad body shape")
+
+    def set_wall_velocity(self, u):
+        """Velocity of the non-periodic faces (moving no-slip walls)."""
+        a, p = _arr(u)
+        lib().ob_set_wall_velocity(self._h, p)
 
     def get_body(self, k):
         outs = [np.zeros(3), np.zeros(4), np.zeros(3), np.zeros(3)]

@@ -271,3 +271,37 @@ def test_righting_moment_converges_with_resolution():
         errs.append(abs(ms / ana - 1))
     assert errs[1] < errs[0]
     assert errs[1] < 0.05
+
+
+def test_moving_walls_keep_a_uniform_flow():
+    """Moving no-slip walls (Eq. noslip with u_w, the paper's channel drive):
+    a uniform flow at the wall velocity is an exact fixed point, since the
+    moving-wall bounce-back of f_eq(1, u) returns f_eq(1, u)."""
+    nx, ny, nz = 12, 10, 8
+    u = np.array([0.02, 0.0, 0.0])
+    o = Oracle(nx, ny, nz, 0.8, periodic=1, threads=NT)
+    o.init_basin(1e9)
+    o.set_wall_velocity(u)
+    fe = feq(1.0, u)
+    o.set_f(np.broadcast_to(fe[:, None, None, None], (19, nz, ny, nx)).copy())
+    o.step(40)
+    vel, rho = velocity(o)
+    np.testing.assert_allclose(rho, 1.0, atol=1e-14)
+    for a in range(3):
+        np.testing.assert_allclose(vel[a], u[a], atol=1e-14)
+
+
+def test_moving_walls_drag_the_liquid_to_their_velocity():
+    """A channel at rest, periodic along x, with all its walls moving at u
+    along x: the liquid relaxes to the uniform velocity u (the steady state of
+    the moving-wall boundary; a wrong sign or factor in the wall term would
+    give another velocity)."""
+    nx, ny, nz = 4, 12, 10
+    u = 1e-3
+    o = Oracle(nx, ny, nz, 1.0, periodic=1, threads=NT)
+    o.init_basin(1e9)
+    o.set_wall_velocity((u, 0.0, 0.0))
+    o.step(3000)
+    vel, _ = velocity(o)
+    assert np.abs(vel[0] / u - 1.0).max() < 1e-4
+    assert np.abs(vel[1]).max() < 1e-12 and np.abs(vel[2]).max() < 1e-12
