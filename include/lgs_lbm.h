@@ -105,6 +105,9 @@ typedef struct lbm_config {
                                   the end of every step (no host round trip);
                                   1 = on the host: every step synchronises,
                                   reads the forces and runs lbm_integrate_body */
+    double wall_vel[3];        /* velocity of the non-periodic faces: moving no-slip
+                                  walls (Eq. noslip with u_w = wall_vel; the paper's
+                                  channel is driven by its long sides); 0 = static */
 } lbm_config;
 
 /* Body shapes (Sec. 2.3 maps any shape by its cell centres; the paper's

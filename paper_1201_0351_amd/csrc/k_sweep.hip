@@ -289,8 +289,12 @@ __device__ __forceinline__ void sweep_bulk(const Inst& I, int parity, int b, int
     // drop the marks a previous conversion phase left on this cell
     if (inb && (fl & ~KEEP_MASK)) I.flags[id] = fl & KEEP_MASK;
 
-    bool defer = (type == IFC);
-    if (type == LIQ) defer = bulk_cell<S>(I, src, dst, x, y, z, id, near);
+    // next to a moving wall the boundary sweep adds the wall term
+    const bool wall = I.wall_moving && ((!(I.periodic & 1) && (x == 0 || x == I.nx - 1)) ||
+                                        (!(I.periodic & 2) && (y == 0 || y == I.ny - 1)) ||
+                                        (!(I.periodic & 4) && (z == 0 || z == I.nz - 1)));
+    bool defer = (type == IFC) || (type == LIQ && wall);
+    if (type == LIQ && !wall) defer = bulk_cell<S>(I, src, dst, x, y, z, id, near);
     block_append<4>(defer, id, I.bnd, &C.n_bnd, I.list_cap, &C.overflow);
 }
 
@@ -509,6 +513,7 @@ __device__ __forceinline__ void sweep_boundary(const Inst& I, int parity, int wg
                     r1 = (float)wrap_rel(xc1 - bpos[bk][1], I.ny, py);
                     r2 = (float)wrap_rel(xc2 - bpos[bk][2], I.nz, pz);
                 }
+                if (e < 0) cu = cxf * I.wall_u[0] + cyf * I.wall_u[1] + czf * I.wall_u[2];  // a moving wall
                 const float mw = 6.f * wi * rhox * cu;
                 d[j] = dxo + mw;
                 if (bk >= 0 && active) {

@@ -137,6 +137,8 @@ int validate(const lbm_config& c, int k) {
     if (c.recon_mode < 0 || c.recon_mode > 2) return bad("unknown recon_mode");
     if (c.max_bodies < 0 || c.max_bodies > MAXB) return bad("max_bodies out of range");
     if (c.host_body_update != 0 && c.host_body_update != 1) return bad("host_body_update must be 0 or 1");
+    for (int a = 0; a < 3; ++a)
+        if (!(std::fabs(c.wall_vel[a]) < 0.1)) return bad("wall_vel must be well below the lattice speed of sound");
     const double n[3] = {(double)c.nx, (double)c.ny, (double)c.nz};
     for (int a = 0; a < 3; ++a)
         if (!(n[a] * std::fabs(c.accel[a]) < 0.1 / 3.0))
@@ -295,6 +297,8 @@ int32_t lbm_create(const lbm_config* cfgs, int32_t n_inst, void* d_workspace, si
         I.ay = (float)h.cfg.accel[1];
         I.az = (float)h.cfg.accel[2];
         I.rho_g = (float)h.cfg.rho_gas;
+        for (int a = 0; a < 3; ++a) I.wall_u[a] = (float)h.cfg.wall_vel[a];
+        I.wall_moving = h.cfg.wall_vel[0] != 0.0 || h.cfg.wall_vel[1] != 0.0 || h.cfg.wall_vel[2] != 0.0;
         I.scale = h.cfg.storage == LBM_FP16_DEV ? (float)h.cfg.fp16_scale : 1.f;
         I.inv_scale = 1.f / I.scale;
         I.eps = h.cfg.eps;
@@ -415,7 +419,8 @@ int32_t lbm_set_body(lbm_ctx* c, int32_t inst, int32_t k, const lbm_body* b) {
     const bool was_mapped = old.active && old.mapped;
     DevBody d;
     memset(&d, 0, sizeof d);
-    if (b->shape != LBM_SHAPE_CUBOID && b->shape != LBM_SHAPE_SPHERE) return fail(LBM_ERR_INVALID, "set_body: unknown shape");
+    if (b->shape != LBM_SHAPE_CUBOID && b->shape != LBM_SHAPE_SPHERE)
+        return fail(LBM_ERR_INVALID, "set_body: unknown shape");
     d.shape = (int)b->shape;
     for (int a = 0; a < 3; ++a) {
         // a sphere keeps its radius on every axis

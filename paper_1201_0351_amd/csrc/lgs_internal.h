@@ -120,6 +120,8 @@ struct Inst {
     float omega;       // 1 / tau
     float ax, ay, az;  // body acceleration
     float rho_g;
+    float wall_u[3];   // velocity of the non-periodic faces (moving no-slip walls)
+    int wall_moving;   // wall_u != 0
     float scale, inv_scale;  // storage scale (FP16), 1 otherwise
     double eps;
     void* pop[2];

@@ -29,7 +29,8 @@ class lbm_config(C.Structure):
                 ("tau", C.c_double), ("accel", C.c_double * 3), ("rho_gas", C.c_double), ("eps", C.c_double),
                 ("fill_height", C.c_double), ("init_ux_surface", C.c_double), ("periodic", C.c_uint32),
                 ("recon_mode", C.c_int32), ("seed", C.c_uint64), ("noise_amp", C.c_double),
-                ("fp16_scale", C.c_double), ("max_bodies", C.c_int32), ("host_body_update", C.c_int32)]
+                ("fp16_scale", C.c_double), ("max_bodies", C.c_int32), ("host_body_update", C.c_int32),
+                ("wall_vel", C.c_double * 3)]
 
 
 class lbm_body(C.Structure):
@@ -115,6 +116,8 @@ def make_config(d):
     c.fp16_scale = float(d.get("fp16_scale", 0.0))
     c.max_bodies = int(d.get("max_bodies", 4))
     c.host_body_update = int(d.get("host_body_update", 0))
+    for k in range(3):
+        c.wall_vel[k] = float(d.get("wall_vel", (0.0, 0.0, 0.0))[k])
     return c
 
 

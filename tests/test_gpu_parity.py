@@ -48,6 +48,8 @@ def oracle_for(cfg, threads=THREADS):
                eps=cfg.get("eps", 1e-2), periodic=cfg.get("periodic", 0), recon_mode=cfg.get("recon_mode", 0),
                threads=threads)
     o.init_basin(cfg["fill_height"], cfg.get("init_ux_surface", 0.0), cfg.get("seed", 0), cfg.get("noise_amp", 0.0))
+    if "wall_vel" in cfg:
+        o.set_wall_velocity(cfg["wall_vel"])
     return o
 
 
@@ -362,6 +364,27 @@ def test_free_sphere_floats_with_the_oracle(lbm):
     assert_force_close(Fg, Fo, 1e-2, atol=1e-7)
     np.testing.assert_allclose(bg["pos"], bo["pos"], atol=1e-5)
     np.testing.assert_allclose(bg["vel"], bo["vel"], atol=1e-7)
+
+
+def test_moving_wall_channel_with_free_sphere(lbm):
+    """The paper's free advection channel (Sec. 3.2): 60x40x30 cells,
+    periodic along x, the long sides moving no-slip walls at u = 0.01 along x,
+    a planar free surface at z = 19.5 under g = 1e-5, and a free sphere of
+    radius 6 and density 0.5 floating at the centre: 300 coupled steps on
+    both sides."""
+    cfg = dict(W.basin((60, 40, 30), 19.5, 0.8, 1e-5, periodic=1), wall_vel=(0.01, 0.0, 0.0))
+    body = _sphere(6.0, (30.0, 20.0, 19.5), density=0.5, fixed=0, dof=0x3F)
+    L, o = pair(lbm, cfg, [body])
+    say("moving-wall channel, free sphere, 300 coupled steps")
+    L.step(300)
+    o.step_coupled(300, [0x3F])
+    rel, mism = compare_pop(L, o, 1e-5, label="channel")
+    assert mism <= 10
+    bg, bo = L.get_body(0), o.get_body(0)
+    say("  sphere velocity gpu %s oracle %s" % (bg["vel"], bo["vel"]))
+    np.testing.assert_allclose(bg["pos"], bo["pos"], atol=1e-5)
+    np.testing.assert_allclose(bg["vel"], bo["vel"], atol=1e-7)
+    assert bo["vel"][0] > 1e-4  # the walls drag the liquid and the sphere along x
 
 
 @pytest.mark.parametrize("seed", [11, 12, 13])

@@ -303,5 +303,5 @@ def test_moving_walls_drag_the_liquid_to_their_velocity():
     o.set_wall_velocity((u, 0.0, 0.0))
     o.step(3000)
     vel, _ = velocity(o)
-    assert np.abs(vel[0] / u - 1.0).max() < 1e-4
+    assert np.abs(vel[0] / u - 1.0).max() < 1e-8
     assert np.abs(vel[1]).max() < 1e-12 and np.abs(vel[2]).max() < 1e-12
