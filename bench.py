@@ -221,6 +221,51 @@ def other_configs(steps, warmup):
     return out
 
 
+# The paper's sphere velocities in the free advection channel (Table
+# tab:velocities, g = 1e-5; None: not evaluated there because the empty
+# channel showed spurious currents).
+PAPER_TABLE_VELOCITIES = {
+    0.62: (1.1e-4, None, None, None),
+    0.8: (1.05e-4, 5.5e-5, 3.0e-5, 2.0e-5),
+    1.1: (1.01e-4, 5.15e-5, 2.8e-5, 1.3e-5),
+    1.7: (1.0e-4, 5.05e-5, 2.55e-5, 1.1e-5),
+}
+
+
+def free_advection(steps, window, every=100):
+    """Sec. 3.2 free advection test: for every (tau, u) of the paper's sweep,
+    the liquid starts at rest, the moving walls drive it, and the sphere's
+    x velocity is averaged over the last `window` steps.  The paper's values
+    are printed beside for context (its scheme differs in the readings listed
+    in the design notes)."""
+    from paper_1201_0351_amd import lbm
+    from paper_1201_0351_amd import workloads as W
+
+    rows = []
+    for tau in W.FREE_ADVECTION_TAUS:
+        for j, u in enumerate(W.FREE_ADVECTION_SPEEDS):
+            w = W.free_advection(tau, u)
+            L = lbm.Lattice(dict(w["lattice"], max_bodies=1))
+            b = dict(w["bodies"][0], dof=w["dof"])
+            L.set_body(0, b)
+            t0 = time.perf_counter()
+            L.step(steps - window)
+            vx = []
+            for _ in range(window // every):
+                L.step(every)
+                vx.append(float(L.get_body(0)["vel"][0]))
+            dt = time.perf_counter() - t0
+            L.close()
+            vm = sum(vx) / len(vx)
+            rows.append(dict(tau=tau, u=u, sphere_vx=vm, ratio=vm / u, vx_min=min(vx), vx_max=max(vx),
+                             paper=PAPER_TABLE_VELOCITIES[tau][j], seconds=round(dt, 2)))
+            print("tau %.2f u %.1e: sphere vx %.4e (ratio %.3f), paper %s" % (
+                tau, u, vm, vm / u, PAPER_TABLE_VELOCITIES[tau][j]), file=sys.stderr, flush=True)
+    return dict(experiment="free advection, 60x40x30 channel, moving walls, free sphere d = 12, rho_s 0.5, "
+                           "g 1e-5, surface z = 19.5, start at rest",
+                steps=steps, window=window, rows=rows)
+
+
 def cpu_baseline(target_s=15.0):
     """The FP64 oracle on the host cores: the same workload (128^3, box held at
     20 deg), timed over as many steps as fit in about target_s seconds."""
@@ -285,11 +330,16 @@ def main():
     ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-storage run")
     ap.add_argument("--no-extra", action="store_true",
                     help="only the timed runs (no host-update run, no righting moment)")
+    ap.add_argument("--free-advection", action="store_true",
+                    help="only run the paper's free advection sweep (Table tab:velocities) and print it as JSON")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain fill and device copy of MIB MiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.free_advection:
+        print(json.dumps(free_advection(steps=args.steps, window=max(100, args.steps // 4))))
         return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the workload is a single-GPU lattice); "

@@ -139,6 +139,31 @@ def config5(storage="fp32"):
                 bodies=[box((48, 24, 24), (128, 128, 125.6), 0.0, 0.6, vel=(us, 0, 0), fixed=0)])
 
 
+def sphere(radius, pos, density=0.5, vel=(0, 0, 0), omega=(0, 0, 0), fixed=1):
+    """A spherical body of the given radius centred at `pos`."""
+    r = float(radius)
+    return dict(half=(r, r, r), pos=tuple(float(p) for p in pos), quat=(1.0, 0.0, 0.0, 0.0), vel=tuple(vel),
+                omega=tuple(omega), density=density, fixed=fixed, shape=1)
+
+
+# The free advection test (Sec. 3.2, Table tab:velocities): relaxation times
+# and wall speeds of the paper's sweep.
+FREE_ADVECTION_TAUS = (0.62, 0.8, 1.1, 1.7)
+FREE_ADVECTION_SPEEDS = (1e-4, 5e-5, 2.5e-5, 1e-5)
+
+
+def free_advection(tau, u, storage="fp32"):
+    """The paper's free advection channel: 60x40x30 cells, periodic along x,
+    the long sides moving no-slip walls at u along x, g 1e-5, a planar free
+    surface at z = 19.5, and a free sphere of diameter 12 and density 0.5 at
+    the centre of the channel (the liquid starts at rest; the walls drive
+    it)."""
+    return dict(name="free_advection_60x40x30", dof=0x3F,
+                lattice=dict(basin((60, 40, 30), 19.5, tau, 1e-5, periodic=1, storage=storage),
+                             wall_vel=(float(u), 0.0, 0.0)),
+                bodies=[sphere(6.0, (30.0, 20.0, 19.5), density=0.5, fixed=0)])
+
+
 # ---------------------------------------------------------------------------
 # Random injected states for phase-isolated parity tests.  Values are rounded
 # to float32 so both sides see identical numbers.
