@@ -254,7 +254,7 @@ __device__ __forceinline__ bool bulk_cell(const Inst& I, const S* __restrict__ s
 
 // Workgroup b of nb (nb a multiple of 8, b % 8 the XCD it runs on) of one
 // instance's bulk grid.
-template <typename S, int TX>
+template <typename S, int TX, bool W>
 __device__ __forceinline__ void sweep_bulk(const Inst& I, int parity, int b, int nb) {
     constexpr int TY = 256 / TX;
     const int tiles_x = (I.nx + TX - 1) / TX, tiles_y = (I.ny + TY - 1) / TY;
@@ -290,9 +290,10 @@ __device__ __forceinline__ void sweep_bulk(const Inst& I, int parity, int b, int
     if (inb && (fl & ~KEEP_MASK)) I.flags[id] = fl & KEEP_MASK;
 
     // next to a moving wall the boundary sweep adds the wall term
-    const bool wall = I.wall_moving && ((!(I.periodic & 1) && (x == 0 || x == I.nx - 1)) ||
-                                        (!(I.periodic & 2) && (y == 0 || y == I.ny - 1)) ||
-                                        (!(I.periodic & 4) && (z == 0 || z == I.nz - 1)));
+    const bool wall = W && I.wall_moving &&
+                      ((!(I.periodic & 1) && (x == 0 || x == I.nx - 1)) ||
+                       (!(I.periodic & 2) && (y == 0 || y == I.ny - 1)) ||
+                       (!(I.periodic & 4) && (z == 0 || z == I.nz - 1)));
     bool defer = (type == IFC) || (type == LIQ && wall);
     if (type == LIQ && !wall) defer = bulk_cell<S>(I, src, dst, x, y, z, id, near);
     block_append<4>(defer, id, I.bnd, &C.n_bnd, I.list_cap, &C.overflow);
@@ -309,10 +310,11 @@ __device__ __forceinline__ int batch_instance(const int* __restrict__ off, int n
     return lo;
 }
 
-// At most 64 VGPRs, so that eight wavefronts fit per SIMD.
-template <typename S, int TX>
+// At most 64 VGPRs, so that eight wavefronts fit per SIMD.  W: the lattice
+// has moving walls (a variant without their test runs otherwise).
+template <typename S, int TX, bool W>
 __global__ __launch_bounds__(256, 8) void k_sweep_bulk(Inst I, int parity) {
-    sweep_bulk<S, TX>(I, parity, blockIdx.x, gridDim.x);
+    sweep_bulk<S, TX, W>(I, parity, blockIdx.x, gridDim.x);
 }
 
 // all instances of a batch in one launch (instance table in device memory;
@@ -322,7 +324,7 @@ __global__ __launch_bounds__(256) void kb_sweep_bulk(const Inst* __restrict__ ta
                                                      int parity) {
     const int k = batch_instance(off, n, blockIdx.x);
     const Inst I = tab[k];
-    sweep_bulk<S, TX>(I, parity, blockIdx.x - off[k], off[k + 1] - off[k]);
+    sweep_bulk<S, TX, true>(I, parity, blockIdx.x - off[k], off[k + 1] - off[k]);
 }
 
 // ---------------------------------------------------------------------------
@@ -347,7 +349,7 @@ __device__ __forceinline__ float osum(float v) {
 
 // Workgroup wg of nwg of one instance's boundary grid (wg is its
 // force-record slot).
-template <typename S>
+template <typename S, bool W>
 __device__ __forceinline__ void sweep_boundary(const Inst& I, int parity, int wg, int nwg) {
     const S* __restrict__ src = (const S*)pop_of(I, parity);
     S* __restrict__ dst = (S*)pop_of(I, parity ^ 1);
@@ -513,7 +515,7 @@ __device__ __forceinline__ void sweep_boundary(const Inst& I, int parity, int wg
                     r1 = (float)wrap_rel(xc1 - bpos[bk][1], I.ny, py);
                     r2 = (float)wrap_rel(xc2 - bpos[bk][2], I.nz, pz);
                 }
-                if (e < 0) cu = cxf * I.wall_u[0] + cyf * I.wall_u[1] + czf * I.wall_u[2];  // a moving wall
+                if (W && e < 0) cu = cxf * I.wall_u[0] + cyf * I.wall_u[1] + czf * I.wall_u[2];  // a moving wall
                 const float mw = 6.f * wi * rhox * cu;
                 d[j] = dxo + mw;
                 if (bk >= 0 && active) {
@@ -684,9 +686,9 @@ __device__ __forceinline__ void sweep_boundary(const Inst& I, int parity, int wg
     }
 }
 
-template <typename S>
+template <typename S, bool W>
 __global__ __launch_bounds__(256, 3) void k_sweep_boundary(Inst I, int parity) {
-    sweep_boundary<S>(I, parity, blockIdx.x, gridDim.x);
+    sweep_boundary<S, W>(I, parity, blockIdx.x, gridDim.x);
 }
 
 template <typename S>
@@ -696,7 +698,7 @@ __global__ __launch_bounds__(256, 3) void kb_sweep_boundary(const Inst* __restri
     const Inst I = tab[k];
     const int b = blockIdx.x - off[k];
     if (b >= boundary_blocks(I)) return;  // padding of the grid to a multiple of 8
-    sweep_boundary<S>(I, parity, b, boundary_blocks(I));
+    sweep_boundary<S, true>(I, parity, b, boundary_blocks(I));
 }
 
 // The sweep kernels go through the extended launch, which records the
@@ -711,7 +713,9 @@ int bulk_blocks(const Inst& I, int tile_x) {
 namespace {
 template <typename S, int TX>
 void bulk_one(const Inst& I, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    hipExtLaunchKernelGGL((k_sweep_bulk<S, TX>), dim3(bulk_blocks(I, TX)), dim3(256), 0, s, e0, e1, 0, I, parity);
+    const dim3 g(bulk_blocks(I, TX)), b(256);
+    if (I.wall_moving) hipExtLaunchKernelGGL((k_sweep_bulk<S, TX, true>), g, b, 0, s, e0, e1, 0, I, parity);
+    else hipExtLaunchKernelGGL((k_sweep_bulk<S, TX, false>), g, b, 0, s, e0, e1, 0, I, parity);
 }
 template <typename S, int TX>
 void bulk_batch(const BatchGrid& G, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
@@ -747,12 +751,20 @@ void launch_sweep_bulk_batch(const BatchGrid& G, int storage, int tile_x, int pa
 
 void launch_sweep_boundary(const Inst& I, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const dim3 g(boundary_blocks(I)), b(256);
+    const bool w = I.wall_moving != 0;
     switch (I.storage) {
-    case LBM_FP16_DEV: hipExtLaunchKernelGGL(k_sweep_boundary<__half>, g, b, 0, s, e0, e1, 0, I, parity); break;
-    case LBM_BF16_DEV:
-        hipExtLaunchKernelGGL(k_sweep_boundary<__hip_bfloat16>, g, b, 0, s, e0, e1, 0, I, parity);
+    case LBM_FP16_DEV:
+        if (w) hipExtLaunchKernelGGL((k_sweep_boundary<__half, true>), g, b, 0, s, e0, e1, 0, I, parity);
+        else hipExtLaunchKernelGGL((k_sweep_boundary<__half, false>), g, b, 0, s, e0, e1, 0, I, parity);
         break;
-    default: hipExtLaunchKernelGGL(k_sweep_boundary<float>, g, b, 0, s, e0, e1, 0, I, parity); break;
+    case LBM_BF16_DEV:
+        if (w) hipExtLaunchKernelGGL((k_sweep_boundary<__hip_bfloat16, true>), g, b, 0, s, e0, e1, 0, I, parity);
+        else hipExtLaunchKernelGGL((k_sweep_boundary<__hip_bfloat16, false>), g, b, 0, s, e0, e1, 0, I, parity);
+        break;
+    default:
+        if (w) hipExtLaunchKernelGGL((k_sweep_boundary<float, true>), g, b, 0, s, e0, e1, 0, I, parity);
+        else hipExtLaunchKernelGGL((k_sweep_boundary<float, false>), g, b, 0, s, e0, e1, 0, I, parity);
+        break;
     }
 }
 
