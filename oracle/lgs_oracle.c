@@ -115,6 +115,7 @@ typedef struct {
     long N;
     double tau, a[3], rho_g, eps;
     double wall_u[3]; /* velocity of the non-periodic faces (moving no-slip walls) */
+    double sigma;     /* surface tension; 0 = none */
     int per[3];
     int recon_mode;
     double *f, *fn;          /* [Q][N] absolute PDFs: current and next */
@@ -317,6 +318,11 @@ void ob_set_threads(ob_state *s, int n) { s->nthreads = n > 0 ? n : 1; }
 void ob_set_wall_velocity(ob_state *s, const double *u) {
     for (int k = 0; k < 3; ++k) s->wall_u[k] = u[k];
 }
+
+/* Surface tension sigma (Sec. 2.2, Laplace pressure): the gas pressure
+ * that an interface cell rebuilds its populations with becomes
+ * p_G + 2 sigma kappa, i.e. the gas density rho_G + 2 sigma kappa / cs^2. */
+void ob_set_surface_tension(ob_state *s, double sigma) { s->sigma = sigma; }
 
 long ob_num_cells(const ob_state *s) { return s->N; }
 
@@ -636,6 +642,70 @@ static double nb_fill(const ob_state *s, int x, int y, int z, int dx, int dy, in
     }
 }
 
+/* Fill of a cell as the normal sees it: LIQ 1, GAS 0, IF phi. */
+static double own_fill(const ob_state *s, long id) {
+    switch (s->type[id]) {
+    case T_LIQ: return 1.0;
+    case T_IF: return s->phi[id];
+    default: return 0.0;
+    }
+}
+
+/* Unit normal at a fluid cell: the central-difference normal of the
+ * reconstruction, divided by its length; zero where the fill is flat. */
+static void unit_normal(const ob_state *s, int x, int y, int z, double n[3]) {
+    double o = own_fill(s, IDX(s, x, y, z));
+    n[0] = 0.5 * (nb_fill(s, x, y, z, -1, 0, 0, o) - nb_fill(s, x, y, z, 1, 0, 0, o));
+    n[1] = 0.5 * (nb_fill(s, x, y, z, 0, -1, 0, o) - nb_fill(s, x, y, z, 0, 1, 0, o));
+    n[2] = 0.5 * (nb_fill(s, x, y, z, 0, 0, -1, o) - nb_fill(s, x, y, z, 0, 0, 1, o));
+    double len = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    if (len > 0.0)
+        for (int k = 0; k < 3; ++k) n[k] /= len;
+}
+
+/* Mean curvature of the free surface at interface cell (x,y,z), the second
+ * step after the normals (Sec. 2.2 leaves the stencil open; it names Pohl's
+ * approach of deriving kappa from the normals of a neighbourhood):
+ *   kappa = 1/2 div(n_hat),
+ * the divergence by central differences of the unit normals of the six axis
+ * neighbours.  A neighbour that is an obstacle or lies beyond a wall lends
+ * the cell's own normal.  With n pointing from the liquid to the gas, a
+ * liquid sphere of radius R has kappa = 1/R and a gas bubble -1/R. */
+static double curvature(const ob_state *s, int x, int y, int z) {
+    double nx[3];
+    unit_normal(s, x, y, z, nx);
+    double div = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double side[2];
+        for (int k = 0; k < 2; ++k) {
+            int d[3] = {0, 0, 0};
+            d[a] = k == 0 ? 1 : -1;
+            long n;
+            side[k] = nx[a];
+            if (nbr(s, x, y, z, d[0], d[1], d[2], &n) && s->type[n] != T_OBS) {
+                double nn[3];
+                int q[3] = {x + d[0], y + d[1], z + d[2]};
+                int dim[3] = {s->nx, s->ny, s->nz};
+                for (int c = 0; c < 3; ++c) q[c] = (q[c] + dim[c]) % dim[c];
+                unit_normal(s, q[0], q[1], q[2], nn);
+                side[k] = nn[a];
+            }
+        }
+        div += 0.5 * (side[0] - side[1]);
+    }
+    return 0.5 * div;
+}
+
+/* kappa of every interface cell of the current state (0 elsewhere). */
+void ob_curvature(const ob_state *s, double *out) {
+    for (int z = 0; z < s->nz; ++z)
+        for (int y = 0; y < s->ny; ++y)
+            for (int x = 0; x < s->nx; ++x) {
+                long id = IDX(s, x, y, z);
+                out[id] = s->type[id] == T_IF ? curvature(s, x, y, z) : 0.0;
+            }
+}
+
 /* ---------------------------------------------------------------------------
  * S2: stream + boundaries + collide for one LIQ/IF cell (Sec. 2.1-2.4).
  * Pull form of Eq. stream: f'_i(x) comes from s = x - c_i.
@@ -694,6 +764,9 @@ static void sweep_cell(ob_state *s, int x, int y, int z) {
      * zero tangential components only in exact arithmetic) does not decide
      * which links are rebuilt. */
     double nthr = NORMAL_TOL * ((fabs(nrm[0]) + fabs(nrm[1])) + fabs(nrm[2]));
+    /* gas density of the reconstruction, raised by the Laplace pressure */
+    double rg = s->rho_g;
+    if (t == T_IF && s->sigma != 0.0) rg += 2.0 * s->sigma * curvature(s, x, y, z) / CS2;
     double xc[3] = {x + 0.5, y + 0.5, z + 0.5};
     fp[0] = fx[0];
     for (int i = 1; i < Q; ++i) {
@@ -721,7 +794,7 @@ static void sweep_cell(ob_state *s, int x, int y, int z) {
             double cn = CX[i] * nrm[0] + CY[i] * nrm[1] + CZ[i] * nrm[2];
             if (s->recon_mode == 0 ? (cn < -nthr) : (cn <= nthr)) recon = 1;
         }
-        if (recon) fp[i] = feq(i, s->rho_g, ux) + feq(ib, s->rho_g, ux) - fx[ib];
+        if (recon) fp[i] = feq(i, rg, ux) + feq(ib, rg, ux) - fx[ib];
         else fp[i] = s->f[(long)i * N + src];
     }
     /* mass exchange (interface cells), on the state at t */

@@ -45,6 +45,8 @@ def lib():
         L.ob_set_body.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp, _dp, _dp, C.c_double, C.c_int]
         L.ob_set_body_shape.argtypes = [C.c_void_p, C.c_int, C.c_int]
         L.ob_set_wall_velocity.argtypes = [C.c_void_p, _dp]
+        L.ob_set_surface_tension.argtypes = [C.c_void_p, C.c_double]
+        L.ob_curvature.argtypes = [C.c_void_p, _dp]
         L.ob_get_body.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp, _dp]
         L.ob_step.argtypes = [C.c_void_p, C.c_int, C.c_int]
         L.ob_body_forces.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
@@ -162,6 +164,16 @@ class Oracle:
         """Velocity of the non-periodic faces (moving no-slip walls)."""
         a, p = _arr(u)
         lib().ob_set_wall_velocity(self._h, p)
+
+    def set_surface_tension(self, sigma):
+        """Surface tension: interface cells rebuild with rho_G + 2 sigma kappa / cs^2."""
+        lib().ob_set_surface_tension(self._h, float(sigma))
+
+    def curvature(self):
+        """Mean curvature kappa of every interface cell, [nz, ny, nx] (0 elsewhere)."""
+        out = np.zeros(self.shape)
+        lib().ob_curvature(self._h, out.ctypes.data_as(_dp))
+        return out
 
     def get_body(self, k):
         outs = [np.zeros(3), np.zeros(4), np.zeros(3), np.zeros(3)]

@@ -214,6 +214,51 @@ def wavy_surface_types(n, H, amp, seed, periodic=0):
     return t
 
 
+def droplet(n, radius, centre, liquid_inside=True, axes=3, sub=8):
+    """Cell types and fill levels of a liquid sphere in gas (axes=3), or of a
+    liquid cylinder along z (axes=2), on a periodic lattice; the complement
+    (a gas bubble in liquid) with liquid_inside=False.  The fill of a cell is
+    the fraction of sub^3 sample points inside the shape, with the distance
+    to the centre taken across the periodic faces.  Cells with fill 1 are
+    liquid, fill 0 gas, the rest interface; a gas cell among the 18 lattice
+    neighbours of a liquid cell is turned into an interface cell of fill 0,
+    so that the interface layer is closed.  Returns (types u8, phi f64),
+    both [nz, ny, nx]."""
+    nx, ny, nz = n
+    s = (np.arange(sub) + 0.5) / sub
+    inside = np.zeros((nz, ny, nx))
+    dims = (nx, ny, nz)
+    for a in s:
+        for b in s:
+            for c in s:
+                d2 = 0.0
+                for k, (o, g) in enumerate(zip((a, b, c), dims)):
+                    if k >= axes:
+                        continue
+                    q = np.arange(g) + o - centre[k]
+                    q = q - g * np.round(q / g)
+                    sh = [1, 1, 1]
+                    sh[2 - k] = g
+                    d2 = d2 + (q * q).reshape(sh)
+                inside += d2 <= radius * radius
+    phi = inside / sub ** 3
+    if not liquid_inside:
+        phi = 1.0 - phi
+    t = np.full((nz, ny, nx), IF, np.uint8)
+    t[phi >= 1.0] = LIQ
+    t[phi <= 0.0] = GAS
+    liq = t == LIQ
+    near = np.zeros_like(liq)
+    for dx in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dz in (-1, 0, 1):
+                if abs(dx) + abs(dy) + abs(dz) in (1, 2):
+                    near |= np.roll(liq, (dz, dy, dx), axis=(0, 1, 2))
+    t[(t == GAS) & near] = IF
+    phi = np.where(t == LIQ, 1.0, np.where(t == GAS, 0.0, phi))
+    return t, phi
+
+
 def random_state(n, types, seed, fill_lo=0.05, fill_hi=0.95, f_spread=0.1, threshold_frac=0.0, eps=1e-2):
     """Random populations (positive, about 1/19 each), fill levels and masses for
     the given cell types.  Interface fill levels are uniform in
