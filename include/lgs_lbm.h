@@ -108,6 +108,17 @@ typedef struct lbm_config {
     double wall_vel[3];        /* velocity of the non-periodic faces: moving no-slip
                                   walls (Eq. noslip with u_w = wall_vel; the paper's
                                   channel is driven by its long sides); 0 = static */
+    double surface_tension;    /* sigma >= 0, below 0.1 (Sec. 2.2, Laplace pressure):
+                                  interface cells rebuild their gas-side populations
+                                  with the gas pressure p_G + 2 sigma kappa, kappa the
+                                  mean curvature taken as half the divergence of the
+                                  unit surface normals (central differences of the
+                                  fill levels, then of the normals of the six axis
+                                  neighbours; an obstacle or wall neighbour lends the
+                                  cell's own normal).  kappa > 0 where the liquid is
+                                  convex (a droplet: 1/R).  0 = no surface tension;
+                                  sigma > 0 adds one small kernel over the interface
+                                  cells per step and 4 bytes per cell of workspace */
 } lbm_config;
 
 /* Body shapes (Sec. 2.3 maps any shape by its cell centres; the paper's

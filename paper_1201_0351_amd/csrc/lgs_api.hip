@@ -83,6 +83,7 @@ size_t layout(const lbm_config& c, Inst* I, char* base) {
     char* ax = take(4 * N);
     char* ru = take(N);
     char* no = take(N);
+    char* kp = take(c.surface_tension != 0.0 ? 4 * N : 0);
     char* cl = take(4 * (N / 32 + 1));
     char* cm = take(4 * N);
     char* l0 = take(4 * N);
@@ -106,6 +107,7 @@ size_t layout(const lbm_config& c, Inst* I, char* base) {
         I->aux = (float*)ax;
         I->rule = (uint8_t*)ru;
         I->nearo = (uint8_t*)no;
+        I->kap = c.surface_tension != 0.0 ? (float*)kp : nullptr;
         I->claim = (uint32_t*)cl;
         I->cmask = (uint32_t*)cm;
         I->cand = (int*)l0;
@@ -139,6 +141,7 @@ int validate(const lbm_config& c, int k) {
     if (c.host_body_update != 0 && c.host_body_update != 1) return bad("host_body_update must be 0 or 1");
     for (int a = 0; a < 3; ++a)
         if (!(std::fabs(c.wall_vel[a]) < 0.1)) return bad("wall_vel must be well below the lattice speed of sound");
+    if (!(c.surface_tension >= 0.0 && c.surface_tension < 0.1)) return bad("surface_tension must be in [0, 0.1)");
     const double n[3] = {(double)c.nx, (double)c.ny, (double)c.nz};
     for (int a = 0; a < 3; ++a)
         if (!(n[a] * std::fabs(c.accel[a]) < 0.1 / 3.0))
@@ -299,6 +302,7 @@ int32_t lbm_create(const lbm_config* cfgs, int32_t n_inst, void* d_workspace, si
         I.rho_g = (float)h.cfg.rho_gas;
         for (int a = 0; a < 3; ++a) I.wall_u[a] = (float)h.cfg.wall_vel[a];
         I.wall_moving = h.cfg.wall_vel[0] != 0.0 || h.cfg.wall_vel[1] != 0.0 || h.cfg.wall_vel[2] != 0.0;
+        I.lap = (float)(6.0 * h.cfg.surface_tension);
         I.scale = h.cfg.storage == LBM_FP16_DEV ? (float)h.cfg.fp16_scale : 1.f;
         I.inv_scale = 1.f / I.scale;
         I.eps = h.cfg.eps;
@@ -575,6 +579,9 @@ static int run_step_batched(lbm_ctx* c) {
     if (rc) return rc;
     launch_sweep_bulk_batch(BatchGrid{c->d_tab, c->d_bulk_off, n, c->bulk_total}, storage, c->tile_x, p, c->stream, e[0],
                             e[1]);
+    bool tension = false;
+    for (int k = 0; k < n; ++k) tension |= c->inst[k].dev.lap != 0.f;
+    if (tension) launch_curvature_batch(BatchGrid{c->d_tab, c->d_bnd_off, n, c->bnd_total}, p, c->stream);
     launch_sweep_boundary_batch(BatchGrid{c->d_tab, c->d_bnd_off, n, c->bnd_total}, storage, p, c->stream, e[2], e[3]);
     for (int g = 0; g < n; g += 64) {
         const int ng = std::min(64, n - g);
@@ -619,6 +626,7 @@ static int run_step(lbm_ctx* c, int mask) {
             int rc = timing_events(c, e);
             if (rc) return rc;
             launch_sweep_bulk(h.dev, p, c->tile_x, c->stream, e[0], e[1]);
+            if (h.dev.lap != 0.f) launch_curvature(h.dev, p, c->stream);
             launch_sweep_boundary(h.dev, p, c->stream, e[2], e[3]);
         } else if (mask & LBM_PHASE_CONVERT) {
             hipLaunchKernelGGL(k_copy_state, dim3((h.dev.N + 255) / 256), dim3(256), 0, c->stream, h.dev, p);

@@ -122,6 +122,7 @@ struct Inst {
     float rho_g;
     float wall_u[3];   // velocity of the non-periodic faces (moving no-slip walls)
     int wall_moving;   // wall_u != 0
+    float lap;         // 2 sigma / cs^2: Laplace density jump per unit curvature (0: no surface tension)
     float scale, inv_scale;  // storage scale (FP16), 1 otherwise
     double eps;
     void* pop[2];
@@ -132,6 +133,7 @@ struct Inst {
     float* share;
     float* aux;
     uint8_t* rule;
+    float* kap;        // mean curvature of the interface cells of this step (surface tension only)
     // Per cell: 1 where the cell may have a gas or obstacle neighbour.  Set
     // by the remap around covered and on uncovered cells, and by written
     // types; cleared by the bulk sweep for a liquid cell whose 18 sources it
@@ -591,6 +593,10 @@ int bulk_blocks(const Inst& I, int tile_x);
 // e0 / e1: optional events recorded at the start / end of the kernel itself
 void launch_sweep_bulk(const Inst& I, int parity, int tile_x, hipStream_t s, hipEvent_t e0 = nullptr,
                        hipEvent_t e1 = nullptr);
+// Mean curvature of the cells of this step's boundary list (surface tension
+// only; after the bulk sweep, before the boundary sweep).
+void launch_curvature(const Inst& I, int parity, hipStream_t s);
+void launch_curvature_batch(const BatchGrid& G, int parity, hipStream_t s);
 void launch_sweep_boundary(const Inst& I, int parity, hipStream_t s, hipEvent_t e0 = nullptr,
                            hipEvent_t e1 = nullptr);
 void launch_sweep_bulk_batch(const BatchGrid& G, int storage, int tile_x, int parity, hipStream_t s,

@@ -30,7 +30,7 @@ class lbm_config(C.Structure):
                 ("fill_height", C.c_double), ("init_ux_surface", C.c_double), ("periodic", C.c_uint32),
                 ("recon_mode", C.c_int32), ("seed", C.c_uint64), ("noise_amp", C.c_double),
                 ("fp16_scale", C.c_double), ("max_bodies", C.c_int32), ("host_body_update", C.c_int32),
-                ("wall_vel", C.c_double * 3)]
+                ("wall_vel", C.c_double * 3), ("surface_tension", C.c_double)]
 
 
 class lbm_body(C.Structure):
@@ -118,6 +118,7 @@ def make_config(d):
     c.host_body_update = int(d.get("host_body_update", 0))
     for k in range(3):
         c.wall_vel[k] = float(d.get("wall_vel", (0.0, 0.0, 0.0))[k])
+    c.surface_tension = float(d.get("surface_tension", 0.0))
     return c
 
 

@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    assert C.sizeof(lbm.lbm_config) == 4 * 4 + 8 + 24 + 8 * 4 + 4 + 4 + 8 + 8 + 8 + 4 + 4 + 24
+    assert C.sizeof(lbm.lbm_config) == 4 * 4 + 8 + 24 + 8 * 4 + 4 + 4 + 8 + 8 + 8 + 4 + 4 + 24 + 8
     # 17 doubles, then fixed, dof_mask and shape (uint32), padded to 8 bytes
     assert C.sizeof(lbm.lbm_body) == 8 * (3 + 3 + 4 + 3 + 3 + 1) + 4 * 3 + 4
 
