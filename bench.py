@@ -29,6 +29,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -266,6 +268,63 @@ def free_advection(steps, window, every=100):
                 steps=steps, window=window, rows=rows)
 
 
+LAPLACE_RADII = (8.0, 16.0, 24.0, 32.0)
+# D3Q19 rest weights in the link order of Sec. 2.1 (centre, six axis links,
+# twelve diagonals): the populations of fluid at rest with rho = 1
+LATTICE_WEIGHTS = (1.0 / 3.0,) + (1.0 / 18.0,) * 6 + (1.0 / 36.0,) * 12
+
+
+def laplace(steps, sigma=1e-3, n=128, every=200):
+    """Sec. 2.2 Laplace pressure on the GPU path: a resting liquid droplet of
+    radius R in gas on a periodic n^3 lattice (tau 1, no gravity, fills from
+    the sphere's volume fractions) relaxes to rho_L - rho_G = 6 sigma / R
+    (p = rho / 3).  For each radius the liquid density jump is averaged over
+    the last quarter of the run and set against 6 sigma / R_eq, R_eq the
+    radius of the liquid volume; the largest speed (spurious currents) is
+    reported beside."""
+    from paper_1201_0351_amd import lbm
+    from paper_1201_0351_amd import workloads as W
+
+    rows = []
+    for R in LAPLACE_RADII:
+        shape = (n, n, n)
+        t, phi = W.droplet(shape, R, (n / 2 + 0.3, n / 2 - 0.2, n / 2 + 0.1))
+        f = np.zeros((19,) + t.shape)
+        fl = (t == W.LIQ) | (t == W.IF)
+        for i, wi in enumerate(LATTICE_WEIGHTS):
+            f[i][fl] = wi
+        L = lbm.Lattice(dict(nx=n, ny=n, nz=n, tau=1.0, accel=(0.0, 0.0, 0.0), fill_height=0.0, periodic=7,
+                             surface_tension=sigma, max_bodies=1))
+        L.write(lbm.FIELD_FLAGS, t)
+        L.write(lbm.FIELD_POP, f)
+        L.write(lbm.FIELD_PHI, phi)
+        L.write(lbm.FIELD_MASS, np.where(t == W.IF, phi, 0.0))
+        t0 = time.perf_counter()
+        L.step(steps - steps // 4)
+        acc = []
+        for _ in range(max(1, (steps // 4) // every)):
+            L.step(every)
+            tt = L.types()
+            acc.append(float(L.read(lbm.FIELD_RHO)[tt == W.LIQ].mean() - 1.0))
+        L.sync()
+        dt = time.perf_counter() - t0
+        tt = L.types()
+        ph = L.phi()
+        vol = float((tt == W.LIQ).sum() + ph[tt == W.IF].sum())
+        req = (3.0 * vol / (4.0 * math.pi)) ** (1.0 / 3.0)
+        vel = L.read(lbm.FIELD_VEL)
+        fluid = (tt == W.LIQ) | (tt == W.IF)
+        umax = float(np.sqrt((vel ** 2).sum(axis=0))[fluid].max())
+        L.close()
+        jump = sum(acc) / len(acc)
+        rows.append(dict(radius=R, r_eq=round(req, 4), drho=jump, laplace=6.0 * sigma / req,
+                         ratio=jump / (6.0 * sigma / req), u_max=umax, seconds=round(dt, 2)))
+        print("R %.0f: rho_L - rho_G %.4e, 6 sigma / R_eq %.4e, ratio %.4f, u_max %.2e" % (
+            R, jump, 6.0 * sigma / req, jump / (6.0 * sigma / req), umax), file=sys.stderr, flush=True)
+    return dict(experiment="Laplace pressure of resting droplets, %d^3 periodic, tau 1, sigma %g" % (n, sigma),
+                steps=steps, rows=rows)
+
+
 def cpu_baseline(target_s=15.0):
     """The FP64 oracle on the host cores: the same workload (128^3, box held at
     20 deg), timed over as many steps as fit in about target_s seconds."""
@@ -332,11 +391,16 @@ def main():
                     help="only the timed runs (no host-update run, no righting moment)")
     ap.add_argument("--free-advection", action="store_true",
                     help="only run the paper's free advection sweep (Table tab:velocities) and print it as JSON")
+    ap.add_argument("--laplace", action="store_true",
+                    help="only run resting droplets with surface tension (Laplace's law) and print them as JSON")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain fill and device copy of MIB MiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.laplace:
+        print(json.dumps(laplace(steps=args.steps)))
         return
     if args.free_advection:
         print(json.dumps(free_advection(steps=args.steps, window=max(100, args.steps // 4))))
