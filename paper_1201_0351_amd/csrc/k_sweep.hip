@@ -6,7 +6,9 @@
 //                        f'_i = f_ibar(x) + 6 w_i rho_x c_i.u_w
 //   s gas              : Eq. reconstruct with this cell's own outgoing
 //                        f_ibar(x): f'_i = f_eq,i + f_eq,ibar - f_ibar(x) at
-//                        (rho_G, u_x)
+//                        (rho_G, u_x); with surface tension, interface
+//                        cells use rho_G + 2 sigma kappa / cs^2 (kappa from
+//                        k_tension.hip, computed just before this sweep)
 // Interface cells also rebuild links from the gas side (c_i.n < -1e-3|n|_1,
 // n = -grad phi), add the mass exchange of Sec. 2.2 to m and set phi = m/rho.
 // Collide: f = f' - (f' - f_eq(rho,u))/tau + F_i with F_i of Eq. forceterm
@@ -297,17 +299,6 @@ __device__ __forceinline__ void sweep_bulk(const Inst& I, int parity, int b, int
     bool defer = (type == IFC) || (type == LIQ && wall);
     if (type == LIQ && !wall) defer = bulk_cell<S>(I, src, dst, x, y, z, id, near);
     block_append<4>(defer, id, I.bnd, &C.n_bnd, I.list_cap, &C.overflow);
-}
-
-// instance k of a batch: off[k] <= block < off[k + 1]
-__device__ __forceinline__ int batch_instance(const int* __restrict__ off, int n, int block) {
-    int lo = 0, hi = n;  // off[lo] <= block < off[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (off[mid] <= block) lo = mid;
-        else hi = mid;
-    }
-    return lo;
 }
 
 // At most 64 VGPRs, so that eight wavefronts fit per SIMD.  W: the lattice
@@ -785,118 +776,6 @@ void launch_sweep_boundary_batch(const BatchGrid& G, int storage, int parity, hi
         break;
     default: hipExtLaunchKernelGGL(kb_sweep_boundary<float>, g, b, 0, s, e0, e1, 0, G.tab, G.off, G.n, parity); break;
     }
-}
-
-// ---------------------------------------------------------------------------
-// Surface tension (Sec. 2.2, Laplace pressure): mean curvature of every
-// interface cell of the boundary list, kappa = 1/2 div(n_hat), from the unit
-// normals of the cell's six axis neighbours (central differences of their
-// normals; each normal the central difference of the fill levels, as the
-// reconstruction's, divided by its length).  Eight lanes per cell: lane 0
-// takes the cell's own normal, lanes 1-6 the normal of neighbour +x, -x, +y,
-// -y, +z, -z, each from six independent flag and fill loads (L2 hits), in
-// double precision like the reconstruction's sign test; lane 0 gathers the
-// six components by shuffles.
-// ---------------------------------------------------------------------------
-namespace {
-__device__ __forceinline__ int axis_step(const Inst& I, int& X, int& Y, int& Z, int a, int d) {
-    if (a == 0) X = step_axis(X, d, I.nx, I.periodic & 1);
-    else if (a == 1) Y = step_axis(Y, d, I.ny, I.periodic & 2);
-    else Z = step_axis(Z, d, I.nz, I.periodic & 4);
-    return (X | Y | Z) >= 0 ? X + I.nx * (Y + I.ny * Z) : -1;
-}
-
-__device__ void curvature_list(const Inst& I, int parity, int wg, int nwg) {
-    const int nlist = min(I.ctl->cnt[parity].n_bnd, I.list_cap);
-    const float* __restrict__ phi_t = phi_of(I, parity);
-    const int l = threadIdx.x & 7;
-    const int cell = threadIdx.x >> 3;
-    for (int base = wg * 32; base < nlist; base += nwg * 32) {
-        const int k = base + cell;
-        const int id = I.bnd[k < nlist ? k : base];
-        const bool act = k < nlist && (I.flags[id] & TYPE_MASK) == IFC;
-        int x, y, z;
-        cell_coords(I, id, x, y, z);
-        // this lane's cell: the interface cell itself or one axis neighbour
-        // (ok = 0 beyond a wall or on an obstacle: the cell's own normal
-        // stands in for it)
-        int c = id, ok = 1;
-        if (l >= 1 && l <= 6) {
-            const int a = (l - 1) >> 1, d = (l & 1) ? 1 : -1;
-            int X = x, Y = y, Z = z;
-            c = axis_step(I, X, Y, Z, a, d);
-            ok = c >= 0;
-            if (ok) {
-                x = X;
-                y = Y;
-                z = Z;
-            } else {
-                c = id;
-            }
-        }
-        const int tc = I.flags[c] & TYPE_MASK;
-        const float pc = phi_t[c];
-        ok = ok && tc != OBS && l <= 6;
-        const double own = tc == LIQ ? 1.0 : tc == IFC ? (double)pc : 0.0;
-        double f[6];
-#pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            int X = x, Y = y, Z = z;
-            const int s = act && ok ? axis_step(I, X, Y, Z, j >> 1, (j & 1) ? 1 : -1) : -1;
-            double v = own;
-            if (s >= 0) {
-                const int t = I.flags[s] & TYPE_MASK;
-                const float p = phi_t[s];
-                v = t == LIQ ? 1.0 : t == GAS ? 0.0 : t == IFC ? (double)p : own;
-            }
-            f[j] = v;
-        }
-        double n[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) n[a] = 0.5 * (f[2 * a] - f[2 * a + 1]);
-        const double len = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-        if (len > 0.0) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) n[a] /= len;
-        }
-        // lane 1 + 2a + j (j = 0: +1, j = 1: -1 neighbour) offers component a
-        const int my_a = l >= 1 && l <= 6 ? (l - 1) >> 1 : 0;
-        const double mine = my_a == 0 ? n[0] : my_a == 1 ? n[1] : n[2];
-        const int g0 = lane_id() & ~7;
-        double div = 0.0;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const double vp = __shfl(mine, g0 + 1 + 2 * a);
-            const int op = __shfl(ok, g0 + 1 + 2 * a);
-            const double vm = __shfl(mine, g0 + 2 + 2 * a);
-            const int om = __shfl(ok, g0 + 2 + 2 * a);
-            const double sp = op ? vp : n[a], sm = om ? vm : n[a];
-            div += 0.5 * (sp - sm);
-        }
-        if (act && l == 0) I.kap[id] = (float)(0.5 * div);
-    }
-}
-}  // namespace
-
-__global__ __launch_bounds__(256) void k_curvature(Inst I, int parity) {
-    curvature_list(I, parity, blockIdx.x, gridDim.x);
-}
-
-__global__ __launch_bounds__(256) void kb_curvature(const Inst* __restrict__ tab, const int* __restrict__ off, int n,
-                                                    int parity) {
-    const int k = batch_instance(off, n, blockIdx.x);
-    const Inst I = tab[k];
-    const int b = blockIdx.x - off[k];
-    if (I.lap == 0.f || b >= boundary_blocks(I)) return;
-    curvature_list(I, parity, b, boundary_blocks(I));
-}
-
-void launch_curvature(const Inst& I, int parity, hipStream_t s) {
-    hipLaunchKernelGGL(k_curvature, dim3(boundary_blocks(I)), dim3(256), 0, s, I, parity);
-}
-
-void launch_curvature_batch(const BatchGrid& G, int parity, hipStream_t s) {
-    hipLaunchKernelGGL(kb_curvature, dim3(G.blocks), dim3(256), 0, s, G.tab, G.off, G.n, parity);
 }
 
 // Candidate scan without a sweep (conversion phase on injected fields).

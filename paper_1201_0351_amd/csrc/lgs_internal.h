@@ -267,6 +267,17 @@ __device__ __forceinline__ int nbr_index(const Inst& I, int x, int y, int z, int
     return X + I.nx * (Y + I.ny * Z);
 }
 
+// instance k of a batch: off[k] <= block < off[k + 1]
+__device__ __forceinline__ int batch_instance(const int* __restrict__ off, int n, int block) {
+    int lo = 0, hi = n;  // off[lo] <= block < off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= block) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 __device__ __forceinline__ void cell_coords(const Inst& I, int id, int& x, int& y, int& z) {
     x = id % I.nx;
     int r = id / I.nx;
