@@ -645,6 +645,42 @@ def test_surface_tension_droplet(lbm, storage, tol):
     np.testing.assert_allclose(L.mass()[iface], o.get_mass()[iface], atol=1e-5 if storage == "fp32" else 1e-2)
 
 
+def test_surface_tension_droplet_on_walls_and_body(lbm):
+    """A droplet against a static wall and a held box, with surface tension:
+    curvature next to obstacles and walls (their neighbours lend the cell's
+    own normal) on both sides; one step, then 20 more, against the oracle."""
+    n, sigma = (30, 28, 24), 2e-3
+    t, phi = W.droplet(n, 7.0, (7.3, 13.8, 12.1))
+    # no periodic faces: cells beyond x = 0 are wall; the droplet reaches x = 0
+    assert (t[:, :, 0] != 0).any()
+    f, _, _ = W.random_state(n, t, 52, f_spread=0.01)
+    state = (t, f, phi, np.where(t == 2, phi, 0.0))
+    cfg = dict(_droplet_cfg(n, sigma), periodic=0)
+    box = W.box((8, 8, 8), (17.5, 14.0, 12.0), 0.0, 0.5)
+    # the state first, then the body (a written flag field is taken as the
+    # mapping of the bodies already set)
+    L, o = pair(lbm, cfg)
+    _write_state(lbm, L, state)
+    _write_state(lbm, o, state)
+    L.set_body(0, box)
+    oracle_body(o, 0, box)
+    say("droplet on a wall and a box, sigma %g" % sigma)
+    L.step(1)
+    o.step(1)
+    tt = o.types()
+    assert (tt == 3).any()
+    assert np.array_equal(L.flags(), o.get_flags())
+    compare_pop(L, o, 1e-5, label="wall+box +1")
+    L.step(20)
+    o.step(20)
+    assert np.array_equal(L.flags(), o.get_flags())
+    compare_pop(L, o, 1e-5, label="wall+box +21")
+    Fg, Tg = L.body_forces(0)
+    Fo, To = o.body_forces(0)
+    assert_force_close(Fg, Fo, 1e-2, atol=1e-6)
+    assert_force_close(Tg, To, 1e-2, atol=1e-5)
+
+
 def test_surface_tension_batched_matches_single(lbm):
     """Two instances in one batched context, one with surface tension and
     one without: each advances exactly as it does alone."""
