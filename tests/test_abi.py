@@ -52,8 +52,13 @@ def test_workspace_size_and_validation():
     assert rc == 0 and n > 32 ** 3 * 19 * 4 * 2
     rc16, n16 = _ws(dict(base, storage="fp16"))
     assert rc16 == 0 and n16 < n
+    # surface tension adds one float per cell (the curvature), and only then
+    rcs, ns = _ws(dict(base, surface_tension=1e-3))
+    assert rcs == 0 and ns - n >= 32 ** 3 * 4
     for bad in (dict(tau=0.5), dict(tau=0.3), dict(accel=(0, 0, -2e-3)), dict(nx=0), dict(eps=-1.0),
-                dict(rho_gas=0.0), dict(storage="fp16", fp16_scale=3.0), dict(recon_mode=7)):
+                dict(rho_gas=0.0), dict(storage="fp16", fp16_scale=3.0), dict(recon_mode=7),
+                dict(surface_tension=-1e-3), dict(surface_tension=0.1), dict(surface_tension=float("nan")),
+                dict(wall_vel=(0.2, 0.0, 0.0))):
         rc, _ = _ws(dict(base, **bad))
         assert rc == -1, bad
         assert lbm.library().lbm_last_error().decode()
