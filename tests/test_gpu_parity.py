@@ -681,6 +681,37 @@ def test_surface_tension_droplet_on_walls_and_body(lbm):
     assert_force_close(Tg, To, 1e-2, atol=1e-5)
 
 
+def test_surface_tension_laplace_law_128(lbm):
+    """At the benchmark lattice size (128^3, periodic, at rest, tau 1): a
+    droplet of radius 24 with sigma = 1e-3 relaxes to the Laplace jump
+    rho_L - rho_G = 6 sigma / R_eq within 5 % (R_eq from the liquid volume),
+    a property that holds at any size; the oracle pins the same law at 24^3
+    and 32^3."""
+    n, R, sigma = (128, 128, 128), 24.0, 1e-3
+    t, phi = W.droplet(n, R, (64.3, 63.8, 64.1))
+    f = np.zeros((19,) + t.shape)
+    fl = (t == 1) | (t == 2)
+    # populations at rest, rho = 1: the D3Q19 weights
+    w = [1.0 / 3.0] + [1.0 / 18.0] * 6 + [1.0 / 36.0] * 12
+    for i in range(19):
+        f[i][fl] = w[i]
+    L = lbm.Lattice(dict(_droplet_cfg(n, sigma), tau=1.0, max_bodies=1))
+    _write_state(lbm, L, (t, f, phi, np.where(t == 2, phi, 0.0)))
+    say("128^3 droplet r 24, sigma %g, 3000 steps" % sigma)
+    L.step(2500)
+    acc = []
+    for _ in range(5):
+        L.step(100)
+        tt = L.types()
+        acc.append(L.read(lbm.FIELD_RHO)[tt == 1].mean() - 1.0)
+    ph = L.phi()
+    vol = (tt == 1).sum() + ph[tt == 2].sum()
+    req = (3.0 * vol / (4.0 * math.pi)) ** (1.0 / 3.0)
+    ratio = float(np.mean(acc)) / (6.0 * sigma / req)
+    say("  Laplace ratio %.4f (R_eq %.3f)" % (ratio, req))
+    assert ratio == pytest.approx(1.0, abs=0.05)
+
+
 def test_surface_tension_batched_matches_single(lbm):
     """Two instances in one batched context, one with surface tension and
     one without: each advances exactly as it does alone."""
