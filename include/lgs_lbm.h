@@ -199,7 +199,11 @@ int32_t lbm_body_forces(lbm_ctx* ctx, int32_t inst, int32_t body, double force[3
 
 /* Copy a field of one instance to / from host memory (synchronous).
  * bytes must equal cells * components * sizeof(dtype).  POP is the absolute
- * f_i; gas and obstacle cells hold unspecified populations. */
+ * f_i; gas and obstacle cells hold unspecified populations.  Writing FLAGS
+ * takes the written obstacle cells as the mapping of the bodies already set,
+ * at their current poses (an obstacle cell of a body that is not set is an
+ * error), and no remap follows until a body moves or is set again: to have
+ * the library map a body onto written fields, set it after writing them. */
 int32_t lbm_read_fields(lbm_ctx* ctx, int32_t inst, int32_t field, int32_t dtype, void* host_dst, size_t bytes);
 int32_t lbm_write_fields(lbm_ctx* ctx, int32_t inst, int32_t field, int32_t dtype, const void* host_src,
                          size_t bytes);
