@@ -20,6 +20,12 @@ reported only while the kernel source is the one that was profiled.
 run and compares the averaged -T_x with the FP64 oracle's values
 (tests/golden/righting_moment_128.json).  `cpu_baseline` times the FP64
 oracle on the host on a bounded sample of the same workload.
+
+Side experiments, each printed as JSON instead of the benchmark line:
+`--free-advection` (the sphere in the moving-wall channel, for every tau and
+wall speed of the paper's sweep), `--laplace` (resting droplets with surface
+tension against Laplace's law), `--copy-probe MIB` (a plain device copy that
+calibrates the HBM byte counters).
 """
 import argparse
 import hashlib
