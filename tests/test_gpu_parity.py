@@ -645,6 +645,24 @@ def test_surface_tension_droplet(lbm, storage, tol):
     np.testing.assert_allclose(L.mass()[iface], o.get_mass()[iface], atol=1e-5 if storage == "fp32" else 1e-2)
 
 
+def test_surface_tension_bubble(lbm):
+    """A gas bubble of radius 6 in liquid (negative curvature: the gas
+    pressure the interface cells rebuild with drops below rho_G), sigma
+    = 3e-3; 30 full steps against the oracle, flags exact."""
+    n, sigma = (28, 28, 28), 3e-3
+    t, phi = W.droplet(n, 6.0, (14.3, 13.8, 14.1), liquid_inside=False)
+    f, _, _ = W.random_state(n, t, 61, f_spread=0.01)
+    state = (t, f, phi, np.where(t == 2, phi, 0.0))
+    L, o = pair(lbm, _droplet_cfg(n, sigma))
+    _write_state(lbm, L, state)
+    _write_state(lbm, o, state)
+    say("bubble r 6, sigma %g" % sigma)
+    L.step(30)
+    o.step(30)
+    assert np.array_equal(L.flags(), o.get_flags())
+    compare_pop(L, o, 1e-5, label="bubble +30")
+
+
 def test_surface_tension_droplet_on_walls_and_body(lbm):
     """A droplet against a static wall and a held box, with surface tension:
     curvature next to obstacles and walls (their neighbours lend the cell's
