@@ -833,6 +833,28 @@ def test_graph_replay_matches_eager(lbm):
         assert_force_close(Fg, Fe, 1e-9, atol=1e-15)
 
 
+def test_graph_replay_with_surface_tension(lbm):
+    """The curvature pass inside a captured two-step graph: droplets with and
+    without surface tension, several replays with eager reads in between,
+    every replay bit for bit like the eager context."""
+    n = (32, 28, 24)
+    cfgs = [_droplet_cfg(n, 3e-3), _droplet_cfg(n, 0.0)]
+    G, E = [lbm.Lattice([dict(c, max_bodies=1) for c in cfgs]) for _ in range(2)]
+    for k in range(2):
+        st = _droplet_state(n, 7.0, 70 + k)
+        _write_state(lbm, G, st, k)
+        _write_state(lbm, E, st, k)
+    G.set_tuning(use_graph=1)
+    say("graph replay with surface tension vs eager")
+    for steps in (2, 4, 5, 6):
+        G.step(steps)
+        E.step(steps)
+        G.mass_total(inst=0)
+        for k in range(2):
+            assert np.array_equal(G.flags(k), E.flags(k)), (steps, k)
+            assert np.array_equal(G.pop(k), E.pop(k)), (steps, k)
+
+
 def test_autotune_keeps_state(lbm):
     """The autotuner sweeps the current state for every tile width without
     changing it: afterwards the context advances exactly like an untouched
