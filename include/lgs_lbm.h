@@ -208,12 +208,25 @@ int32_t lbm_read_fields(lbm_ctx* ctx, int32_t inst, int32_t field, int32_t dtype
 int32_t lbm_write_fields(lbm_ctx* ctx, int32_t inst, int32_t field, int32_t dtype, const void* host_src,
                          size_t bytes);
 
-/* Liquid mass sum_LIQ rho + sum_IF m (FP64 reduction on the device) and the
- * ledger: mass added to the fluid minus mass removed by remaps and
- * undistributable conversion excess.  total - ledger is conserved up to
+/* Liquid mass sum_LIQ rho + sum_IF m (FP64 reduction on the device in a
+ * fixed order: one partial per 4096 cells, then their sum, so the result
+ * does not depend on scheduling) and the ledger: mass added to the fluid
+ * minus mass removed by remaps and undistributable conversion excess.  total - ledger is conserved up to
  * round-off and moving-wall mass fluxes.  Synchronises. */
 int32_t lbm_mass_total(lbm_ctx* ctx, int32_t inst, double* total, double* ledger);
 int32_t lbm_set_ledger(lbm_ctx* ctx, int32_t inst, double ledger);
+
+/* lbm_mass_total without any use of the context's workspace or of device
+ * memory allocation, for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * kernels and same result bit for bit; the partial sums (one per 4096 cells)
+ * and the result live in a static device array of the library, 16384
+ * partials + 1 double (128 KiB) per GPU, kept until the process ends.
+ * Lattices of more than 16384 * 4096 = 67,108,864 cells: LBM_ERR_INVALID
+ * (use lbm_mass_total).  Every call on a GPU shares that array: calls that
+ * overlap on one GPU (several host threads, or streams of several contexts)
+ * race.  Synchronises. */
+int32_t lbm_mass_total_noalloc(lbm_ctx* ctx, int32_t inst, double* total, double* ledger);
 
 /* Counts of the last conversion phase: filled, emptied, gas->interface,
  * liquid->interface.  Synchronises. */

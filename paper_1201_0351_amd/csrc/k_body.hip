@@ -390,18 +390,19 @@ void launch_remap_batch(const Inst* tab, int n, int max_bodies, int storage, int
 // diagnostics
 // ---------------------------------------------------------------------------
 __global__ void k_zero_diag(Ctl* c) {
-    if (threadIdx.x == 0) {
-        c->mass_total = 0.0;
-        c->contacts = 0ull;
-    }
+    if (threadIdx.x == 0) c->contacts = 0ull;
 }
 
+// Partial liquid mass of chunk blockIdx.x (cells [b MASS_CHUNK, (b+1)
+// MASS_CHUNK)): every thread sums its cells in index order, then a fixed
+// tree over the workgroup.
 template <typename S>
-__global__ __launch_bounds__(256) void k_mass(Inst I, int parity) {
+__global__ __launch_bounds__(256) void k_mass_part(Inst I, int parity, double* __restrict__ part) {
     __shared__ double red[256];
     double acc = 0.0;
     const S* pop = (const S*)pop_of(I, parity);
-    for (int id = blockIdx.x * 256 + threadIdx.x; id < I.N; id += gridDim.x * 256) {
+    const int lo = blockIdx.x * MASS_CHUNK, hi = min(I.N, lo + MASS_CHUNK);
+    for (int id = lo + (int)threadIdx.x; id < hi; id += 256) {
         const int t = I.flags[id] & TYPE_MASK;
         if (t == LIQ) acc += 1.0 + (double)cell_drho<S>(I, pop, id);
         else if (t == IFC) acc += (double)I.m_hi[id] + (double)I.m_lo[id];
@@ -412,17 +413,32 @@ __global__ __launch_bounds__(256) void k_mass(Inst I, int parity) {
         if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicAdd(&I.ctl->mass_total, red[0]);
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-void launch_mass_total(const Inst& I, int parity, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_diag, dim3(1), dim3(64), 0, s, I.ctl);
-    const dim3 g(min(1024, (I.N + 255) / 256)), b(256);
-    switch (I.storage) {
-    case LBM_FP16_DEV: hipLaunchKernelGGL(k_mass<__half>, g, b, 0, s, I, parity); break;
-    case LBM_BF16_DEV: hipLaunchKernelGGL(k_mass<__hip_bfloat16>, g, b, 0, s, I, parity); break;
-    default: hipLaunchKernelGGL(k_mass<float>, g, b, 0, s, I, parity); break;
+// Sum of the n partials in a fixed order (one workgroup).
+__global__ __launch_bounds__(256) void k_mass_sum(const double* __restrict__ part, int n, double* __restrict__ out) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < n; k += 256) acc += part[k];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+void launch_mass_total(const Inst& I, int parity, double* part, double* out, hipStream_t s) {
+    const int n = mass_parts(I.N);
+    const dim3 g(n), b(256);
+    switch (I.storage) {
+    case LBM_FP16_DEV: hipLaunchKernelGGL(k_mass_part<__half>, g, b, 0, s, I, parity, part); break;
+    case LBM_BF16_DEV: hipLaunchKernelGGL(k_mass_part<__hip_bfloat16>, g, b, 0, s, I, parity, part); break;
+    default: hipLaunchKernelGGL(k_mass_part<float>, g, b, 0, s, I, parity, part); break;
+    }
+    hipLaunchKernelGGL(k_mass_sum, dim3(1), b, 0, s, part, n, out);
 }
 
 __global__ __launch_bounds__(256) void k_contacts(Inst I) {

@@ -11,12 +11,19 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "lgs_internal.h"
 
 using namespace lgs;
+
+// Scratch memory of lbm_mass_total_noalloc: the chunk partials of the mass
+// total (MASS_PARTS_MAX) and its result, one copy per GPU, held until the
+// process ends.  Host code never uses this name as an address: it uses the
+// device's copy looked up by scratch_setup.
+static __device__ __align__(256) double scratch[MASS_PARTS_MAX + 1];
 
 namespace {
 
@@ -32,6 +39,30 @@ int fail(int code, const std::string& msg) {
         hipError_t e_ = (expr);                                                               \
         if (e_ != hipSuccess) return fail(LBM_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
+
+// Address of `scratch` on each device (null until looked up).
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[MAX_DEVICES];
+
+// Look up device dev's copy of `scratch` once; dev must be the current device.
+int scratch_setup(int dev) {
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(LBM_ERR_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[dev]) return LBM_OK;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return fail(LBM_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch[dev] = (double*)p;
+    return LBM_OK;
+}
+
+double* scratch_of(int dev) {
+    if (dev < 0 || dev >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch[dev];
+}
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -93,6 +124,7 @@ size_t layout(const lbm_config& c, Inst* I, char* base) {
     char* l4 = take(4 * N);
     char* fb = take(sizeof(int) * BND_BLOCKS_MAX);
     char* fv = take(sizeof(double) * 6 * BND_BLOCKS_MAX);
+    char* mp = take(sizeof(double) * mass_parts((int)N));
     char* ct = take(sizeof(Ctl));
     char* bd = take(sizeof(DevBody) * MAXB);
     if (I) {
@@ -117,6 +149,7 @@ size_t layout(const lbm_config& c, Inst* I, char* base) {
         I->bnd = (int*)l4;
         I->frec_body = (int*)fb;
         I->frec_v = (double*)fv;
+        I->mass_part = (double*)mp;
         I->ctl = (Ctl*)ct;
         I->bodies = (DevBody*)bd;
         I->list_cap = (int)N;
@@ -158,6 +191,7 @@ int validate(const lbm_config& c, int k) {
 
 struct lbm_ctx {
     int n_inst = 0;
+    int device = 0;  // the device current at creation
     hipStream_t stream = nullptr;
     char* ws = nullptr;
     size_t ws_bytes = 0;
@@ -248,8 +282,13 @@ int32_t lbm_create(const lbm_config* cfgs, int32_t n_inst, void* d_workspace, si
     size_t need = 0;
     int rc = lbm_workspace_size(cfgs, n_inst, &need);
     if (rc) return rc;
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    rc = scratch_setup(dev);
+    if (rc) return rc;
     lbm_ctx* c = new lbm_ctx();
     c->n_inst = n_inst;
+    c->device = dev;
     c->stream = (hipStream_t)hip_stream;
     if (d_workspace) {
         if (ws_bytes < need) {
@@ -930,11 +969,32 @@ int32_t lbm_mass_total(lbm_ctx* c, int32_t inst, double* total, double* ledger) 
     int rc = check_inst(c, inst);
     if (rc) return rc;
     const Inst& I = c->inst[inst].dev;
-    launch_mass_total(I, c->parity, c->stream);
+    launch_mass_total(I, c->parity, I.mass_part, &I.ctl->mass_total, c->stream);
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(c->stream));
     double v[2];
     HIP_OK(hipMemcpy(&v[0], &I.ctl->mass_total, sizeof(double), hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(&v[1], &I.ctl->ledger, sizeof(double), hipMemcpyDeviceToHost));
+    if (total) *total = v[0];
+    if (ledger) *ledger = v[1];
+    return LBM_OK;
+}
+
+int32_t lbm_mass_total_noalloc(lbm_ctx* c, int32_t inst, double* total, double* ledger) {
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    const Inst& I = c->inst[inst].dev;
+    if (mass_parts(I.N) > MASS_PARTS_MAX)
+        return fail(LBM_ERR_INVALID, "mass_total_noalloc: more than " + std::to_string((long long)MASS_PARTS_MAX * MASS_CHUNK) +
+                                         " cells (the static scratch holds " + std::to_string(MASS_PARTS_MAX) +
+                                         " partial sums); use lbm_mass_total");
+    double* sp = scratch_of(c->device);
+    if (!sp) return fail(LBM_ERR_STATE, "mass_total_noalloc: scratch of the context's device not set up");
+    launch_mass_total(I, c->parity, sp, sp + MASS_PARTS_MAX, c->stream);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(c->stream));
+    double v[2];
+    HIP_OK(hipMemcpy(&v[0], sp + MASS_PARTS_MAX, sizeof(double), hipMemcpyDeviceToHost));
     HIP_OK(hipMemcpy(&v[1], &I.ctl->ledger, sizeof(double), hipMemcpyDeviceToHost));
     if (total) *total = v[0];
     if (ledger) *ledger = v[1];

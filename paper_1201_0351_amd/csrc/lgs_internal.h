@@ -156,6 +156,9 @@ struct Inst {
     // sums do not depend on scheduling.
     int* frec_body;
     double* frec_v;
+    // FP64 partial sums of the liquid-mass total, one per chunk of
+    // MASS_CHUNK cells (mass_parts(N) of them)
+    double* mass_part;
     int list_cap;
     Ctl* ctl;
     DevBody* bodies;
@@ -624,7 +627,14 @@ void launch_remap_batch(const Inst* tab, int n, int max_bodies, int storage, int
 void launch_convert_batch(const Inst* tab, int n, int storage, int parity, unsigned long long retire_mask,
                           unsigned long long integrate_mask, hipStream_t s);
 void launch_set_body(const Inst& I, int slot, const DevBody& b, hipStream_t s);
-void launch_mass_total(const Inst& I, int parity, hipStream_t s);
+// Liquid-mass total sum_LIQ rho + sum_IF m in two fixed-order passes: one
+// FP64 partial per chunk of MASS_CHUNK cells into part[0 .. mass_parts(N)),
+// then their sum in chunk order into *out.  The result does not depend on
+// scheduling.
+constexpr int MASS_CHUNK = 4096;
+constexpr int MASS_PARTS_MAX = 16384;  // chunks of the allocation-free variant
+__host__ __device__ inline int mass_parts(int N) { return (N + MASS_CHUNK - 1) / MASS_CHUNK; }
+void launch_mass_total(const Inst& I, int parity, double* part, double* out, hipStream_t s);
 void launch_contacts(const Inst& I, hipStream_t s);
 
 }  // namespace lgs

@@ -70,6 +70,7 @@ def library():
         "lbm_read_fields": [vp, i32, i32, i32, vp, sz],
         "lbm_write_fields": [vp, i32, i32, i32, vp, sz],
         "lbm_mass_total": [vp, i32, dp, dp],
+        "lbm_mass_total_noalloc": [vp, i32, dp, dp],
         "lbm_set_ledger": [vp, i32, C.c_double],
         "lbm_conversion_counts": [vp, i32, C.POINTER(C.c_int64)],
         "lbm_liq_gas_contacts": [vp, i32, C.POINTER(C.c_int64)],
@@ -301,6 +302,13 @@ class Lattice:
     def mass_total(self, inst=0):
         M, L = C.c_double(), C.c_double()
         _check(library().lbm_mass_total(self._h, inst, C.byref(M), C.byref(L)))
+        return M.value, L.value
+
+    def mass_total_noalloc(self, inst=0):
+        """lbm_mass_total with its partial sums in the library's static device
+        scratch (no use of the workspace, no allocation)."""
+        M, L = C.c_double(), C.c_double()
+        _check(library().lbm_mass_total_noalloc(self._h, inst, C.byref(M), C.byref(L)))
         return M.value, L.value
 
     def set_ledger(self, v, inst=0):
