@@ -127,6 +127,7 @@ typedef struct {
     int nb;
     ob_body b[OB_MAXB];
     int nthreads;
+    int stranded_rule;       /* 1: interface cells without a liquid neighbour empty (default) */
     long last_conv[4];       /* counts of the last conversion pass: F, E, NEW_G, NEW_L */
 } ob_state;
 
@@ -294,6 +295,7 @@ ob_state *ob_create(int nx, int ny, int nz, double tau, const double *a, double 
     s->mn = (double *)calloc(s->N, sizeof(double));
     s->phin = (double *)calloc(s->N, sizeof(double));
     s->nthreads = 1;
+    s->stranded_rule = 1;
     if (!s->f || !s->fn || !s->type || !s->bid || !s->m || !s->phi || !s->mn || !s->phin) return NULL;
     return s;
 }
@@ -312,6 +314,10 @@ void ob_destroy(ob_state *s) {
 }
 
 void ob_set_threads(ob_state *s, int n) { s->nthreads = n > 0 ? n : 1; }
+
+/* Switch the stranded-interface rule of the conversions (on by default);
+ * off keeps only the fill-level thresholds. */
+void ob_set_stranded_rule(ob_state *s, int on) { s->stranded_rule = on != 0; }
 
 /* Velocity of the lattice's non-periodic faces: moving no-slip walls
  * (Eq. noslip with u_w; the paper's channel is driven by its long sides). */
@@ -846,7 +852,12 @@ static void sweep(ob_state *s) {
  * S4: free-surface conversions on the state at t+1 (Sec. 2.2; the paper gives
  * the thresholds -eps / 1+eps, forbids direct gas<->liquid transitions and
  * initialises new interface cells at phi 0 or 1; the rest is this reading):
- *  1. F = IF with phi >= 1+eps (filled), E = IF with phi <= -eps (emptied).
+ *  1. F = IF with phi >= 1+eps (filled), E = IF with phi <= -eps (emptied),
+ *     and also E = IF not in F with no liquid cell among its 18 neighbours
+ *     (a stranded interface cell: the paper gives no rule for it; without
+ *     one a droplet of interface cells cut off from the liquid keeps
+ *     rebuilding all its gas-side links from its own populations and can
+ *     reach a negative density).
  *  2. Filling wins: an E cell touching an F cell stays interface.
  *  3. GAS neighbours of F become IF: f = f_eq(mean rho, mean u) over the
  *     neighbours that were LIQ/IF and are not emptying; m = 0.
@@ -869,6 +880,15 @@ static void convert(ob_state *s) {
         if (s->type[id] != T_IF) continue;
         if (s->phi[id] >= 1.0 + s->eps) c[id] = C_FILL;
         else if (s->phi[id] <= -s->eps) c[id] = C_EMPTY;
+        else if (s->stranded_rule) {
+            int x, y, z, liq = 0;
+            coords(s, id, &x, &y, &z);
+            for (int i = 1; i < Q && !liq; ++i) {
+                long n;
+                if (nbr(s, x, y, z, CX[i], CY[i], CZ[i], &n) && s->type[n] == T_LIQ) liq = 1;
+            }
+            if (!liq) c[id] = C_EMPTY;
+        }
     }
     /* filling wins */
     unsigned char *keep = (unsigned char *)calloc(N, 1);

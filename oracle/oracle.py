@@ -41,6 +41,7 @@ def lib():
                                 C.c_int, C.c_int]
         L.ob_destroy.argtypes = [C.c_void_p]
         L.ob_set_threads.argtypes = [C.c_void_p, C.c_int]
+        L.ob_set_stranded_rule.argtypes = [C.c_void_p, C.c_int]
         L.ob_init_basin.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_uint64, C.c_double]
         L.ob_set_body.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp, _dp, _dp, C.c_double, C.c_int]
         L.ob_set_body_shape.argtypes = [C.c_void_p, C.c_int, C.c_int]
@@ -159,6 +160,11 @@ class Oracle:
             raise ValueError("bad body index")
         if shape is not None and lib().ob_set_body_shape(self._h, int(k), int(shape)) != 0:
             raise ValueError("bad body shape")
+
+    def set_stranded_rule(self, on):
+        """Interface cells with no liquid neighbour empty at the conversions
+        (on by default); off keeps only the fill-level thresholds."""
+        lib().ob_set_stranded_rule(self._h, int(bool(on)))
 
     def set_wall_velocity(self, u):
         """Velocity of the non-periodic faces (moving no-slip walls)."""

@@ -208,6 +208,7 @@ def test_new_interface_cell_from_gas_takes_mean_density_and_velocity():
              (2, 1, 2): (LIQ, 1.0),
              (2, 2, 1): (LIQ, 1.0),
              (2, 3, 3): (IF, 0.5),
+             (2, 4, 4): (LIQ, 1.0),  # liquid next to (2, 3, 3) only: not stranded
              (3, 3, 2): (IF, -0.3)}  # emptied, not next to the filled cell
     for (x, y, z), (ty, ph) in cells.items():
         t[z, y, x] = ty
@@ -232,3 +233,59 @@ def test_new_interface_cell_from_gas_takes_mean_density_and_velocity():
     assert np.allclose(C.T.astype(float) @ fg / fg.sum(), u_bar, atol=1e-14)
     # the emptied cell turned gas and its liquid neighbours (none here) stay
     assert o.types()[2, 3, 3] == GAS
+
+
+def _isolated_cell(rule):
+    """One interface cell at rest in gas (all 18 neighbours gas, no gravity),
+    f_0 = 1.2 and the other populations 0.075 w_i (rho = 1.25, u = 0)."""
+    n = 5
+    o = Oracle(n, n, n, 0.526, accel=(0, 0, 0))
+    o.set_stranded_rule(rule)
+    t = np.zeros((n, n, n), np.uint8)
+    t[2, 2, 2] = IF
+    f = np.zeros((19, n, n, n))
+    f[:, 2, 2, 2] = 0.075 * WTS
+    f[0, 2, 2, 2] = 1.2
+    phi = np.zeros((n, n, n))
+    phi[2, 2, 2] = 0.02
+    o.set_flags(t)
+    o.set_f(f)
+    o.set_phi(phi)
+    o.set_mass(phi * 1.25)
+    return o
+
+
+def test_stranded_interface_cell_empties_before_its_density_turns_negative():
+    """Interface cells with no liquid neighbour (the reading taken for a case
+    the paper leaves open).  An isolated interface cell at rest rebuilds all
+    18 links from the gas (Eq. reconstruct with rho_G = 1, u = 0):
+      rho' = f_0 + sum_i (2 w_i - f_ibar) = 2 f_0 - rho + 4/3,
+    and BGK leaves f_0 <- (1 - omega) f_0 + omega rho'/3 (f_eq,0 = rho/3).
+    With f_0 = 1.2, rho = 1.25, omega = 1/0.526:
+      step 1: rho_1 = 2.4833..., f_0 = 0.49235...
+      step 2: rho_2 = 2 (0.49235...) - 2.4833... + 4/3 = -0.1653...
+    Without a rule the cell stays interface (phi = 0.025 / 2.48 is inside the
+    thresholds) and the second step's sweep computes a negative density.  With the
+    stranded rule it is emptied at the end of step 1: it turns gas, its mass
+    m = 0.025 leaves the fluid to the ledger (no interface neighbour
+    receives it), and nothing negative is ever computed."""
+    om = 1.0 / 0.526
+    rho1 = 2 * 1.2 - 1.25 + 4.0 / 3.0
+    f01 = (1 - om) * 1.2 + om * rho1 / 3.0
+    rho2 = 2 * f01 - rho1 + 4.0 / 3.0
+    assert rho2 < -0.16
+    o = _isolated_cell(False)
+    o.step(1)
+    assert o.types()[2, 2, 2] == IF
+    assert o.get_f()[:, 2, 2, 2].sum() == pytest.approx(rho1, abs=1e-12)
+    assert o.get_f()[0, 2, 2, 2] == pytest.approx(f01, abs=1e-12)
+    o.step(1, PH_SWEEP)  # the second step's sweep (its conversions would empty the cell: phi < -eps)
+    assert o.get_f()[:, 2, 2, 2].sum() == pytest.approx(rho2, abs=1e-12)
+    o = _isolated_cell(True)
+    o.step(1)
+    assert o.types()[2, 2, 2] == GAS
+    M, led = o.mass_total()
+    assert M == 0.0 and led == pytest.approx(-0.025, abs=1e-15)
+    assert o.last_conversions()["emptied"] == 1
+    o.step(5)
+    assert (o.types() == GAS).all()
