@@ -127,7 +127,7 @@ typedef struct {
     int nb;
     ob_body b[OB_MAXB];
     int nthreads;
-    int stranded_rule;       /* 1: interface cells without a liquid neighbour empty (default) */
+    int stranded_rule;       /* 1: stranded interface cells empty at the conversions (default) */
     long last_conv[4];       /* counts of the last conversion pass: F, E, NEW_G, NEW_L */
 } ob_state;
 
@@ -853,11 +853,14 @@ static void sweep(ob_state *s) {
  * the thresholds -eps / 1+eps, forbids direct gas<->liquid transitions and
  * initialises new interface cells at phi 0 or 1; the rest is this reading):
  *  1. F = IF with phi >= 1+eps (filled), E = IF with phi <= -eps (emptied),
- *     and also E = IF not in F with no liquid cell among its 18 neighbours
- *     (a stranded interface cell: the paper gives no rule for it; without
- *     one a droplet of interface cells cut off from the liquid keeps
- *     rebuilding all its gas-side links from its own populations and can
- *     reach a negative density).
+ *     and also E = IF not in F that is stranded: no liquid cell among its 18
+ *     neighbours, and no interface neighbour that has one (a droplet or film
+ *     of interface cells cut off from the liquid; the outer cells of a
+ *     two-cell-thick curved surface reach liquid through an interface
+ *     neighbour and are not stranded).  The paper gives no rule for such
+ *     cells; without one an isolated interface cell keeps rebuilding its
+ *     gas-side links from its own populations and can reach a negative
+ *     density.
  *  2. Filling wins: an E cell touching an F cell stays interface.
  *  3. GAS neighbours of F become IF: f = f_eq(mean rho, mean u) over the
  *     neighbours that were LIQ/IF and are not emptying; m = 0.
@@ -876,20 +879,32 @@ static void convert(ob_state *s) {
     double *ex = (double *)calloc(N, sizeof(double));
     double *sh = (double *)calloc(N, sizeof(double));
     long cnt[4] = {0, 0, 0, 0};
+    /* interface cells with a liquid neighbour */
+    unsigned char *lnb = (unsigned char *)calloc(N, 1);
+    for (long id = 0; id < N; ++id) {
+        if (s->type[id] != T_IF) continue;
+        int x, y, z;
+        coords(s, id, &x, &y, &z);
+        for (int i = 1; i < Q && !lnb[id]; ++i) {
+            long n;
+            if (nbr(s, x, y, z, CX[i], CY[i], CZ[i], &n) && s->type[n] == T_LIQ) lnb[id] = 1;
+        }
+    }
     for (long id = 0; id < N; ++id) {
         if (s->type[id] != T_IF) continue;
         if (s->phi[id] >= 1.0 + s->eps) c[id] = C_FILL;
         else if (s->phi[id] <= -s->eps) c[id] = C_EMPTY;
-        else if (s->stranded_rule) {
-            int x, y, z, liq = 0;
+        else if (s->stranded_rule && !lnb[id]) {
+            int x, y, z, near = 0;
             coords(s, id, &x, &y, &z);
-            for (int i = 1; i < Q && !liq; ++i) {
+            for (int i = 1; i < Q && !near; ++i) {
                 long n;
-                if (nbr(s, x, y, z, CX[i], CY[i], CZ[i], &n) && s->type[n] == T_LIQ) liq = 1;
+                if (nbr(s, x, y, z, CX[i], CY[i], CZ[i], &n) && s->type[n] == T_IF && lnb[n]) near = 1;
             }
-            if (!liq) c[id] = C_EMPTY;
+            if (!near) c[id] = C_EMPTY;
         }
     }
+    free(lnb);
     /* filling wins */
     unsigned char *keep = (unsigned char *)calloc(N, 1);
     for (long id = 0; id < N; ++id) {

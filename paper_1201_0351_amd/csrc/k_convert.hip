@@ -1,36 +1,36 @@
 // k_convert.hip -- free-surface cell conversions (Sec. 2.2) on the state at
 // t+1, driven by the candidate list the sweep built, plus the end of a step.
 //
-// One workgroup of 1024 threads runs the phases one after the other,
-// separated by workgroup barriers (candidate lists are short: a few to a few
-// thousand cells per step).  Per-cell work is spread over a 32-lane group
-// (lane i looks at neighbour x + c_i, or population i), so a cell costs a
-// few dependent memory round trips, not a serial walk over its neighbours.
-// Each phase is a function of the state before it, so the result does not
-// depend on the order of the (atomically appended) lists:
-//   forces  the boundary sweep's per-workgroup momentum-exchange records are
-//           summed per body in slot order (fixed-order FP64 reduction); the
-//           records are loaded before the claims and summed after them
-//   bodies  (last wavefront, beside new-gas) retire the step's body moves;
-//           free bodies take the rigid-body update from the reduced force
-//           and torque
-//   claim   per candidate: a filled cell (phi >= 1+eps) records its excess
-//           m - rho and claims its gas neighbours as new interface cells; an
-//           emptied cell (phi <= -eps) touching a filled one stays interface
-//           (filling wins), otherwise it records its excess m and claims its
-//           liquid neighbours as new interface cells (m = rho).  Claims go
-//           through a bitmap, so every new cell is listed once.
-//   newgas  each new cell from gas: f = f_eq(mean rho, mean u) over its
-//           neighbours that are liquid or interface and not emptying, m = 0
-//   share   per converted cell: count the neighbours that are interface after
-//           the conversion (a function of the flags, marks and claims), divide
-//           the excess among them and list them as receivers; with none the
-//           excess leaves the fluid (ledger).
-//   commit  receivers add the shares of their converted neighbours in link
-//           order i = 1..18 and recompute phi = m / rho; converted and new
-//           cells take their new types.  Converted cells keep their mark until
-//           the next sweep clears it.
-//   finish  clear the other parity's counters.
+// Three launches over the whole chip, each a pure function of the state the
+// launch before it left, so the result does not depend on the order of the
+// (atomically appended) lists or on scheduling.  Per-cell work is spread
+// over a 32-lane group (lane i looks at neighbour x + c_i, or population i):
+//   claim   (one group per candidate) a filled cell (phi >= 1+eps) records
+//           its excess m - rho and claims its gas neighbours as new
+//           interface cells; an emptied cell (phi <= -eps) touching a filled
+//           one stays interface (filling wins: its empty mark is dropped),
+//           otherwise it records its excess m and claims its liquid
+//           neighbours as new interface cells (m = rho).  Claims go through a
+//           bitmap, so every new cell is listed once.  A stranded interface
+//           cell (no liquid neighbour, and no interface neighbour that has
+//           one) empties as well, unless a neighbour fills.
+//           The last workgroup of the grid instead sums the boundary sweep's
+//           per-workgroup momentum-exchange records per body in slot order
+//           (fixed-order FP64 reduction), retires the step's body moves and
+//           gives free bodies the rigid-body update.
+//   middle  (one group per new cell from gas) f = f_eq(mean rho, mean u) over
+//           its neighbours that are liquid or interface and not emptying,
+//           m = 0; (one thread per new cell from liquid) m = rho, phi = 1;
+//           (one group per converted cell) count the neighbours that are
+//           interface after the conversion (a function of the flags, marks
+//           and claims), divide the excess among them and note this cell in
+//           each receiver's link mask; with none the excess leaves the fluid
+//           (ledger).
+//   commit  converted and new cells take their new types; receivers add the
+//           shares of their converted neighbours in link order i = 1..18 and
+//           recompute phi = m / rho.  Converted cells keep their mark until
+//           the next sweep clears it.  The other parity's counters are
+//           cleared for the next step.
 #include <cstddef>
 
 #include "lgs_internal.h"
@@ -39,33 +39,26 @@ namespace lgs {
 
 namespace {
 
-constexpr int CONV_THREADS = 1024;
+constexpr int CT = 256;      // threads per workgroup of the conversion kernels
+constexpr int CG = CT / 32;  // 32-lane groups per workgroup
+constexpr int CW = CT / 64;  // wavefronts per workgroup
 
 __device__ __forceinline__ bool claim(uint32_t* bits, int id) {
     const uint32_t m = 1u << (id & 31);
     return (atomicOr(bits + (id >> 5), m) & m) == 0;
 }
 __device__ __forceinline__ bool claimed(const uint32_t* bits, int id) {
-    return (__hip_atomic_load(bits + (id >> 5), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> (id & 31)) & 1u;
-}
-__device__ __forceinline__ int load_count(int* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (bits[id >> 5] >> (id & 31)) & 1u;
 }
 // Clear the whole bitmap word of a claimed cell with a plain store: for use
-// only where every bit set in the bitmap is being cleared in the same phase
+// only where every bit set in the bitmap is being cleared in the same launch
 // and none is read or set there.
 __device__ __forceinline__ void unclaim_word(uint32_t* bits, int id) { bits[id >> 5] = 0u; }
 // add the number of calling lanes with `on` set to *cnt (one atomic per
-// wavefront)
+// wavefront; every lane of the wavefront calls it)
 __device__ __forceinline__ void wave_count(bool on, int* cnt) {
     const unsigned long long m = __ballot(on);
     if (m && (threadIdx.x & 63) == __ffsll((long long)m) - 1) atomicAdd(cnt, __popcll(m));
-}
-
-__device__ __forceinline__ void push(int* list, int* cnt, int cap, int* overflow, int id) {
-    const int p = atomicAdd(cnt, 1);
-    if (p < cap) list[p] = id;
-    else atomicOr(overflow, 1);
 }
 
 template <typename S>
@@ -104,24 +97,10 @@ __device__ __forceinline__ void add_comp(float& hi, float& lo, float v) {
     hi = h;
 }
 
-__device__ __forceinline__ bool has_fill_neighbour(const Inst& I, int x, int y, int z) {
-    for (int i = 1; i < Q; ++i) {
-        const int nb = nbr_index(I, x, y, z, cx(i), cy(i), cz(i));
-        if (nb >= 0 && (I.flags[nb] & MARK_FILL)) return true;
-    }
-    return false;
-}
-
-// an interface cell that will become gas in this conversion phase
-__device__ __forceinline__ bool empties(const Inst& I, int id, uint8_t f) {
-    if (!(f & MARK_EMPTY)) return false;
-    int x, y, z;
-    cell_coords(I, id, x, y, z);
-    return !has_fill_neighbour(I, x, y, z);
-}
-
-// type of a neighbour after this conversion phase (flags, marks and claims
-// are not modified while the share kernel runs)
+// Type of a cell after this conversion phase, read between the claim and
+// the commit launches: the claim launch has dropped the empty mark of every
+// emptied cell that filling overrides, so the marks name exactly the cells
+// that convert, and the claim bitmap the new interface cells.
 __device__ __forceinline__ int post_type(const Inst& I, int id) {
     const uint8_t f = I.flags[id];
     const int t = f & TYPE_MASK;
@@ -129,10 +108,6 @@ __device__ __forceinline__ int post_type(const Inst& I, int id) {
     if ((t == GAS || t == LIQ) && claimed(I.claim, id)) return IFC;
     return t;
 }
-
-#define BLOCK_LOOP(k, n) for (int k = threadIdx.x; k < (n); k += blockDim.x)
-
-}  // namespace
 
 // group-aggregated append (one atomic per group)
 __device__ __forceinline__ void g_push(bool pred, int id, int* list, int* cnt, int cap, int* overflow) {
@@ -156,196 +131,17 @@ __device__ __forceinline__ int lane_nbr(const Inst& I, int x, int y, int z) {
     return nbr_index(I, x, y, z, lane_c(CXP, i), lane_c(CYP, i), lane_c(CZP, i));
 }
 
-// claim: one 32-lane group per candidate, lane i looks at neighbour x + c_i.
-template <typename S>
-__device__ __forceinline__ void phase_claim(const Inst& I, int parity, int g0, int ngroups) {
-    StepCounters& C = I.ctl->cnt[parity];
-    const int n = min(load_count(&C.n_cand), I.list_cap);
-    const int i = g_lane();
-    for (int k = g0; k < n; k += ngroups) {
-        const int id = I.cand[k];
-        const uint8_t fl = I.flags[id];
-        int x, y, z;
-        cell_coords(I, id, x, y, z);
-        const int nb = lane_nbr(I, x, y, z);
-        const uint8_t nf = nb >= 0 ? I.flags[nb] : 0;
-        if (fl & MARK_FILL) {
-            if (i == 0) {
-                const float dr = I.aux[id];  // rho - 1 left by the sweep
-                I.share[id] = (float)(((double)I.m_hi[id] - 1.0) + ((double)I.m_lo[id] - (double)dr));
-            }
-            const bool take = nb >= 0 && (nf & TYPE_MASK) == GAS && claim(I.claim, nb);
-            g_push(take, nb, I.newg, &C.n_newg, I.list_cap, &C.overflow);
-        } else if (fl & MARK_EMPTY) {
-            if (g_ballot(nb >= 0 && (nf & MARK_FILL))) {
-                if (i == 0) I.flags[id] = fl & (uint8_t)~MARK_EMPTY;  // filling wins: stays interface
-                continue;
-            }
-            if (i == 0) I.share[id] = (float)((double)I.m_hi[id] + (double)I.m_lo[id]);
-            const bool take = nb >= 0 && (nf & TYPE_MASK) == LIQ && claim(I.claim, nb);
-            g_push(take, nb, I.newl, &C.n_newl, I.list_cap, &C.overflow);
-        }
-    }
-}
+__device__ __forceinline__ int list_len(const int* cnt, int cap) { return min(*cnt, cap); }
+// converted cells after the claim launch: the sweep's candidates, then the
+// stranded cells that empty
+__device__ __forceinline__ int cand_len(const StepCounters& C, int cap) { return min(C.n_cand + C.n_se, cap); }
 
-// New interface cells from gas: equilibrium of the mean density and
-// velocity of their liquid / interface neighbours that are not emptying
-// (one group per new cell, lane j looks at neighbour j); m = 0.  New
-// interface cells from liquid (one thread each): m = rho, phi = 1.
-template <typename S>
-__device__ __forceinline__ void phase_newgas(const Inst& I, int parity, int g0, int ngroups) {
-    StepCounters& C = I.ctl->cnt[parity];
-    const int n = min(load_count(&C.n_newg), I.list_cap);
-    S* pop = (S*)pop_of(I, parity ^ 1);
-    float* phi = phi_of(I, parity ^ 1);
-    const int j = g_lane();
-    for (int k = g0; k < n; k += ngroups) {
-        const int g = I.newg[k];
-        int gx, gy, gz;
-        cell_coords(I, g, gx, gy, gz);
-        const int nb = lane_nbr(I, gx, gy, gz);
-        bool use = false;
-        if (nb >= 0) {
-            const uint8_t f = I.flags[nb];
-            const int t = f & TYPE_MASK;
-            use = (t == LIQ || t == IFC) && !empties(I, nb, f);
-        }
-        float d = 0.f, u0 = 0.f, u1 = 0.f, u2 = 0.f;
-        if (use) {
-            float u[3];
-            moments<S>(I, pop, nb, d, u);
-            u0 = u[0];
-            u1 = u[1];
-            u2 = u[2];
-        }
-        const int ns = __popc(g_ballot(use));
-        const float rs = gsum(d), us0 = gsum(u0), us1 = gsum(u1), us2 = gsum(u2);
-        const float inv = 1.f / (float)max(ns, 1);
-        const float drb = ns > 0 ? rs * inv : I.rho_g - 1.f, rb = 1.f + drb;
-        const float v0 = us0 * inv, v1 = us1 * inv, v2 = us2 * inv;
-        const float uu = v0 * v0 + v1 * v1 + v2 * v2;
-        if (j < Q) {
-            const float cu = lane_c(CXP, j) * v0 + lane_c(CYP, j) * v1 + lane_c(CZP, j) * v2;
-            const float deq = lane_w(j) * (drb + rb * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
-            Store<S>::st(pop, (size_t)j * I.ps + g, deq, I.scale);
-        }
-        if (j == 0) {
-            I.m_hi[g] = 0.f;
-            I.m_lo[g] = 0.f;
-            I.aux[g] = drb;
-            phi[g] = 0.f;
-        }
-    }
-    const int nl = min(load_count(&C.n_newl), I.list_cap);
-    for (int k = g0 * 32 + g_lane(); k < nl; k += ngroups * 32) {
-        const int id = I.newl[k];
-        const float dr = drho_of<S>(I, pop, id);
-        I.m_hi[id] = 1.f;
-        I.m_lo[id] = dr;
-        I.aux[id] = dr;
-        phi[id] = 1.f;
-    }
-}
+}  // namespace
 
-// share: one group per converted cell; lane i counts neighbour x + c_i if it
-// is interface after the conversions (flags, marks and claims are not
-// modified in this phase).
-__device__ __forceinline__ void phase_share(const Inst& I, int parity) {
-    StepCounters& C = I.ctl->cnt[parity];
-    const int nc = min(load_count(&C.n_cand), I.list_cap);
-    const int grp = threadIdx.x >> 5, ngrp = blockDim.x >> 5;
-    for (int k = grp; k < nc; k += ngrp) {
-        const int id = I.cand[k];
-        const uint8_t fl = I.flags[id];
-        if (!(fl & (MARK_FILL | MARK_EMPTY))) continue;
-        int x, y, z;
-        cell_coords(I, id, x, y, z);
-        const int nb = lane_nbr(I, x, y, z);
-        const bool rcv = nb >= 0 && post_type(I, nb) == IFC;
-        const int nr = __popc(g_ballot(rcv));
-        if (nr == 0) {
-            if (g_lane() == 0) {
-                atomicAdd(&I.ctl->ledger, -(double)I.share[id]);
-                I.share[id] = 0.f;
-            }
-            continue;
-        }
-        if (g_lane() == 0) I.share[id] = (float)((double)I.share[id] / nr);
-        // the receiver notes this converted neighbour (its link opp(i));
-        // the first note puts it on the list
-        const bool first = rcv && atomicOr(&I.cmask[nb], 1u << lane_opp(g_lane())) == 0u;
-        g_push(first, nb, I.recv, &C.n_recv, I.list_cap, &C.overflow);
-    }
-}
-
-// commit: converted and new cells take their new types; receivers add the
-// shares of their converted neighbours in link order i = 1..18 and
-// recompute phi = m / rho.
-template <typename S>
-__device__ __forceinline__ void phase_commit(const Inst& I, int parity) {
-    StepCounters& C = I.ctl->cnt[parity];
-    const int nc = min(load_count(&C.n_cand), I.list_cap), ng = min(load_count(&C.n_newg), I.list_cap);
-    const int nl = min(load_count(&C.n_newl), I.list_cap), nr = min(load_count(&C.n_recv), I.list_cap);
-    float* phi = phi_of(I, parity ^ 1);
-    // single-thread items; the claim bits of the new cells are the only
-    // bits set in I.claim, and all of them are cleared here
-    for (int k0 = 0; k0 < nc + ng + nl; k0 += blockDim.x) {
-        const int k = k0 + (int)threadIdx.x;
-        bool f = false, e = false, g = false, l = false;
-        if (k < nc) {
-            const int id = I.cand[k];
-            const uint8_t fl = I.flags[id];
-            if (fl & MARK_FILL) {
-                I.flags[id] = LIQ | MARK_FILL;
-                I.m_hi[id] = 0.f;
-                I.m_lo[id] = 0.f;
-                phi[id] = 1.f;
-                f = true;
-            } else if (fl & MARK_EMPTY) {
-                I.flags[id] = GAS | MARK_EMPTY;
-                I.m_hi[id] = 0.f;
-                I.m_lo[id] = 0.f;
-                phi[id] = 0.f;
-                e = true;
-            }
-        } else if (k < nc + ng + nl) {
-            g = k < nc + ng;
-            l = !g;
-            const int id = g ? I.newg[k - nc] : I.newl[k - nc - ng];
-            I.flags[id] = IFC;
-            unclaim_word(I.claim, id);
-        }
-        wave_count(f, &C.filled);
-        wave_count(e, &C.emptied);
-        wave_count(g, &C.newg);
-        wave_count(l, &C.newl);
-    }
-    // receivers, one thread each: the note mask names the converted
-    // neighbours, whose shares are added in link order; rho - 1 of every
-    // receiver is in I.aux (left by the sweep for interface cells, by the
-    // claim and new-gas phases for new ones)
-    BLOCK_LOOP(k, nr) {
-        const int id = I.recv[k];
-        const uint32_t m = I.cmask[id];
-        int x, y, z;
-        cell_coords(I, id, x, y, z);
-        float sh[Q];
-#pragma unroll
-        for (int l = 1; l < Q; ++l) {
-            sh[l] = 0.f;
-            if ((m >> l) & 1u) sh[l] = I.share[nbr_index(I, x, y, z, cx(l), cy(l), cz(l))];
-        }
-        float hi = I.m_hi[id], lo = I.m_lo[id];
-        const float dr = I.aux[id];
-#pragma unroll
-        for (int l = 1; l < Q; ++l)
-            if ((m >> l) & 1u) add_comp(hi, lo, sh[l]);
-        I.m_hi[id] = hi;
-        I.m_lo[id] = lo;
-        phi[id] = (float)(((double)hi + (double)lo) / (1.0 + (double)dr));
-        I.cmask[id] = 0u;
-    }
-}
+// ---------------------------------------------------------------------------
+// force reduction and body update (one workgroup of CT threads)
+// ---------------------------------------------------------------------------
+namespace {
 
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
@@ -353,77 +149,52 @@ __device__ __forceinline__ double wave_sum_d(double v) {
     return v;
 }
 
-// Fixed-order FP64 sum of the boundary sweep's force records, per body, in
-// three parts so that its memory round trip overlaps the claim phase:
-//   load     every thread loads its records (slots tid + j * CONV_THREADS)
-//            and threads t < 6 nbodies the accumulator entry they finish
-//   partial  per body: the thread's records in slot order, wavefront
-//            butterflies, one partial per wavefront in LDS
-//   final    (after a barrier) acc = loaded entry + partials in wavefront order
-struct ForceLoad {
-    static constexpr int PER = BND_BLOCKS_MAX / CONV_THREADS;
+// Fixed-order FP64 sum of the boundary sweep's force records, per body:
+// thread t takes records t + j CT in order j, then wavefront butterflies,
+// then acc = (entry the atomics left) + wavefront partials in wavefront
+// order.  The result is in the accumulators and in sacc.
+__device__ __forceinline__ void reduce_forces(const Inst& I, int parity, double (*sacc)[6]) {
+    constexpr int PER = BND_BLOCKS_MAX / CT;
+    static_assert(PER * CT == BND_BLOCKS_MAX, "force records per thread");
+    __shared__ double part[CW][MAXB][6];
+    const int nrec = boundary_blocks(I);
     int rb[PER];
     double rv[PER][6];
-    double acc0;
-};
-static_assert(ForceLoad::PER * CONV_THREADS == BND_BLOCKS_MAX, "force records per thread");
-constexpr int CONV_WAVES = CONV_THREADS / 64;
-
-__device__ __forceinline__ void forces_load(const Inst& I, int parity, ForceLoad& F) {
-    const int nrec = boundary_blocks(I);
 #pragma unroll
-    for (int j = 0; j < ForceLoad::PER; ++j) {
-        const int k = threadIdx.x + j * CONV_THREADS;
-        F.rb[j] = k < nrec ? I.frec_body[k] : -1;
+    for (int j = 0; j < PER; ++j) {
+        const int k = threadIdx.x + j * CT;
+        rb[j] = k < nrec ? I.frec_body[k] : -1;
 #pragma unroll
-        for (int q = 0; q < 6; ++q) F.rv[j][q] = k < nrec ? I.frec_v[q * BND_BLOCKS_MAX + k] : 0.0;
+        for (int q = 0; q < 6; ++q) rv[j][q] = k < nrec ? I.frec_v[q * BND_BLOCKS_MAX + k] : 0.0;
     }
     const int t = threadIdx.x;
-    F.acc0 = t < 6 * I.nbodies ? I.ctl->cnt[parity].acc[t / 6][t % 6] : 0.0;
-}
-
-__device__ __forceinline__ void forces_partial(const Inst& I, const ForceLoad& F, double (*part)[MAXB][6]) {
+    const double acc0 = t < 6 * I.nbodies ? I.ctl->cnt[parity].acc[t / 6][t % 6] : 0.0;
     for (int b = 0; b < I.nbodies; ++b) {
         double v[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
-        for (int j = 0; j < ForceLoad::PER; ++j)
-            if (F.rb[j] == b)
+        for (int j = 0; j < PER; ++j)
+            if (rb[j] == b)
 #pragma unroll
-                for (int q = 0; q < 6; ++q) v[q] += F.rv[j][q];
+                for (int q = 0; q < 6; ++q) v[q] += rv[j][q];
 #pragma unroll
         for (int q = 0; q < 6; ++q) v[q] = wave_sum_d(v[q]);
         if ((threadIdx.x & 63) == 0)
 #pragma unroll
             for (int q = 0; q < 6; ++q) part[threadIdx.x >> 6][b][q] = v[q];
     }
-}
-
-__device__ __forceinline__ void forces_final(const Inst& I, int parity, const ForceLoad& F,
-                                             const double (*part)[MAXB][6], double (*sacc)[6]) {
-    const int t = threadIdx.x;
+    __syncthreads();
     if (t < 6 * I.nbodies) {
-        double s = F.acc0;
+        double s = acc0;
 #pragma unroll
-        for (int w = 0; w < CONV_WAVES; ++w) s += part[w][t / 6][t % 6];
+        for (int w = 0; w < CW; ++w) s += part[w][t / 6][t % 6];
         I.ctl->cnt[parity].acc[t / 6][t % 6] = s;
-        sacc[t / 6][t % 6] = s;  // the body update reads it from here
+        sacc[t / 6][t % 6] = s;
     }
-}
-
-// the whole sum at once (phase-isolated calls)
-__device__ __forceinline__ void phase_forces(const Inst& I, int parity, double (*sacc)[6]) {
-    __shared__ double part[CONV_WAVES][MAXB][6];
-    ForceLoad F;
-    forces_load(I, parity, F);
-    forces_partial(I, F, part);
-    __syncthreads();
-    forces_final(I, parity, F, part, sacc);
     __syncthreads();
 }
 
-// Copy of the body records in LDS, written by one wavefront (32-bit words),
-// so that the body update does not wait on global memory after the force
-// reduction.
+// Copy of the body records in LDS (32-bit words, one wavefront), so that the
+// body update reads them without a global round trip after the reduction.
 __device__ __forceinline__ void stage_bodies(const Inst& I, DevBody* sb) {
     static_assert(sizeof(DevBody) % 4 == 0, "body record in 32-bit words");
     const int nw = I.nbodies * (int)(sizeof(DevBody) / 4);
@@ -432,13 +203,13 @@ __device__ __forceinline__ void stage_bodies(const Inst& I, DevBody* sb) {
     for (int w = threadIdx.x & 63; w < nw; w += 64) dst[w] = src[w];
 }
 
-// clear the other parity's counters
-__device__ __forceinline__ void phase_finish(const Inst& I, int parity) {
+// clear the other parity's counters (the next step's)
+__device__ __forceinline__ void clear_other(const Inst& I, int parity, int tid, int nthr) {
     StepCounters& O = I.ctl->cnt[parity ^ 1];
     int* ci = (int*)&O;
     const int nint = (int)(offsetof(StepCounters, acc) / sizeof(int));
-    for (int q = threadIdx.x; q < nint; q += blockDim.x) ci[q] = 0;
-    for (int q = threadIdx.x; q < MAXB * 6; q += blockDim.x) (&O.acc[0][0])[q] = 0.0;
+    for (int q = tid; q < nint; q += nthr) ci[q] = 0;
+    for (int q = tid; q < MAXB * 6; q += nthr) (&O.acc[0][0])[q] = 0.0;
 }
 
 // Bodies after the force reduction of a full step, run by one wavefront
@@ -449,10 +220,9 @@ __device__ __forceinline__ void phase_finish(const Inst& I, int parity) {
 // update that would leave the domain's interior, reach one cell per step at
 // the surface, jump a cell from the mapped pose or bring two bodies closer
 // than three cells is rejected: the body keeps its pose and Ctl::body_err
-// records why.
-// The inputs come from the LDS copies of the body records (sb, staged at the
-// kernel's start) and of the reduced force and torque (sacc); the results go
-// to the records in global memory.
+// records why.  Inputs from the LDS copies of the body records (sb) and of
+// the reduced force and torque (sacc); results to the records in global
+// memory.
 __device__ __forceinline__ void bodies_wave(const Inst& I, bool retire_moves, bool integrate, const DevBody* sb,
                                             const double (*sacc)[6]) {
     const int b = threadIdx.x & 63;
@@ -548,88 +318,320 @@ __device__ __forceinline__ void bodies_wave(const Inst& I, bool retire_moves, bo
     }
 }
 
-// One step's conversions.  The last wavefront updates the bodies while the
-// others claim; the later phases use all groups.
-// The force records are loaded first and reduced after the claims, so their
-// round trip overlaps the claim phase; the body update (last wavefront)
-// overlaps the new-gas phase (the other wavefronts).
-template <typename S>
-__device__ __forceinline__ void convert(const Inst& I, int parity, bool retire_moves, bool integrate) {
-    __shared__ double part[CONV_WAVES][MAXB][6];
+// The end of a step's body work in one workgroup: optional fixed-order force
+// reduction, then the body update by wavefront 0.
+__device__ __forceinline__ void forces_and_bodies(const Inst& I, int parity, bool reduce, bool retire_moves,
+                                                  bool integrate) {
     __shared__ double sacc[MAXB][6];
     __shared__ DevBody sb[MAXB];
-    const bool last = (int)(threadIdx.x >> 6) == CONV_WAVES - 1;
-    constexpr int WORK_GROUPS = CONV_THREADS / 32 - 2;  // the 32-lane groups of all but the last wavefront
-    ForceLoad F;
-    forces_load(I, parity, F);
-    if (!last) phase_claim<S>(I, parity, threadIdx.x >> 5, WORK_GROUPS);
-    else stage_bodies(I, sb);
-    forces_partial(I, F, part);
+    if ((int)(threadIdx.x >> 6) == CW - 1) stage_bodies(I, sb);
+    if (reduce) reduce_forces(I, parity, sacc);
     __syncthreads();
-    forces_final(I, parity, F, part, sacc);
-    __syncthreads();
-    if (last) bodies_wave(I, retire_moves, integrate, sb, sacc);
-    else phase_newgas<S>(I, parity, threadIdx.x >> 5, WORK_GROUPS);
-    __syncthreads();
-    phase_share(I, parity);
-    __syncthreads();
-    phase_commit<S>(I, parity);
-    __syncthreads();
-    phase_finish(I, parity);
+    if (threadIdx.x < 64) bodies_wave(I, retire_moves, integrate, sb, sacc);
+}
+
+// ---------------------------------------------------------------------------
+// the three conversion launches; blk of nblk is the workgroup's place in the
+// instance's grid
+// ---------------------------------------------------------------------------
+template <typename S>
+__device__ __forceinline__ void conv_claim(const Inst& I, int parity, int blk, int nblk, bool retire_moves,
+                                           bool integrate) {
+    if (blk == nblk - 1) {
+        forces_and_bodies(I, parity, true, retire_moves, integrate);
+        return;
+    }
+    StepCounters& C = I.ctl->cnt[parity];
+    const int n = list_len(&C.n_cand, I.list_cap);
+    const int ns = list_len(&C.n_strd, I.list_cap);
+    const int i = g_lane();
+    const int ng = (nblk - 1) * CG;
+    for (int k = blk * CG + (int)(threadIdx.x >> 5); k < n + ns; k += ng) {
+        if (k >= n) {
+            // a stranded candidate (no liquid neighbour, no mark): it empties
+            // unless an interface neighbour has a liquid neighbour (it is an
+            // outer cell of a surface two cells thick) or a neighbour fills
+            // (filling wins); emptying cells are listed after the sweep's
+            // candidates, which this loop does not reach
+            const int id = I.recv[k - n];
+            int x, y, z;
+            cell_coords(I, id, x, y, z);
+            const int nb = lane_nbr(I, x, y, z);
+            const uint8_t nf = nb >= 0 ? I.flags[nb] : 0;
+            const bool keep = nb >= 0 && ((nf & MARK_FILL) || ((nf & TYPE_MASK) == IFC && I.lnb[nb]));
+            if (g_ballot(keep)) continue;
+            if (i == 0) {
+                I.flags[id] = I.flags[id] | MARK_EMPTY;
+                I.share[id] = (float)((double)I.m_hi[id] + (double)I.m_lo[id]);
+                const int p = n + atomicAdd(&C.n_se, 1);
+                if (p < I.list_cap) I.cand[p] = id;
+                else atomicOr(&C.overflow, 1);
+            }
+            continue;
+        }
+        const int id = I.cand[k];
+        const uint8_t fl = I.flags[id];
+        int x, y, z;
+        cell_coords(I, id, x, y, z);
+        const int nb = lane_nbr(I, x, y, z);
+        const uint8_t nf = nb >= 0 ? I.flags[nb] : 0;
+        if (fl & MARK_FILL) {
+            if (i == 0) {
+                const float dr = I.aux[id];  // rho - 1 left by the sweep
+                I.share[id] = (float)(((double)I.m_hi[id] - 1.0) + ((double)I.m_lo[id] - (double)dr));
+            }
+            const bool take = nb >= 0 && (nf & TYPE_MASK) == GAS && claim(I.claim, nb);
+            g_push(take, nb, I.newg, &C.n_newg, I.list_cap, &C.overflow);
+        } else if (fl & MARK_EMPTY) {
+            if (g_ballot(nb >= 0 && (nf & MARK_FILL))) {
+                if (i == 0) I.flags[id] = fl & (uint8_t)~MARK_EMPTY;  // filling wins: stays interface
+                continue;
+            }
+            if (i == 0) I.share[id] = (float)((double)I.m_hi[id] + (double)I.m_lo[id]);
+            const bool take = nb >= 0 && (nf & TYPE_MASK) == LIQ && claim(I.claim, nb);
+            g_push(take, nb, I.newl, &C.n_newl, I.list_cap, &C.overflow);
+        }
+    }
 }
 
 template <typename S>
-__global__ __launch_bounds__(CONV_THREADS) void k_convert(Inst I, int parity, int retire_moves, int integrate) {
-    convert<S>(I, parity, retire_moves != 0, integrate != 0);
+__device__ __forceinline__ void conv_middle(const Inst& I, int parity, int blk, int nblk) {
+    StepCounters& C = I.ctl->cnt[parity];
+    S* pop = (S*)pop_of(I, parity ^ 1);
+    float* phi = phi_of(I, parity ^ 1);
+    const int j = g_lane();
+    const int g0 = blk * CG + (int)(threadIdx.x >> 5), ng = nblk * CG;
+    // new interface cells from gas, one group each (lane j: neighbour j)
+    const int nng = list_len(&C.n_newg, I.list_cap);
+    for (int k = g0; k < nng; k += ng) {
+        const int g = I.newg[k];
+        int gx, gy, gz;
+        cell_coords(I, g, gx, gy, gz);
+        const int nb = lane_nbr(I, gx, gy, gz);
+        bool use = false;
+        if (nb >= 0) {
+            const uint8_t f = I.flags[nb];
+            const int t = f & TYPE_MASK;
+            use = (t == LIQ || t == IFC) && !(f & MARK_EMPTY);
+        }
+        float d = 0.f, u0 = 0.f, u1 = 0.f, u2 = 0.f;
+        if (use) {
+            float u[3];
+            moments<S>(I, pop, nb, d, u);
+            u0 = u[0];
+            u1 = u[1];
+            u2 = u[2];
+        }
+        const int ns = __popc(g_ballot(use));
+        const float rs = gsum(d), us0 = gsum(u0), us1 = gsum(u1), us2 = gsum(u2);
+        const float inv = 1.f / (float)max(ns, 1);
+        const float drb = ns > 0 ? rs * inv : I.rho_g - 1.f, rb = 1.f + drb;
+        const float v0 = us0 * inv, v1 = us1 * inv, v2 = us2 * inv;
+        const float uu = v0 * v0 + v1 * v1 + v2 * v2;
+        if (j < Q) {
+            const float cu = lane_c(CXP, j) * v0 + lane_c(CYP, j) * v1 + lane_c(CZP, j) * v2;
+            const float deq = lane_w(j) * (drb + rb * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
+            Store<S>::st(pop, (size_t)j * I.ps + g, deq, I.scale);
+        }
+        if (j == 0) {
+            I.m_hi[g] = 0.f;
+            I.m_lo[g] = 0.f;
+            I.aux[g] = drb;
+            phi[g] = 0.f;
+        }
+    }
+    // new interface cells from liquid, one thread each: m = rho, phi = 1
+    const int nnl = list_len(&C.n_newl, I.list_cap);
+    for (int k = blk * CT + (int)threadIdx.x; k < nnl; k += nblk * CT) {
+        const int id = I.newl[k];
+        const float dr = drho_of<S>(I, pop, id);
+        I.m_hi[id] = 1.f;
+        I.m_lo[id] = dr;
+        I.aux[id] = dr;
+        phi[id] = 1.f;
+    }
+    // excess shares, one group per converted cell (lane i: neighbour x + c_i)
+    const int nc = cand_len(C, I.list_cap);
+    for (int k = g0; k < nc; k += ng) {
+        const int id = I.cand[k];
+        const uint8_t fl = I.flags[id];
+        if (!(fl & (MARK_FILL | MARK_EMPTY))) continue;
+        int x, y, z;
+        cell_coords(I, id, x, y, z);
+        const int nb = lane_nbr(I, x, y, z);
+        const bool rcv = nb >= 0 && post_type(I, nb) == IFC;
+        const int nr = __popc(g_ballot(rcv));
+        if (nr == 0) {
+            if (j == 0) {
+                atomicAdd(&I.ctl->ledger, -(double)I.share[id]);
+                I.share[id] = 0.f;
+            }
+            continue;
+        }
+        if (j == 0) I.share[id] = (float)((double)I.share[id] / nr);
+        // the receiver notes this converted neighbour (its link opp(i)); the
+        // first note puts it on the list
+        const bool first = rcv && atomicOr(&I.cmask[nb], 1u << lane_opp(j)) == 0u;
+        g_push(first, nb, I.recv, &C.n_recv, I.list_cap, &C.overflow);
+    }
 }
 
-// one workgroup per instance of a batch (at most 64: bit k of the masks
-// belongs to instance k)
 template <typename S>
-__global__ __launch_bounds__(CONV_THREADS) void kb_convert(const Inst* __restrict__ tab, int parity,
-                                                          unsigned long long retire_mask,
-                                                          unsigned long long integrate_mask) {
-    const int k = blockIdx.x;
+__device__ __forceinline__ void conv_commit(const Inst& I, int parity, int blk, int nblk) {
+    StepCounters& C = I.ctl->cnt[parity];
+    const int nc = cand_len(C, I.list_cap), ng = list_len(&C.n_newg, I.list_cap);
+    const int nl = list_len(&C.n_newl, I.list_cap), nr = list_len(&C.n_recv, I.list_cap);
+    float* phi = phi_of(I, parity ^ 1);
+    const int t0 = blk * CT, step = nblk * CT;
+    // converted and new cells, one thread each (the claim bits of the new
+    // cells are the only bits set in the bitmap, and all are cleared here)
+    const int items = nc + ng + nl;
+    for (int k0 = t0; k0 < items; k0 += step) {
+        const int k = k0 + (int)threadIdx.x;
+        bool f = false, e = false, g = false, l = false;
+        if (k < nc) {
+            const int id = I.cand[k];
+            const uint8_t fl = I.flags[id];
+            if (fl & MARK_FILL) {
+                I.flags[id] = LIQ | MARK_FILL;
+                I.m_hi[id] = 0.f;
+                I.m_lo[id] = 0.f;
+                phi[id] = 1.f;
+                f = true;
+            } else if (fl & MARK_EMPTY) {
+                I.flags[id] = GAS | MARK_EMPTY;
+                I.m_hi[id] = 0.f;
+                I.m_lo[id] = 0.f;
+                phi[id] = 0.f;
+                e = true;
+            }
+        } else if (k < items) {
+            g = k < nc + ng;
+            l = !g;
+            const int id = g ? I.newg[k - nc] : I.newl[k - nc - ng];
+            I.flags[id] = IFC;
+            unclaim_word(I.claim, id);
+        }
+        wave_count(f, &C.filled);
+        wave_count(e, &C.emptied);
+        wave_count(g, &C.newg);
+        wave_count(l, &C.newl);
+    }
+    // receivers, one thread each: the note mask names the converted
+    // neighbours, whose shares are added in link order; rho - 1 of every
+    // receiver is in I.aux (left by the sweep for interface cells, by the
+    // middle launch for new ones)
+    for (int k = t0 + (int)threadIdx.x; k < nr; k += step) {
+        const int id = I.recv[k];
+        const uint32_t m = I.cmask[id];
+        int x, y, z;
+        cell_coords(I, id, x, y, z);
+        float sh[Q];
+#pragma unroll
+        for (int q = 1; q < Q; ++q) {
+            sh[q] = 0.f;
+            if ((m >> q) & 1u) sh[q] = I.share[nbr_index(I, x, y, z, cx(q), cy(q), cz(q))];
+        }
+        float hi = I.m_hi[id], lo = I.m_lo[id];
+        const float dr = I.aux[id];
+#pragma unroll
+        for (int q = 1; q < Q; ++q)
+            if ((m >> q) & 1u) add_comp(hi, lo, sh[q]);
+        I.m_hi[id] = hi;
+        I.m_lo[id] = lo;
+        phi[id] = (float)(((double)hi + (double)lo) / (1.0 + (double)dr));
+        I.cmask[id] = 0u;
+    }
+    if (blk == 0) clear_other(I, parity, threadIdx.x, CT);
+}
+
+}  // namespace
+
+// one instance
+template <typename S>
+__global__ __launch_bounds__(CT) void k_conv_claim(Inst I, int parity, int retire_moves, int integrate) {
+    conv_claim<S>(I, parity, blockIdx.x, gridDim.x, retire_moves != 0, integrate != 0);
+}
+template <typename S>
+__global__ __launch_bounds__(CT) void k_conv_middle(Inst I, int parity) {
+    conv_middle<S>(I, parity, blockIdx.x, gridDim.x);
+}
+template <typename S>
+__global__ __launch_bounds__(CT) void k_conv_commit(Inst I, int parity) {
+    conv_commit<S>(I, parity, blockIdx.x, gridDim.x);
+}
+
+// a batch of at most 64 instances: blockIdx.y is the instance (bit y of the
+// masks), blockIdx.x the workgroup of its grid (grids of other sizes: the
+// extra workgroups return)
+template <typename S>
+__global__ __launch_bounds__(CT) void kb_conv_claim(const Inst* __restrict__ tab, int parity,
+                                                    unsigned long long retire_mask, unsigned long long integrate_mask) {
+    const int k = blockIdx.y;
     const Inst I = tab[k];
-    convert<S>(I, parity, (retire_mask >> k) & 1ull, (integrate_mask >> k) & 1ull);
+    const int nb = conv_blocks(I);
+    if ((int)blockIdx.x >= nb) return;
+    conv_claim<S>(I, parity, blockIdx.x, nb, (retire_mask >> k) & 1ull, (integrate_mask >> k) & 1ull);
+}
+template <typename S>
+__global__ __launch_bounds__(CT) void kb_conv_middle(const Inst* __restrict__ tab, int parity) {
+    const Inst I = tab[blockIdx.y];
+    const int nb = conv_blocks(I);
+    if ((int)blockIdx.x >= nb) return;
+    conv_middle<S>(I, parity, blockIdx.x, nb);
+}
+template <typename S>
+__global__ __launch_bounds__(CT) void kb_conv_commit(const Inst* __restrict__ tab, int parity) {
+    const Inst I = tab[blockIdx.y];
+    const int nb = conv_blocks(I);
+    if ((int)blockIdx.x >= nb) return;
+    conv_commit<S>(I, parity, blockIdx.x, nb);
 }
 
 // End of a step without conversions (phase-isolated calls).
-__global__ __launch_bounds__(CONV_THREADS) void k_finish(Inst I, int parity, int reduce, int zero_other,
-                                                         int retire_moves) {
-    __shared__ double sacc[MAXB][6];
-    __shared__ DevBody sb[MAXB];
-    if (threadIdx.x < 64) stage_bodies(I, sb);
-    if (reduce) phase_forces(I, parity, sacc);
-    __syncthreads();
-    if (threadIdx.x < 64) bodies_wave(I, retire_moves != 0, false, sb, sacc);
-    if (zero_other) phase_finish(I, parity);
+__global__ __launch_bounds__(CT) void k_finish(Inst I, int parity, int reduce, int zero_other, int retire_moves) {
+    forces_and_bodies(I, parity, reduce != 0, retire_moves != 0, false);
+    if (zero_other) clear_other(I, parity, threadIdx.x, CT);
 }
 
-void launch_convert_batch(const Inst* tab, int n, int storage, int parity, unsigned long long retire_mask,
+namespace {
+template <typename S>
+void convert_one(const Inst& I, int parity, int r, int n, hipStream_t s) {
+    const dim3 g(conv_blocks(I)), b(CT);
+    hipLaunchKernelGGL(k_conv_claim<S>, g, b, 0, s, I, parity, r, n);
+    hipLaunchKernelGGL(k_conv_middle<S>, g, b, 0, s, I, parity);
+    hipLaunchKernelGGL(k_conv_commit<S>, g, b, 0, s, I, parity);
+}
+template <typename S>
+void convert_batch(const Inst* tab, int n, int blocks, int parity, unsigned long long rm, unsigned long long im,
+                   hipStream_t s) {
+    const dim3 g(blocks, n), b(CT);
+    hipLaunchKernelGGL(kb_conv_claim<S>, g, b, 0, s, tab, parity, rm, im);
+    hipLaunchKernelGGL(kb_conv_middle<S>, g, b, 0, s, tab, parity);
+    hipLaunchKernelGGL(kb_conv_commit<S>, g, b, 0, s, tab, parity);
+}
+}  // namespace
+
+void launch_convert_batch(const Inst* tab, int n, int blocks, int storage, int parity, unsigned long long retire_mask,
                           unsigned long long integrate_mask, hipStream_t s) {
-    const dim3 g(n), b(CONV_THREADS);
     switch (storage) {
-    case LBM_FP16_DEV: hipLaunchKernelGGL(kb_convert<__half>, g, b, 0, s, tab, parity, retire_mask, integrate_mask); break;
-    case LBM_BF16_DEV:
-        hipLaunchKernelGGL(kb_convert<__hip_bfloat16>, g, b, 0, s, tab, parity, retire_mask, integrate_mask);
-        break;
-    default: hipLaunchKernelGGL(kb_convert<float>, g, b, 0, s, tab, parity, retire_mask, integrate_mask); break;
+    case LBM_FP16_DEV: convert_batch<__half>(tab, n, blocks, parity, retire_mask, integrate_mask, s); break;
+    case LBM_BF16_DEV: convert_batch<__hip_bfloat16>(tab, n, blocks, parity, retire_mask, integrate_mask, s); break;
+    default: convert_batch<float>(tab, n, blocks, parity, retire_mask, integrate_mask, s); break;
     }
 }
 
 void launch_convert(const Inst& I, int parity, bool retire_moves, bool integrate, hipStream_t s) {
-    const dim3 g(1), b(CONV_THREADS);
     const int r = (int)retire_moves, n = (int)integrate;
     switch (I.storage) {
-    case LBM_FP16_DEV: hipLaunchKernelGGL(k_convert<__half>, g, b, 0, s, I, parity, r, n); break;
-    case LBM_BF16_DEV: hipLaunchKernelGGL(k_convert<__hip_bfloat16>, g, b, 0, s, I, parity, r, n); break;
-    default: hipLaunchKernelGGL(k_convert<float>, g, b, 0, s, I, parity, r, n); break;
+    case LBM_FP16_DEV: convert_one<__half>(I, parity, r, n, s); break;
+    case LBM_BF16_DEV: convert_one<__hip_bfloat16>(I, parity, r, n, s); break;
+    default: convert_one<float>(I, parity, r, n, s); break;
     }
 }
 
 void launch_finish(const Inst& I, int parity, bool reduce, bool zero_other, bool retire_moves, hipStream_t s) {
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(CONV_THREADS), 0, s, I, parity, (int)reduce, (int)zero_other,
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(CT), 0, s, I, parity, (int)reduce, (int)zero_other,
                        (int)retire_moves);
 }
 

@@ -429,6 +429,16 @@ __device__ __forceinline__ void sweep_boundary(const Inst& I, int parity, int wg
             }
         }
         const float drx = osum(p0), jx0 = osum(p1), jx1 = osum(p2), jx2 = osum(p3);
+        // a liquid cell among the 18 neighbours (the sources of links 1..18)
+        int liq = 0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int i = l + BL * j;
+            if (i >= 1 && i < Q && sfe[j] >= 0 && (sfe[j] & TYPE_MASK) == LIQ) liq = 1;
+        }
+        liq |= __shfl_xor(liq, 4);
+        liq |= __shfl_xor(liq, 2);
+        liq |= __shfl_xor(liq, 1);
         const float rhox = 1.f + drx;
         const float ux0 = jx0 / rhox, ux1 = jx1 / rhox, ux2 = jx2 / rhox;
         const float uu = ux0 * ux0 + ux1 * ux1 + ux2 * ux2;
@@ -571,10 +581,14 @@ __device__ __forceinline__ void sweep_boundary(const Inst& I, int parity, int wg
         }
         const float drho = osum(q0), j0 = osum(q1), j1 = osum(q2), j2 = osum(q3);
         const float rho = 1.f + drho;
+        bool cand = false, strd = false;
         if (active && type == IFC && l == 0) {
             two_sum_add(mhi, mlo, dm);
             const float ph = (float)(((double)mhi + (double)mlo) / (1.0 + (double)drho));
             const double phd = (double)ph;
+            // filled past 1 + eps, emptied past -eps; an unmarked cell
+            // without a liquid neighbour is a stranded candidate, decided by
+            // the claim launch from its neighbours' liquid contacts
             uint8_t mark = 0;
             if (phd >= 1.0 + I.eps) mark = MARK_FILL;
             else if (phd <= -I.eps) mark = MARK_EMPTY;
@@ -582,13 +596,15 @@ __device__ __forceinline__ void sweep_boundary(const Inst& I, int parity, int wg
             I.m_lo[id] = mlo;
             phi_of(I, parity ^ 1)[id] = ph;
             I.aux[id] = drho;  // rho - 1 of this interface cell, for the conversion phase
+            I.lnb[id] = (uint8_t)liq;
             if (mark) {
                 I.flags[id] = (fl & KEEP_MASK) | mark;
-                const int p = atomicAdd(&C.n_cand, 1);
-                if (p < I.list_cap) I.cand[p] = id;
-                else atomicOr(&C.overflow, 1);
+                cand = true;
             }
+            strd = !mark && !liq;
         }
+        wave_append(cand, id, I.cand, &C.n_cand, I.list_cap, &C.overflow);
+        wave_append(strd, id, I.recv, &C.n_strd, I.list_cap, &C.overflow);
         if (active) {
             const float irho = 1.f / rho;
             const float u0 = j0 * irho, u1 = j1 * irho, u2 = j2 * irho;
@@ -782,7 +798,7 @@ void launch_sweep_boundary_batch(const BatchGrid& G, int storage, int parity, hi
 __global__ __launch_bounds__(256) void k_mark(Inst I, int parity) {
     StepCounters& C = I.ctl->cnt[parity];
     const int id = blockIdx.x * 256 + threadIdx.x;
-    bool cand = false;
+    bool cand = false, strd = false;
     if (id < I.N) {
         const uint8_t fl = I.flags[id];
         uint8_t mark = 0;
@@ -805,15 +821,25 @@ __global__ __launch_bounds__(256) void k_mark(Inst I, int parity) {
                 break;
             }
             I.aux[id] = dr;
+            int x, y, z;
+            cell_coords(I, id, x, y, z);
+            bool liq = false;
+            for (int i = 1; i < Q; ++i) {
+                const int nb = nbr_index(I, x, y, z, cx(i), cy(i), cz(i));
+                if (nb >= 0 && (I.flags[nb] & TYPE_MASK) == LIQ) liq = true;
+            }
             const double ph = (double)phi_of(I, parity ^ 1)[id];
             if (ph >= 1.0 + I.eps) mark = MARK_FILL;
             else if (ph <= -I.eps) mark = MARK_EMPTY;
+            I.lnb[id] = (uint8_t)liq;
+            strd = !mark && !liq;
         }
         cand = mark != 0;
         const uint8_t nf = (fl & KEEP_MASK) | mark;
         if (nf != fl) I.flags[id] = nf;
     }
     wave_append(cand, id, I.cand, &C.n_cand, I.list_cap, &C.overflow);
+    wave_append(strd, id, I.recv, &C.n_strd, I.list_cap, &C.overflow);
 }
 
 void launch_mark(const Inst& I, int parity, hipStream_t s) {

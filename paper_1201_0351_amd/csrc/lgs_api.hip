@@ -114,6 +114,7 @@ size_t layout(const lbm_config& c, Inst* I, char* base) {
     char* ax = take(4 * N);
     char* ru = take(N);
     char* no = take(N);
+    char* lb = take(N);
     char* kp = take(c.surface_tension != 0.0 ? 4 * N : 0);
     char* cl = take(4 * (N / 32 + 1));
     char* cm = take(4 * N);
@@ -139,6 +140,7 @@ size_t layout(const lbm_config& c, Inst* I, char* base) {
         I->aux = (float*)ax;
         I->rule = (uint8_t*)ru;
         I->nearo = (uint8_t*)no;
+        I->lnb = (uint8_t*)lb;
         I->kap = c.surface_tension != 0.0 ? (float*)kp : nullptr;
         I->claim = (uint32_t*)cl;
         I->cmask = (uint32_t*)cm;
@@ -625,13 +627,15 @@ static int run_step_batched(lbm_ctx* c) {
     for (int g = 0; g < n; g += 64) {
         const int ng = std::min(64, n - g);
         unsigned long long rm = 0, im = 0;
+        int blocks = 0;
         for (int k = g; k < g + ng; ++k) {
             InstHost& h = c->inst[k];
             integrate[k] = h.any_free && h.cfg.host_body_update == 0;
             if (remapped[k]) rm |= 1ull << (k - g);
             if (integrate[k]) im |= 1ull << (k - g);
+            blocks = std::max(blocks, conv_blocks(h.dev));
         }
-        launch_convert_batch(c->d_tab + g, ng, storage, p, rm, im, c->stream);
+        launch_convert_batch(c->d_tab + g, ng, blocks, storage, p, rm, im, c->stream);
     }
     for (int k = 0; k < n; ++k)
         if (integrate[k]) c->inst[k].need_remap = true;  // the device moved free bodies

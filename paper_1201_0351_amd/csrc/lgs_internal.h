@@ -71,7 +71,9 @@ __host__ __device__ constexpr double wgtd(int i) {
 struct StepCounters {
     int n_cand, n_newg, n_newl, n_recv;
     int filled, emptied, newg, newl;
-    int overflow, n_bnd, pad[2];
+    int overflow, n_bnd;
+    int n_strd;  // stranded candidates the sweep listed (in Inst::recv)
+    int n_se;    // of those, the ones that empty (listed after the sweep's candidates)
     double acc[MAXB][6];  // per body: F (3), T (3), FP64
 };
 
@@ -140,11 +142,18 @@ struct Inst {
     // found fluid or wall.  The conversions keep an interface layer between
     // liquid and gas (Sec. 2.2), so a liquid cell with 0 here has neither.
     uint8_t* nearo;
+    // Per interface cell: 1 if one of its 18 neighbours is liquid (written
+    // by the sweep every step; stale for other cells)
+    uint8_t* lnb;
     uint32_t* claim;   // new-interface claims
     uint32_t* cmask;   // per cell: bit l set when the neighbour over link l converted this step
     int* cand;
     int* newg;
     int* newl;
+    // receivers of excess mass (appended by the middle conversion launch);
+    // before that, from the sweep to the claim launch, the stranded
+    // candidates: interface cells without a liquid neighbour and without a
+    // conversion mark
     int* recv;
     int* bnd;  // cells the bulk sweep leaves to the boundary sweep
     // Momentum-exchange partial sums of the boundary sweep, one record per
@@ -624,7 +633,15 @@ void launch_remap(const Inst& I, int parity, int blocks_per_body, hipStream_t s)
 // batches of at most 64 instances (bit k of a mask belongs to instance k)
 void launch_remap_batch(const Inst* tab, int n, int max_bodies, int storage, int parity, int blocks_per_body,
                         hipStream_t s);
-void launch_convert_batch(const Inst* tab, int n, int storage, int parity, unsigned long long retire_mask,
+// Workgroups of an instance's conversion grid (three launches of this many
+// 256-thread workgroups): one per 512 cells of an x-y layer, the size of a
+// basin's free surface, 8 .. 256.
+__host__ __device__ inline int conv_blocks(const Inst& I) {
+    const int b = (int)(((long long)I.nx * I.ny + 511) / 512);
+    return b < 8 ? 8 : (b > 256 ? 256 : b);
+}
+// blocks: the largest conv_blocks of the batch's instances
+void launch_convert_batch(const Inst* tab, int n, int blocks, int storage, int parity, unsigned long long retire_mask,
                           unsigned long long integrate_mask, hipStream_t s);
 void launch_set_body(const Inst& I, int slot, const DevBody& b, hipStream_t s);
 // Liquid-mass total sum_LIQ rho + sum_IF m in two fixed-order passes: one

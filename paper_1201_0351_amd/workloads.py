@@ -72,18 +72,18 @@ def config3(heel=20.0, storage="fp16"):
                 bodies=[box((64, 64, 32), (128, 96, 96), heel, 0.5, fixed=1)])
 
 
-def floating_cubes(dof=0x0C, storage="fp32"):
+def floating_cubes(dof=0x0C, storage="fp32", heel0=2.86):
     """Rotational equilibrium of floating cubes: a 130x40x40 basin filled to
     z = 20, tau 0.526, g 7.5e-4, three 32x16x16 boxes (the cube of side 16
     extruded along x) of density 0.75, 0.5 and 0.25, released with their
-    centre at the upright equilibrium draft and heeled 2.86 deg about x; they
-    roll (and heave) towards the stable heel of a square section:
+    centre at the upright equilibrium draft and heeled heel0 deg about x;
+    they roll (and heave) towards the stable heel of a square section:
     26.565 deg for densities 1/4 and 3/4, 45 deg for 1/2."""
     H, s = 20.0, 16
     bodies = []
     for k, rs in enumerate((0.75, 0.5, 0.25)):
         gz = H + s / 2 - rs * s
-        bodies.append(box((2 * s, s, s), (21.0 + 44.0 * k, 20.0, gz), 2.86, rs, fixed=0))
+        bodies.append(box((2 * s, s, s), (21.0 + 44.0 * k, 20.0, gz), heel0, rs, fixed=0))
     return dict(name="floating_cubes_130x40x40", dof=dof, lattice=basin((130, 40, 40), H, 1.0 / 1.9, 7.5e-4,
                                                                        storage=storage), bodies=bodies)
 

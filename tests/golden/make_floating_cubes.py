@@ -15,9 +15,17 @@ FP32.  With heave the bottom faces sink onto a row of cell centres within a
 few hundred steps, the mapping turns asymmetric and the trajectory is
 deterministic enough to compare.)
 
+The paper starts its cubes far from equilibrium.  Two more runs do that:
+  settle    heave and roll from 10 deg at the upright draft, `--settle`
+            steps; the heels averaged over the last quarter are the settled
+            heels to set against the paper's 26.565 / 45 / 26.565 deg
+  roll_only roll only (centre held at the upright draft) from 15 deg,
+            `--steps` steps (the closed form for a held centre is
+            20.7 / 45 / 20.7 deg)
+
 Only the oracle is called.
 
-Usage: python tests/golden/make_floating_cubes.py [--steps 3000] [--threads 8]
+Usage: python tests/golden/make_floating_cubes.py [--steps 3000] [--settle 15000] [--threads 8]
 """
 import argparse
 import json
@@ -42,10 +50,10 @@ def heel_deg(q):
     return math.degrees(2.0 * math.atan2(q[1], q[0]))
 
 
-def run(dof, steps, every, threads):
+def run(dof, steps, every, threads, heel0=HEEL0):
     o = Oracle(NX, NY, NZ, TAU, accel=(0.0, 0.0, -G), eps=EPS, threads=threads)
     o.init_basin(H)
-    a = math.radians(HEEL0)
+    a = math.radians(heel0)
     for k, rs in enumerate(DENSITIES):
         o.set_body(k, (S, S / 2, S / 2), (21.0 + 44.0 * k, 20.0, H + S / 2 - rs * S),
                    (math.cos(a / 2), math.sin(a / 2), 0.0, 0.0), density=rs, fixed=0)
@@ -65,13 +73,16 @@ def run(dof, steps, every, threads):
             print("dof 0x%02x step %d heel/z %s (%.0f s)" % (dof, done, [round(v, 3) for v in row[1:]],
                                                           time.time() - t0), flush=True)
     M1, L1 = o.mass_total()
-    return dict(dof=dof, steps=steps, every=every, columns="step, then heel_deg and z per body",
-                trace=trace, mass_minus_ledger=[M0 - L0, M1 - L1])
+    late = [row for row in trace if row[0] > 0.75 * steps]
+    settled = [sum(abs(row[1 + 2 * k]) for row in late) / len(late) for k in range(3)]
+    return dict(dof=dof, heel0_deg=heel0, steps=steps, every=every, columns="step, then heel_deg and z per body",
+                trace=trace, mass_minus_ledger=[M0 - L0, M1 - L1], settled_heel_deg=settled)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--settle", type=int, default=15000)
     ap.add_argument("--every", type=int, default=250)
     ap.add_argument("--threads", type=int, default=min(8, os.cpu_count() or 1))
     ap.add_argument("--out", type=str, default=os.path.join(HERE, "floating_cubes_130x40x40.json"))
@@ -79,7 +90,9 @@ def main():
     res = dict(_source="FP64 oracle (oracle/lgs_oracle.c), written by tests/golden/make_floating_cubes.py",
                nx=NX, ny=NY, nz=NZ, fill_height=H, side=S, tau=TAU, g=G, eps=EPS, densities=list(DENSITIES),
                heel0_deg=HEEL0,
-               heave_roll=run(0x0C, args.steps, args.every, args.threads))
+               heave_roll=run(0x0C, args.steps, args.every, args.threads),
+               roll_only=run(0x08, args.steps, args.every, args.threads, heel0=15.0),
+               settle=run(0x0C, args.settle, args.every, args.threads, heel0=10.0))
     with open(args.out, "w") as fh:
         json.dump(res, fh, indent=1)
     print("wrote", args.out)

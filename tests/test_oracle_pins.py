@@ -289,3 +289,36 @@ def test_stranded_interface_cell_empties_before_its_density_turns_negative():
     assert o.last_conversions()["emptied"] == 1
     o.step(5)
     assert (o.types() == GAS).all()
+
+
+def test_stranded_means_cut_off_from_the_liquid():
+    """The stranded rule reaches two cells: a 4 x 4 periodic column with
+    liquid at z = 0..3, interface at z = 4 (fill 0.8) and z = 5 (fill 0.2)
+    over it, gas at z = 6, 7, and a detached interface film at z = 8, 9
+    (fill 0.5).  The outer interface layer z = 5 has no liquid neighbour but
+    its interface neighbours below have one, so it stays; the film at
+    z = 8, 9 reaches no liquid and empties.  Fill levels are inside the
+    thresholds, so nothing else converts."""
+    n = 4
+    o = Oracle(n, n, 12, 0.8, accel=(0, 0, 0), periodic=3)
+    t = np.zeros((12, n, n), np.uint8)
+    t[:4] = LIQ
+    t[4:6] = IF
+    t[8:10] = IF
+    phi = np.zeros((12, n, n))
+    phi[:4] = 1.0
+    phi[4], phi[5], phi[8:10] = 0.8, 0.2, 0.5
+    f = np.zeros((19, 12, n, n))
+    for i in range(19):
+        f[i][t > 0] = WTS[i]
+    o.set_flags(t)
+    o.set_f(f)
+    o.set_phi(phi)
+    o.set_mass(np.where(t == IF, phi, 0.0))
+    o.step(1, PH_CONVERT)
+    tt = o.types()
+    assert (tt[4:6] == IF).all() and (tt[:4] == LIQ).all()
+    assert (tt[8:10] == GAS).all()
+    assert o.last_conversions() == dict(filled=0, emptied=32, new_from_gas=0, new_from_liquid=0)
+    M, led = o.mass_total()
+    assert led == pytest.approx(-16.0, abs=1e-12)  # the film's mass 32 x 0.5 has no receiver
