@@ -1,37 +1,49 @@
 """Benchmark of the liquid-gas-solid LBM hot path on one MI355X.
 
-Workload (the configuration the headline metric is quoted on): a 128^3
-basin, tau 0.55, gravity 5e-6, liquid depth 64, with a 32x32x16 box of
-density 0.5 released at 20 deg heel about x (roll only).  One "step" is one
-pass of the whole hot path: body remap, fused stream/collide/boundary/mass-
-exchange/momentum-exchange sweep, interface conversions, force reduction and
-the rigid-body update feeding the next remap.  Inputs are synthetic and
-resident in HBM before the timed region.
+Workload of the headline (the largest single-GPU configuration): a
+512x256x256 open channel, periodic along x and y, walls at the bottom and
+the top, liquid depth 128, tau 0.8, gravity 1e-5, a body-force drive for a
+surface speed of 0.05 (the liquid starts on the half-Poiseuille profile),
+and one free 48x24x24 box of density 0.6 advected along x in 6 DOF.  One
+"step" is one pass of the whole hot path: body remap, fused stream / collide
+/ boundary / mass-exchange / momentum-exchange sweep, interface conversions,
+force reduction and the rigid-body update feeding the next remap.  Inputs
+are synthetic and resident in HBM before the timed region; the channel is
+prepared by 200 steps from its initial state (its start-up transient) before
+the warm-up steps.
 
 Prints one JSON line.  `value` is MLUPS over all cells of the FP32-storage
-run with the rigid-body update on the device; `fp16` repeats the timed run
-with FP16 deviation storage, `host_body_update` with the update on the host.
-`roofline` prices the dominant kernel (the bulk sweep) with its algorithmic
-bytes against the 8 TB/s HBM peak, its duration measured with HIP events
-around every launch inside the timed region; `traffic` is the HBM bytes per
-launch the profiler counted (profiles/k_sweep_bulk_basin128_traffic.txt),
-reported only while the kernel source is the one that was profiled.
-`righting_moment` holds the box at the heel angles of the oracle's golden
-run and compares the averaged -T_x with the FP64 oracle's values
-(tests/golden/righting_moment_128.json).  `cpu_baseline` times the FP64
-oracle on the host on a bounded sample of the same workload.
+run with the rigid-body update on the device; `ms_per_step` is the median
+over 5 windows of K/5 steps (each window bracketed by stream
+synchronisation; `ms_windows` lists them).  `roofline` prices the dominant
+kernel (the bulk sweep) with its algorithmic bytes against the 8 TB/s HBM
+peak, its duration measured with HIP events attached to every one of its
+dispatches (`kernels` gives the boundary sweep too); `traffic` is the HBM
+bytes per launch the profiler counted for the same kernel and workload
+(profiles/k_sweep_bulk_channel512_traffic.txt), reported only while the
+kernel source is the one that was profiled.  `channel` repeats the timed run
+with FP16 and BF16 deviation storage and with the rigid-body update on the
+host; `accuracy` compares the channel's body force and torque after four
+steps with the FP64 oracle's; `righting_moment` holds the 128^3 box at the
+heel angles of the oracle's golden run and compares the averaged -T_x
+(tests/golden/righting_moment_128.json); `other_configs` times the 128^3
+basin (cache resident), the 256x192x192 held box and the 48-instance heel
+sweep.  `cpu_baseline` times the FP64 oracle on the host on a bounded sample
+of the headline workload, on all cores and on one thread.
 
 Side experiments, each printed as JSON instead of the benchmark line:
 `--free-advection` (the sphere in the moving-wall channel, for every tau and
 wall speed of the paper's sweep), `--laplace` (resting droplets with surface
 tension against Laplace's law), `--copy-probe MIB` (a plain device copy that
-calibrates the HBM byte counters).
+calibrates the HBM byte counters).  `--profile CASE` runs only one timed case
+(for the profiler).
 """
 import argparse
 import hashlib
 import json
 import math
 import os
+import statistics
 import sys
 import time
 
@@ -43,9 +55,13 @@ if ROOT not in sys.path:
 
 METRIC = "MLUPS + % of HBM roofline (FP32 vs FP16-storage) at ≤1% righting-moment error"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_bulk_basin128_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_bulk_channel512_traffic.txt")
 GOLDEN_RM = os.path.join(ROOT, "tests", "golden", "righting_moment_128.json")
 SWEEP_SOURCES = ("paper_1201_0351_amd/csrc/k_sweep.hip", "paper_1201_0351_amd/csrc/lgs_internal.h")
+PREP_STEPS = 200
+WINDOWS = 5
+STORAGE_BYTES = {"fp32": 4, "fp16": 2, "bf16": 2}
+KERNEL_NAMES = {"fp32": "float", "fp16": "__half", "bf16": "__hip_bfloat16"}
 
 
 def sweep_source_hash():
@@ -57,8 +73,8 @@ def sweep_source_hash():
 
 
 def profiled_traffic(storage):
-    """HBM bytes per bulk-sweep launch from the committed counter summary,
-    if it was taken on the current kernel source; else None."""
+    """HBM bytes per bulk-sweep launch on the channel from the committed
+    counter summary, if it was taken on the current kernel source; else None."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -92,45 +108,87 @@ def algorithmic_bytes(types, storage_bytes, n_boundary):
                                                                   boundary_list=n_boundary)
 
 
-def run_gpu(storage, steps, warmup, host_update=0, timing=True):
+def _sync(L):
     import torch
 
-    from paper_1201_0351_amd import lbm
-    from paper_1201_0351_amd import workloads as W
+    L.sync()
+    torch.cuda.synchronize()
 
-    w = W.config2(20.0, released=True, storage=storage)
-    cfg = dict(w["lattice"], max_bodies=1, host_body_update=host_update)
-    L = lbm.Lattice(cfg)
-    # free body: the rigid-body update runs after every step
-    L.set_body(0, dict(w["bodies"][0], fixed=0, dof=w["dof"]))
+
+def run_case(workload, storage, steps, warmup, free=True, host_update=0, prep=0, timing=True, tune=True):
+    """Time K = `steps` full steps of one instance in WINDOWS windows (each
+    bracketed by synchronisation); then, with HIP events on the two sweep
+    kernels, the same number of steps again for the per-kernel times."""
+    from paper_1201_0351_amd import lbm
+
+    lat = dict(workload["lattice"], storage=storage)
+    L = lbm.Lattice(dict(lat, max_bodies=1, host_body_update=host_update))
+    b = dict(workload["bodies"][0])
+    if free:
+        b.update(fixed=0, dof=workload["dof"])
+    L.set_body(0, b)
+    if prep:
+        L.step(prep)
+    tuned = None
+    if tune:
+        tx, nt, _ = L.autotune(4)
+        tuned = dict(tile_x=tx, stream_store=nt)
     L.step(max(1, warmup))
-    types = L.types()
-    alg_bytes, counts = algorithmic_bytes(types, 4 if storage == "fp32" else 2, L.boundary_cells())
-    L.sync()
-    torch.cuda.synchronize()
-    # plain timed run (no events), then the same number of steps with the
-    # sweep kernels bracketed by HIP events
-    t0 = time.perf_counter()
-    L.step(steps)
-    L.sync()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    _sync(L)
+    # exactly `steps` timed steps in WINDOWS windows of nearly equal length
+    nwin = max(1, min(WINDOWS, steps))
+    sizes = [steps // nwin + (1 if k < steps % nwin else 0) for k in range(nwin)]
+    win = []
+    for per in sizes:
+        t0 = time.perf_counter()
+        L.step(per)
+        _sync(L)
+        win.append(1e3 * (time.perf_counter() - t0) / per)
+    ms = statistics.median(win)
     n = L.ncells()
-    res = dict(value=n * steps / dt / 1e6, ms_per_step=1e3 * dt / steps, cells=n, counts=counts, alg_bytes=alg_bytes)
+    types = L.types()
+    alg, counts = algorithmic_bytes(types, STORAGE_BYTES[storage], L.boundary_cells())
+    res = dict(value=n / ms / 1e3, ms_per_step=ms, ms_windows=[round(v, 5) for v in win], steps=sum(sizes),
+               cells=n, counts=counts, alg_bytes=alg, tuning=tuned)
     if timing:
         L.enable_kernel_timing(True)
-        L.step(steps)
+        L.step(max(1, steps))
         bulk_ms, launches = L.kernel_time(0)
         bnd_ms, _ = L.kernel_time(1)
         L.enable_kernel_timing(False)
         res.update(bulk_ms=bulk_ms / max(1, launches), boundary_ms=bnd_ms / max(1, launches))
     F, T = L.body_forces(0)
-    body = L.get_body(0)
-    q = body["quat"]
+    bd = L.get_body(0)
+    q = bd["quat"]
     res["body"] = dict(heel_deg=math.degrees(2.0 * math.atan2(q[1], q[0])), torque_x=float(T[0]),
-                       force_z=float(F[2]))
+                       force_z=float(F[2]), pos=[round(float(v), 4) for v in bd["pos"]])
     L.close()
     return res
+
+
+def kernel_rooflines(r, storage):
+    """Per-kernel achieved bandwidth (algorithmic bytes / event-timed
+    duration) of the two sweep kernels."""
+    out = {}
+    for k, key in (("bulk", "bulk_ms"), ("boundary", "boundary_ms")):
+        gbs = r["alg_bytes"][k] / (r[key] * 1e-3) / 1e9
+        out[k] = dict(avg_us=round(1e3 * r[key], 2), alg_bytes=r["alg_bytes"][k], achieved_gbs=round(gbs, 1),
+                      frac=round(gbs / HBM_PEAK_GBS, 4))
+    return out
+
+
+def roofline(r, storage):
+    achieved = r["alg_bytes"]["bulk"] / (r["bulk_ms"] * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(storage),
+            "kernel": "k_sweep_bulk<%s>" % KERNEL_NAMES[storage],
+            "alg_bytes_per_launch": r["alg_bytes"]["bulk"], "avg_launch_ms": round(r["bulk_ms"], 5)}
+
+
+def summary(r, storage):
+    return {"value": round(r["value"], 1), "ms_per_step": round(r["ms_per_step"], 4), "ms_windows": r["ms_windows"],
+            "roofline": roofline(r, storage), "kernels": kernel_rooflines(r, storage), "tuning": r["tuning"],
+            "body": r["body"]}
 
 
 def righting_moment(storage):
@@ -163,15 +221,11 @@ def righting_moment(storage):
 
 
 def _timed(L, steps, warmup):
-    import torch
-
     L.step(max(1, warmup))
-    L.sync()
-    torch.cuda.synchronize()
+    _sync(L)
     t0 = time.perf_counter()
     L.step(steps)
-    L.sync()
-    torch.cuda.synchronize()
+    _sync(L)
     return time.perf_counter() - t0
 
 
@@ -189,7 +243,7 @@ def run_batch(storage, steps, warmup, batched=True, graph=False):
         L.set_body(0, i["bodies"][0], inst=k)
     L.set_tuning(batched=int(batched), use_graph=int(graph))
     L.step(2)
-    tile, tune_ms = L.autotune(4)
+    tile, nt, tune_ms = L.autotune(4)
     dt = _timed(L, steps, warmup)
     cells = sum(L.ncells(k) for k in range(len(insts)))
     L.close()
@@ -198,34 +252,35 @@ def run_batch(storage, steps, warmup, batched=True, graph=False):
                 instance_steps_per_s=round(len(insts) * steps / dt, 1),
                 instances_per_s=round(len(insts) / (w["steps"] * dt / steps), 3),
                 note="instances_per_s: the %d-step heel sweep of all instances per second" % w["steps"],
-                batched=batched, graph=graph, autotuned_tile_x=tile)
-
-
-def run_single(workload, steps, warmup, free=False):
-    from paper_1201_0351_amd import lbm
-
-    L = lbm.Lattice(dict(workload["lattice"], max_bodies=1))
-    b = dict(workload["bodies"][0])
-    if free:
-        b.update(fixed=0, dof=workload["dof"])
-    L.set_body(0, b)
-    dt = _timed(L, steps, warmup)
-    n = L.ncells()
-    L.close()
-    return dict(cells=n, steps=steps, ms_per_step=round(1e3 * dt / steps, 4), mlups=round(n * steps / dt / 1e6, 1))
+                batched=batched, graph=graph, autotuned_tile_x=tile, autotuned_stream_store=nt)
 
 
 def other_configs(steps, warmup):
+    """The 128^3 basin (the released box, roll only; cache resident: its
+    160 MB per step fit the 256 MB cache in front of HBM), the 256x192x192
+    held box (FP32 / FP16 / BF16) and the 48-instance heel sweep."""
     from paper_1201_0351_amd import workloads as W
 
     out = {}
+    b128 = {}
+    for st in ("fp32", "fp16"):
+        r = run_case(W.config2(20.0, released=True), st, steps, warmup)
+        b128[st] = summary(r, st)
+    r = run_case(W.config2(20.0, released=True), "fp32", max(5, steps // 4), warmup, host_update=1, timing=False,
+                 tune=False)
+    b128["fp32_host_update"] = {"value": round(r["value"], 1), "ms_per_step": round(r["ms_per_step"], 4)}
+    b128["note"] = "cache resident (160 MB per FP32 step < 256 MB cache): not an HBM figure"
+    out["basin128_box32x32x16_released"] = b128
+    b3 = {}
+    for st in ("fp32", "fp16", "bf16"):
+        r = run_case(W.config3(20.0), st, steps, warmup, free=False)
+        b3[st] = summary(r, st)
+    b3["accuracy"] = "righting moment vs the FP64 oracle on the 128^3 geometry held at the same angles: " \
+                     "see righting_moment"
+    out["basin256x192x192_box64x64x32_heel20_held"] = b3
     out["batch48_heel_sweep"] = {st: run_batch(st, steps, warmup) for st in ("fp32", "fp16")}
     out["batch48_heel_sweep"]["fp32_one_launch_per_instance"] = run_batch("fp32", steps, warmup, batched=False)
     out["batch48_heel_sweep"]["fp32_graph"] = run_batch("fp32", steps, warmup, graph=True)
-    out["basin256x192x192_box64x64x32_heel20_held"] = {st: run_single(W.config3(20.0, st), steps, warmup)
-                                                      for st in ("fp32", "fp16", "bf16")}
-    out["channel512x256x256_box48x24x24_free"] = {st: run_single(W.config5(st), steps, warmup, free=True)
-                                                  for st in ("fp32", "fp16")}
     return out
 
 
@@ -331,31 +386,81 @@ def laplace(steps, sigma=1e-3, n=128, every=200):
                 steps=steps, rows=rows)
 
 
-def cpu_baseline(target_s=15.0):
-    """The FP64 oracle on the host cores: the same workload (128^3, box held at
-    20 deg), timed over as many steps as fit in about target_s seconds."""
-    from oracle.oracle import Oracle
+def channel_oracle(steps_all=2, steps_one=1):
+    """The FP64 oracle on the headline workload (the channel with its free
+    box, coupled host update after every step): one untimed step (it maps
+    the box), `steps_all` steps timed on all host cores, `steps_one` steps
+    timed on one thread.  Returns the timings and the body force, torque and
+    pose after the 1 + steps_all + steps_one steps."""
+    from oracle.oracle import Oracle, lib
     from paper_1201_0351_amd import workloads as W
 
     threads = min(16, os.cpu_count() or 1)
-    w = W.config2(20.0, released=False)
-    cfg = w["lattice"]
-    o = Oracle(cfg["nx"], cfg["ny"], cfg["nz"], cfg["tau"], accel=cfg["accel"], eps=cfg["eps"], threads=threads)
-    o.init_basin(cfg["fill_height"])
+    w = W.config5()
+    c = w["lattice"]
+    o = Oracle(c["nx"], c["ny"], c["nz"], c["tau"], accel=c["accel"], eps=c["eps"], periodic=c["periodic"],
+               threads=threads)
+    o.init_basin(c["fill_height"], c["init_ux_surface"])
     b = w["bodies"][0]
-    o.set_body(0, b["half"], b["pos"], b["quat"], b["vel"], b["omega"], b["density"], 1)
-    o.step(1)  # mapping + first step, untimed
+    o.set_body(0, b["half"], b["pos"], b["quat"], b["vel"], b["omega"], b["density"], 0)
+    o.step_coupled(1, [w["dof"]])
     t0 = time.perf_counter()
-    o.step(1)
-    one = time.perf_counter() - t0
-    k = max(1, min(50, int(target_s / max(one, 1e-3)) - 1))
+    o.step_coupled(steps_all, [w["dof"]])
+    t_all = time.perf_counter() - t0
+    lib().ob_set_threads(o._h, 1)
     t0 = time.perf_counter()
-    o.step(k)
-    dt = time.perf_counter() - t0
+    o.step_coupled(steps_one, [w["dof"]])
+    t_one = time.perf_counter() - t0
+    F, T = o.body_forces(0)
+    bd = o.get_body(0)
+    flags = o.get_flags()
     n = o.ncells
-    steps = k + 1
-    return dict(value=n * steps / (dt + one) / 1e6, unit="MLUPS", cores=threads, kind="oracle",
-                sample="%d steps of the 128^3 heeled-box basin (box held), FP64, %d OpenMP threads" % (steps, threads))
+    o.close()
+    return dict(threads=threads, n=n, steps_all=steps_all, t_all=t_all, steps_one=steps_one, t_one=t_one,
+                steps=1 + steps_all + steps_one, F=F, T=T, pos=bd["pos"], flags=flags)
+
+
+def channel_accuracy(ref, storages=("fp32", "fp16", "bf16")):
+    """The channel on the GPU for the oracle's number of steps from the same
+    initial state: error of the body force and torque of the last sweep,
+    relative to the oracle's vector and (since the box floats near balance,
+    so that the net force is a small difference of large link sums) to the
+    box's weight M g and M g h/2; the body position after the rigid-body
+    updates; and the cells whose type differs."""
+    from paper_1201_0351_amd import lbm
+    from paper_1201_0351_amd import workloads as W
+
+    b = W.config5()["bodies"][0]
+    g = abs(W.config5()["lattice"]["accel"][2])
+    weight = b["density"] * 8.0 * b["half"][0] * b["half"][1] * b["half"][2] * g
+    out = {"steps": ref["steps"], "reference": "FP64 oracle, same initial state, coupled host update every step",
+           "oracle_force": [float(v) for v in ref["F"]], "oracle_torque": [float(v) for v in ref["T"]],
+           "weight": weight}
+    for st in storages:
+        w = W.config5(st)
+        L = lbm.Lattice(dict(w["lattice"], max_bodies=1))
+        L.set_body(0, dict(w["bodies"][0], fixed=0, dof=w["dof"]))
+        L.step(ref["steps"])
+        F, T = L.body_forces(0)
+        pos = L.get_body(0)["pos"]
+        mism = int((L.flags() != ref["flags"]).sum())
+        L.close()
+        dF, dT = np.linalg.norm(F - ref["F"]), np.linalg.norm(T - ref["T"])
+        out[st] = dict(force_rel_err=float(dF / np.linalg.norm(ref["F"])),
+                       torque_rel_err=float(dT / np.linalg.norm(ref["T"])),
+                       force_err_of_weight=float(dF / weight), torque_err_of_weight_arm=float(dT / (weight * b["half"][2])),
+                       pos_err=float(np.abs(np.asarray(pos) - ref["pos"]).max()), flag_mismatches=mism,
+                       force=[float(v) for v in F], torque=[float(v) for v in T])
+    return out
+
+
+def cpu_baseline(ref):
+    n = ref["n"]
+    return dict(value=n * ref["steps_all"] / ref["t_all"] / 1e6, unit="MLUPS", cores=ref["threads"], kind="oracle",
+                sample="%d steps of the 512x256x256 channel with its free box (after one untimed mapping step), "
+                       "FP64, %d OpenMP threads; one_thread: %d more step(s) on 1 thread" % (
+                           ref["steps_all"], ref["threads"], ref["steps_one"]),
+                one_thread=dict(value=n * ref["steps_one"] / ref["t_one"] / 1e6, cores=1))
 
 
 def copy_probe(mib):
@@ -374,27 +479,17 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes_per_copy": 4 * n}))
 
 
-def roofline(r, storage):
-    achieved = r["alg_bytes"]["bulk"] / (r["bulk_ms"] * 1e-3) / 1e9
-    sweep_gbs = r["alg_bytes"]["total"] / ((r["bulk_ms"] + r["boundary_ms"]) * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(storage),
-            "kernel": "k_sweep_bulk<%s,64>" % ("float" if storage == "fp32" else "__half"),
-            "alg_bytes_per_launch": r["alg_bytes"]["bulk"], "avg_launch_ms": round(r["bulk_ms"], 5),
-            "sweep_both_kernels": {"alg_bytes": r["alg_bytes"]["total"],
-                                   "avg_ms": round(r["bulk_ms"] + r["boundary_ms"], 5),
-                                   "achieved": round(sweep_gbs, 1), "frac": round(sweep_gbs / HBM_PEAK_GBS, 4)}}
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-storage run")
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline and the accuracy check")
     ap.add_argument("--no-extra", action="store_true",
-                    help="only the timed runs (no host-update run, no righting moment)")
+                    help="only the headline and its FP16 / BF16 / host-update runs")
+    ap.add_argument("--profile", choices=["channel-fp32", "channel-fp16", "channel-bf16", "basin128-fp32",
+                                          "basin256-fp32", "basin256-fp16"],
+                    help="only run this timed case (for the profiler) and print its summary")
     ap.add_argument("--free-advection", action="store_true",
                     help="only run the paper's free advection sweep (Table tab:velocities) and print it as JSON")
     ap.add_argument("--laplace", action="store_true",
@@ -415,16 +510,27 @@ def main():
         print("bench.py: this build runs on one GPU only (the workload is a single-GPU lattice); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    from paper_1201_0351_amd import workloads as W
 
-    r32 = run_gpu("fp32", args.steps, args.warmup)
-    print("fp32: %.1f MLUPS, %.4f ms/step, bulk %.4f ms, boundary %.4f ms" % (
-        r32["value"], r32["ms_per_step"], r32["bulk_ms"], r32["boundary_ms"]), file=sys.stderr, flush=True)
+    if args.profile:
+        name, st = args.profile.split("-")
+        wl = {"channel": (W.config5(), True, PREP_STEPS), "basin128": (W.config2(20.0, released=True), True, 0),
+              "basin256": (W.config3(20.0), False, 0)}[name]
+        r = run_case(wl[0], st, args.steps, args.warmup, free=wl[1], prep=wl[2])
+        print(json.dumps(dict(case=args.profile, **summary(r, st))))
+        return
+
+    chan = W.config5()
+    r32 = run_case(chan, "fp32", args.steps, args.warmup, prep=PREP_STEPS)
+    print("channel fp32: %.1f MLUPS, %.4f ms/step (windows %s), bulk %.4f ms, boundary %.4f ms" % (
+        r32["value"], r32["ms_per_step"], r32["ms_windows"], r32["bulk_ms"], r32["boundary_ms"]),
+        file=sys.stderr, flush=True)
     out = {
         "metric": METRIC,
         "value": round(r32["value"], 1),
         "unit": "MLUPS",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": r32["steps"],
         "warmup": args.warmup,
         "ms_per_step": round(r32["ms_per_step"], 4),
         "higher_is_better": True,
@@ -432,29 +538,32 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "basin 128^3, tau 0.55, g 5e-6, depth 64, box 32x32x16 rho_s 0.5 released at "
-                               "20 deg heel (roll only), FP32 deviation storage, rigid-body update on the device",
+        "config": {"workload": "channel 512x256x256, periodic x and y, walls at z = 0 and 256, liquid depth 128, "
+                               "tau 0.8, g 1e-5, body-force drive for surface speed 0.05 (half-Poiseuille start), "
+                               "free 48x24x24 box of density 0.6 in 6 DOF, remap and conversions every step, FP32 "
+                               "deviation storage, rigid-body update on the device; prepared by %d steps from its "
+                               "start" % PREP_STEPS,
                    "cells": r32["cells"], "cell_types": r32["counts"]},
         "roofline": roofline(r32, "fp32"),
+        "kernels": kernel_rooflines(r32, "fp32"),
+        "ms_windows": r32["ms_windows"],
+        "tuning": r32["tuning"],
+        "body": r32["body"],
     }
-    from oracle import analytic as A
-
-    heel = r32["body"]["heel_deg"]
-    out["body"] = dict(r32["body"], analytic_righting_moment=A.righting_moment_polygon(
-        32, 16, 32, math.radians(heel), 5e-6, zw=0.0), note="dynamic roll; measured -T_x vs the static curve")
-    if not args.no_fp16:
-        r16 = run_gpu("fp16", args.steps, args.warmup)
-        out["fp16"] = {"value": round(r16["value"], 1), "ms_per_step": round(r16["ms_per_step"], 4),
-                       "roofline": roofline(r16, "fp16"), "body": r16["body"]}
-        print("fp16: %.1f MLUPS" % r16["value"], file=sys.stderr, flush=True)
+    chan_out = {}
+    for st in ("fp16", "bf16"):
+        r = run_case(W.config5(st), st, args.steps, args.warmup, prep=PREP_STEPS)
+        chan_out[st] = summary(r, st)
+        print("channel %s: %.1f MLUPS" % (st, r["value"]), file=sys.stderr, flush=True)
+    rh = run_case(chan, "fp32", max(5, args.steps // 4), args.warmup, prep=PREP_STEPS, host_update=1, timing=False,
+                  tune=False)
+    chan_out["fp32_host_update"] = {"value": round(rh["value"], 1), "ms_per_step": round(rh["ms_per_step"], 4),
+                                    "steps": rh["steps"]}
+    print("channel fp32 host update: %.1f MLUPS" % rh["value"], file=sys.stderr, flush=True)
+    out["channel"] = chan_out
     if not args.no_extra:
-        steps_h = max(1, args.steps // 4)
-        rh = run_gpu("fp32", steps_h, args.warmup, host_update=1, timing=False)
-        out["host_body_update"] = {"value": round(rh["value"], 1), "ms_per_step": round(rh["ms_per_step"], 4),
-                                   "steps": steps_h, "body": rh["body"]}
-        print("fp32 host update: %.1f MLUPS" % rh["value"], file=sys.stderr, flush=True)
         rm = {}
-        for st in ("fp32", "fp16"):
+        for st in ("fp32", "fp16", "bf16"):
             v = righting_moment(st)
             if v is not None:
                 rm[st] = v
@@ -462,10 +571,13 @@ def main():
             out["righting_moment"] = dict(rm, reference="FP64 oracle, held box, tests/golden/righting_moment_128.json",
                                           max_rel_err={k: round(max(x["rel_err"] for x in v), 5)
                                                        for k, v in rm.items()})
-        out["other_configs"] = other_configs(max(50, args.steps // 10), 20)
+        out["other_configs"] = other_configs(max(50, args.steps // 4), 20)
         print("other configs done", file=sys.stderr, flush=True)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline()
+        ref = channel_oracle()
+        out["accuracy"] = channel_accuracy(ref)
+        out["cpu_baseline"] = cpu_baseline(ref)
+        print("oracle done", file=sys.stderr, flush=True)
     print(json.dumps(out))
 
 

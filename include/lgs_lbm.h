@@ -258,16 +258,22 @@ int32_t lbm_kernel_time(lbm_ctx* ctx, int32_t kernel, double* total_ms, int64_t*
  * use_graph: lbm_step replays pairs of full steps from a captured HIP graph
  * when no instance updates free bodies on the host; the capture is redone
  * when the step parity or the set of instances that remap changes.
- * Synchronises.  Errors: LBM_ERR_INVALID for a bad width or mixed storage. */
-int32_t lbm_set_tuning(lbm_ctx* ctx, int32_t tile_x, int32_t batched, int32_t use_graph);
-int32_t lbm_get_tuning(lbm_ctx* ctx, int32_t* tile_x, int32_t* batched, int32_t* use_graph);
+ * stream_store: 1 = the bulk sweep writes the populations with
+ * non-temporal (streaming) stores that pass the caches: faster once the
+ * populations of a step exceed the 256 MiB cache in front of HBM, slower
+ * below it (the default follows that size).
+ * Synchronises.  Errors: LBM_ERR_INVALID for a bad width or flag, or mixed
+ * storage in a batch. */
+int32_t lbm_set_tuning(lbm_ctx* ctx, int32_t tile_x, int32_t batched, int32_t use_graph, int32_t stream_store);
+int32_t lbm_get_tuning(lbm_ctx* ctx, int32_t* tile_x, int32_t* batched, int32_t* use_graph, int32_t* stream_store);
 
 /* Autotuner: times reps launches of the bulk sweep on the current state for
- * every tile width and keeps the fastest.  The state does not change (the
- * sweep writes the lattice the next step overwrites; the boundary-list count
- * it appends to is reset).  Outputs (nullable): the chosen width and its
- * average launch time in ms.  Synchronises.  reps: 1..64. */
-int32_t lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* tile_x, double* best_ms);
+ * every tile width (32, 64, 128) and store policy (cached, streaming) and
+ * keeps the fastest of the six.  The state does not change (the sweep writes
+ * the lattice the next step overwrites; the boundary-list count it appends
+ * to is reset).  Outputs (nullable): the chosen width and store policy and
+ * their average launch time in ms.  Synchronises.  reps: 1..64. */
+int32_t lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* tile_x, int32_t* stream_store, double* best_ms);
 
 /* Number of cells the last sweep of an instance handled in the boundary
  * kernel (synchronises). */

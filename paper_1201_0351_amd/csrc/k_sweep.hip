@@ -161,13 +161,12 @@ __device__ __forceinline__ void collide(const Inst& I, const float (&d)[Q], floa
     }
 }
 
-template <typename S>
-__device__ __forceinline__ void collide_store(const Inst& I, const float (&d)[Q], S* __restrict__ dst, size_t N,
-                                              int id) {
+template <typename S, bool NT>
+__device__ __forceinline__ void collide_store(const Inst& I, const float (&d)[Q], S* __restrict__ dst, int id) {
     float o[Q];
     collide(I, d, o);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) Store<S>::store(dst, (size_t)i * I.ps + id, o[i], I.scale);
+    for (int i = 0; i < Q; ++i) Store<S>::template store<NT>(dst, (size_t)i * I.ps + id, o[i], I.scale);
 }
 
 }  // namespace
@@ -180,7 +179,7 @@ __device__ __forceinline__ void collide_store(const Inst& I, const float (&d)[Q]
 // mark): read the 18 source types, and clear the mark if none is gas or an
 // obstacle; without it every source is known to be liquid, interface or a
 // static wall.  The population loads go out first.
-template <typename S>
+template <typename S, bool NT>
 __device__ __forceinline__ bool bulk_cell(const Inst& I, const S* __restrict__ src, S* __restrict__ dst, int x, int y,
                                           int z, int id, bool chk) {
     float d[Q];
@@ -250,13 +249,13 @@ __device__ __forceinline__ bool bulk_cell(const Inst& I, const S* __restrict__ s
         if (bad) return true;
         I.nearo[id] = 0;
     }
-    collide_store<S>(I, d, dst, I.ps, id);
+    collide_store<S, NT>(I, d, dst, id);
     return false;
 }
 
 // Workgroup b of nb (nb a multiple of 8, b % 8 the XCD it runs on) of one
 // instance's bulk grid.
-template <typename S, int TX, bool W>
+template <typename S, int TX, bool W, bool NT>
 __device__ __forceinline__ void sweep_bulk(const Inst& I, int parity, int b, int nb) {
     constexpr int TY = 256 / TX;
     const int tiles_x = (I.nx + TX - 1) / TX, tiles_y = (I.ny + TY - 1) / TY;
@@ -297,25 +296,26 @@ __device__ __forceinline__ void sweep_bulk(const Inst& I, int parity, int b, int
                        (!(I.periodic & 2) && (y == 0 || y == I.ny - 1)) ||
                        (!(I.periodic & 4) && (z == 0 || z == I.nz - 1)));
     bool defer = (type == IFC) || (type == LIQ && wall);
-    if (type == LIQ && !wall) defer = bulk_cell<S>(I, src, dst, x, y, z, id, near);
+    if (type == LIQ && !wall) defer = bulk_cell<S, NT>(I, src, dst, x, y, z, id, near);
     block_append<4>(defer, id, I.bnd, &C.n_bnd, I.list_cap, &C.overflow);
 }
 
 // At most 64 VGPRs, so that eight wavefronts fit per SIMD.  W: the lattice
-// has moving walls (a variant without their test runs otherwise).
-template <typename S, int TX, bool W>
+// has moving walls (a variant without their test runs otherwise).  NT:
+// non-temporal population stores.
+template <typename S, int TX, bool W, bool NT>
 __global__ __launch_bounds__(256, 8) void k_sweep_bulk(Inst I, int parity) {
-    sweep_bulk<S, TX, W>(I, parity, blockIdx.x, gridDim.x);
+    sweep_bulk<S, TX, W, NT>(I, parity, blockIdx.x, gridDim.x);
 }
 
 // all instances of a batch in one launch (instance table in device memory;
 // the copied descriptor needs registers of its own, so no 64-VGPR bound)
-template <typename S, int TX>
+template <typename S, int TX, bool NT>
 __global__ __launch_bounds__(256) void kb_sweep_bulk(const Inst* __restrict__ tab, const int* __restrict__ off, int n,
                                                      int parity) {
     const int k = batch_instance(off, n, blockIdx.x);
     const Inst I = tab[k];
-    sweep_bulk<S, TX, true>(I, parity, blockIdx.x - off[k], off[k + 1] - off[k]);
+    sweep_bulk<S, TX, true, NT>(I, parity, blockIdx.x - off[k], off[k + 1] - off[k]);
 }
 
 // ---------------------------------------------------------------------------
@@ -723,42 +723,53 @@ int bulk_blocks(const Inst& I, int tile_x) {
 }
 
 namespace {
-template <typename S, int TX>
+template <typename S, int TX, bool NT>
 void bulk_one(const Inst& I, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const dim3 g(bulk_blocks(I, TX)), b(256);
-    if (I.wall_moving) hipExtLaunchKernelGGL((k_sweep_bulk<S, TX, true>), g, b, 0, s, e0, e1, 0, I, parity);
-    else hipExtLaunchKernelGGL((k_sweep_bulk<S, TX, false>), g, b, 0, s, e0, e1, 0, I, parity);
+    if (I.wall_moving) hipExtLaunchKernelGGL((k_sweep_bulk<S, TX, true, NT>), g, b, 0, s, e0, e1, 0, I, parity);
+    else hipExtLaunchKernelGGL((k_sweep_bulk<S, TX, false, NT>), g, b, 0, s, e0, e1, 0, I, parity);
 }
-template <typename S, int TX>
+template <typename S, int TX, bool NT>
 void bulk_batch(const BatchGrid& G, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    hipExtLaunchKernelGGL((kb_sweep_bulk<S, TX>), dim3(G.blocks), dim3(256), 0, s, e0, e1, 0, G.tab, G.off, G.n,
+    hipExtLaunchKernelGGL((kb_sweep_bulk<S, TX, NT>), dim3(G.blocks), dim3(256), 0, s, e0, e1, 0, G.tab, G.off, G.n,
                           parity);
 }
-template <typename S>
+template <typename S, int TX, bool NT>
+void bulk_go(const Inst* I, const BatchGrid* G, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (I) bulk_one<S, TX, NT>(*I, parity, s, e0, e1);
+    else bulk_batch<S, TX, NT>(*G, parity, s, e0, e1);
+}
+template <typename S, bool NT>
 void bulk_tx(int tile_x, const Inst* I, const BatchGrid* G, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     switch (tile_x) {
-    case 32: I ? bulk_one<S, 32>(*I, parity, s, e0, e1) : bulk_batch<S, 32>(*G, parity, s, e0, e1); break;
-    case 128: I ? bulk_one<S, 128>(*I, parity, s, e0, e1) : bulk_batch<S, 128>(*G, parity, s, e0, e1); break;
-    default: I ? bulk_one<S, 64>(*I, parity, s, e0, e1) : bulk_batch<S, 64>(*G, parity, s, e0, e1); break;
+    case 32: bulk_go<S, 32, NT>(I, G, parity, s, e0, e1); break;
+    case 128: bulk_go<S, 128, NT>(I, G, parity, s, e0, e1); break;
+    default: bulk_go<S, 64, NT>(I, G, parity, s, e0, e1); break;
     }
 }
-void bulk_dispatch(int storage, int tile_x, const Inst* I, const BatchGrid* G, int parity, hipStream_t s,
+template <typename S>
+void bulk_nt(int tile_x, bool nt, const Inst* I, const BatchGrid* G, int parity, hipStream_t s, hipEvent_t e0,
+             hipEvent_t e1) {
+    if (nt) bulk_tx<S, true>(tile_x, I, G, parity, s, e0, e1);
+    else bulk_tx<S, false>(tile_x, I, G, parity, s, e0, e1);
+}
+void bulk_dispatch(int storage, int tile_x, bool nt, const Inst* I, const BatchGrid* G, int parity, hipStream_t s,
                    hipEvent_t e0, hipEvent_t e1) {
     switch (storage) {
-    case LBM_FP16_DEV: bulk_tx<__half>(tile_x, I, G, parity, s, e0, e1); break;
-    case LBM_BF16_DEV: bulk_tx<__hip_bfloat16>(tile_x, I, G, parity, s, e0, e1); break;
-    default: bulk_tx<float>(tile_x, I, G, parity, s, e0, e1); break;
+    case LBM_FP16_DEV: bulk_nt<__half>(tile_x, nt, I, G, parity, s, e0, e1); break;
+    case LBM_BF16_DEV: bulk_nt<__hip_bfloat16>(tile_x, nt, I, G, parity, s, e0, e1); break;
+    default: bulk_nt<float>(tile_x, nt, I, G, parity, s, e0, e1); break;
     }
 }
 }  // namespace
 
-void launch_sweep_bulk(const Inst& I, int parity, int tile_x, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    bulk_dispatch(I.storage, tile_x, &I, nullptr, parity, s, e0, e1);
+void launch_sweep_bulk(const Inst& I, int parity, int tile_x, bool nt, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    bulk_dispatch(I.storage, tile_x, nt, &I, nullptr, parity, s, e0, e1);
 }
 
-void launch_sweep_bulk_batch(const BatchGrid& G, int storage, int tile_x, int parity, hipStream_t s, hipEvent_t e0,
-                             hipEvent_t e1) {
-    bulk_dispatch(storage, tile_x, nullptr, &G, parity, s, e0, e1);
+void launch_sweep_bulk_batch(const BatchGrid& G, int storage, int tile_x, bool nt, int parity, hipStream_t s,
+                             hipEvent_t e0, hipEvent_t e1) {
+    bulk_dispatch(storage, tile_x, nt, nullptr, &G, parity, s, e0, e1);
 }
 
 void launch_sweep_boundary(const Inst& I, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {

@@ -184,37 +184,21 @@ __device__ __forceinline__ float* phi_of(const Inst& I, int p) { return p ? I.ph
 // --------------------------------------------------------------------------
 template <typename S>
 struct Store;
-// Streaming accesses of the sweep: `load` / `store`; random accesses: `ld` /
-// `st`.  LGS_STREAM_NT_LOAD / LGS_STREAM_NT_STORE select non-temporal
-// (streaming) cache policy for the sweep's population traffic.
-#ifndef LGS_STREAM_NT_LOAD
-#define LGS_STREAM_NT_LOAD 0
-#endif
-#ifndef LGS_STREAM_NT_STORE
-#define LGS_STREAM_NT_STORE 0
-#endif
-template <typename T>
-__device__ __forceinline__ T stream_load(const T* p) {
-#if LGS_STREAM_NT_LOAD
-    return __builtin_nontemporal_load(p);
-#else
-    return *p;
-#endif
-}
-template <typename T>
+// Streaming accesses of the sweep: `load` / `store` (`store<true>`:
+// non-temporal, streaming past the caches, for lattices larger than the cache
+// in front of HBM); random accesses: `ld` / `st`.
+template <bool NT, typename T>
 __device__ __forceinline__ void stream_store(T v, T* p) {
-#if LGS_STREAM_NT_STORE
-    __builtin_nontemporal_store(v, p);
-#else
-    *p = v;
-#endif
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
 }
 
 template <>
 struct Store<float> {
-    __device__ static inline float load(const float* p, size_t k, float) { return stream_load(p + k); }
+    __device__ static inline float load(const float* p, size_t k, float) { return p[k]; }
     __device__ static inline float ld(const float* p, size_t k, float) { return p[k]; }
-    __device__ static inline void store(float* p, size_t k, float v, float) { stream_store(v, p + k); }
+    template <bool NT = false>
+    __device__ static inline void store(float* p, size_t k, float v, float) { stream_store<NT>(v, p + k); }
     __device__ static inline void st(float* p, size_t k, float v, float) { p[k] = v; }
 };
 // 16-bit storage: the bits are moved as unsigned short so the streaming
@@ -240,22 +224,22 @@ __device__ __forceinline__ unsigned short f2b(float f) {
 template <>
 struct Store<__half> {
     using U = unsigned short;
-    __device__ static inline float load(const __half* p, size_t k, float inv) {
-        return h2f(stream_load((const U*)p + k)) * inv;
-    }
+    __device__ static inline float load(const __half* p, size_t k, float inv) { return h2f(((const U*)p)[k]) * inv; }
     __device__ static inline float ld(const __half* p, size_t k, float inv) { return h2f(((const U*)p)[k]) * inv; }
-    __device__ static inline void store(__half* p, size_t k, float v, float sc) { stream_store(f2h(v * sc), (U*)p + k); }
+    template <bool NT = false>
+    __device__ static inline void store(__half* p, size_t k, float v, float sc) {
+        stream_store<NT>(f2h(v * sc), (U*)p + k);
+    }
     __device__ static inline void st(__half* p, size_t k, float v, float sc) { ((U*)p)[k] = f2h(v * sc); }
 };
 template <>
 struct Store<__hip_bfloat16> {
     using U = unsigned short;
-    __device__ static inline float load(const __hip_bfloat16* p, size_t k, float) {
-        return b2f(stream_load((const U*)p + k));
-    }
+    __device__ static inline float load(const __hip_bfloat16* p, size_t k, float) { return b2f(((const U*)p)[k]); }
     __device__ static inline float ld(const __hip_bfloat16* p, size_t k, float) { return b2f(((const U*)p)[k]); }
+    template <bool NT = false>
     __device__ static inline void store(__hip_bfloat16* p, size_t k, float v, float) {
-        stream_store(f2b(v), (U*)p + k);
+        stream_store<NT>(f2b(v), (U*)p + k);
     }
     __device__ static inline void st(__hip_bfloat16* p, size_t k, float v, float) { ((U*)p)[k] = f2b(v); }
 };
@@ -613,8 +597,9 @@ struct BatchGrid {
 // cells along x, 256 / width rows), padded to a multiple of 8
 int bulk_blocks(const Inst& I, int tile_x);
 
-// e0 / e1: optional events recorded at the start / end of the kernel itself
-void launch_sweep_bulk(const Inst& I, int parity, int tile_x, hipStream_t s, hipEvent_t e0 = nullptr,
+// e0 / e1: optional events recorded at the start / end of the kernel itself;
+// nt: non-temporal population stores
+void launch_sweep_bulk(const Inst& I, int parity, int tile_x, bool nt, hipStream_t s, hipEvent_t e0 = nullptr,
                        hipEvent_t e1 = nullptr);
 // Mean curvature of the cells of this step's boundary list (surface tension
 // only; after the bulk sweep, before the boundary sweep).
@@ -622,7 +607,7 @@ void launch_curvature(const Inst& I, int parity, hipStream_t s);
 void launch_curvature_batch(const BatchGrid& G, int parity, hipStream_t s);
 void launch_sweep_boundary(const Inst& I, int parity, hipStream_t s, hipEvent_t e0 = nullptr,
                            hipEvent_t e1 = nullptr);
-void launch_sweep_bulk_batch(const BatchGrid& G, int storage, int tile_x, int parity, hipStream_t s,
+void launch_sweep_bulk_batch(const BatchGrid& G, int storage, int tile_x, bool nt, int parity, hipStream_t s,
                              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void launch_sweep_boundary_batch(const BatchGrid& G, int storage, int parity, hipStream_t s, hipEvent_t e0 = nullptr,
                                  hipEvent_t e1 = nullptr);

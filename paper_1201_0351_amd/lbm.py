@@ -79,9 +79,9 @@ def library():
         "lbm_kernel_time": [vp, i32, dp, C.POINTER(C.c_int64)],
         "lbm_boundary_cells": [vp, i32, C.POINTER(C.c_int64)],
         "lbm_integrate_body": [C.POINTER(lbm_body), dp, dp, dp, C.c_uint32, C.POINTER(lbm_body)],
-        "lbm_set_tuning": [vp, i32, i32, i32],
-        "lbm_get_tuning": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
-        "lbm_autotune": [vp, i32, C.POINTER(i32), dp],
+        "lbm_set_tuning": [vp, i32, i32, i32, i32],
+        "lbm_get_tuning": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
+        "lbm_autotune": [vp, i32, C.POINTER(i32), C.POINTER(i32), dp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -226,23 +226,24 @@ class Lattice:
         return np.array(F[:]), np.array(T[:])
 
     # ---- launch configuration ----------------------------------------------
-    def set_tuning(self, tile_x=None, batched=None, use_graph=None):
+    def set_tuning(self, tile_x=None, batched=None, use_graph=None, stream_store=None):
         cur = self.get_tuning()
-        _check(library().lbm_set_tuning(self._h, int(cur["tile_x"] if tile_x is None else tile_x),
-                                        int(cur["batched"] if batched is None else batched),
-                                        int(cur["use_graph"] if use_graph is None else use_graph)))
+        pick = lambda v, k: int(cur[k] if v is None else v)  # noqa: E731
+        _check(library().lbm_set_tuning(self._h, pick(tile_x, "tile_x"), pick(batched, "batched"),
+                                        pick(use_graph, "use_graph"), pick(stream_store, "stream_store")))
 
     def get_tuning(self):
-        t, b, g = C.c_int32(), C.c_int32(), C.c_int32()
-        _check(library().lbm_get_tuning(self._h, C.byref(t), C.byref(b), C.byref(g)))
-        return dict(tile_x=t.value, batched=b.value, use_graph=g.value)
+        t, b, g, n = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(library().lbm_get_tuning(self._h, C.byref(t), C.byref(b), C.byref(g), C.byref(n)))
+        return dict(tile_x=t.value, batched=b.value, use_graph=g.value, stream_store=n.value)
 
     def autotune(self, reps=8):
-        """Time the bulk sweep for every tile width on the current state and
-        keep the fastest; returns (width, ms per launch)."""
-        t, ms = C.c_int32(), C.c_double()
-        _check(library().lbm_autotune(self._h, int(reps), C.byref(t), C.byref(ms)))
-        return t.value, ms.value
+        """Time the bulk sweep for every tile width and store policy on the
+        current state and keep the fastest; returns (width, stream_store, ms
+        per launch)."""
+        t, n, ms = C.c_int32(), C.c_int32(), C.c_double()
+        _check(library().lbm_autotune(self._h, int(reps), C.byref(t), C.byref(n), C.byref(ms)))
+        return t.value, n.value, ms.value
 
     # ---- stepping ---------------------------------------------------------
     def step(self, n=1):

@@ -916,9 +916,9 @@ def test_graph_replay_with_surface_tension(lbm):
 
 
 def test_autotune_keeps_state(lbm):
-    """The autotuner sweeps the current state for every tile width without
-    changing it: afterwards the context advances exactly like an untouched
-    one (held bodies, bit for bit)."""
+    """The autotuner sweeps the current state for every tile width and store
+    policy without changing it: afterwards the context advances exactly like
+    an untouched one (held bodies, bit for bit), also with streaming stores."""
     cfgs = [W.basin((64, 40, 36), 18.0, 0.6, 1e-5, seed=41, noise_amp=1e-4),
             W.basin((96, 32, 30), 15.0, 0.6, 1e-5, seed=42, noise_amp=1e-4)]
     A = lbm.Lattice([dict(c, max_bodies=1) for c in cfgs])
@@ -926,10 +926,14 @@ def test_autotune_keeps_state(lbm):
     for L in (A, B):
         L.set_body(0, W.box((12, 12, 6), (32, 20, 18), 12.0, 0.5), inst=0)
         L.step(7)
-    tx, ms = A.autotune(reps=3)
-    say("autotune: tile %d, %.4f ms" % (tx, ms))
-    assert tx in (32, 64, 128) and ms > 0
-    assert A.get_tuning()["tile_x"] == tx
+    tx, nt, ms = A.autotune(reps=3)
+    say("autotune: tile %d, stream_store %d, %.4f ms" % (tx, nt, ms))
+    assert tx in (32, 64, 128) and nt in (0, 1) and ms > 0
+    assert A.get_tuning()["tile_x"] == tx and A.get_tuning()["stream_store"] == nt
+    # streaming stores write the same values: force them on A, leave B on the
+    # default (cached stores at this size)
+    assert B.get_tuning()["stream_store"] == 0
+    A.set_tuning(stream_store=1)
     A.step(9)
     B.step(9)
     for k in range(2):
