@@ -161,12 +161,24 @@ __device__ __forceinline__ void collide(const Inst& I, const float (&d)[Q], floa
     }
 }
 
+// Post-collision deviations to the 19 planes of cell id.  fits (uniform):
+// the planes span less than 2^32 bytes, so buffer stores take the cell's
+// byte offset once and a uniform offset per plane.
 template <typename S, bool NT>
-__device__ __forceinline__ void collide_store(const Inst& I, const float (&d)[Q], S* __restrict__ dst, int id) {
+__device__ __forceinline__ void collide_store(const Inst& I, const float (&d)[Q], S* __restrict__ dst, int id,
+                                              bool fits) {
     float o[Q];
     collide(I, d, o);
+    if (fits) {
+        const uint32_t psb = (uint32_t)(I.ps * sizeof(S));
+        const auto rd = buf_rsrc(dst, (uint32_t)Q * psb);
+        const uint32_t ub = (uint32_t)id * (uint32_t)sizeof(S);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) Store<S>::template store<NT>(dst, (size_t)i * I.ps + id, o[i], I.scale);
+        for (int i = 0; i < Q; ++i) BufIO<S>::template store<NT>(rd, ub, (uint32_t)i * psb, o[i], I.scale);
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) Store<S>::template store<NT>(dst, (size_t)i * I.ps + id, o[i], I.scale);
+    }
 }
 
 }  // namespace
@@ -192,7 +204,8 @@ __device__ __forceinline__ bool bulk_cell(const Inst& I, const S* __restrict__ s
     // path for those lanes made each wavefront wait for one set of loads
     // before issuing the other.  Other wavefronts take the general sources
     // for all their lanes.
-    const bool inner = y > 0 && y < ny - 1 && z > 0 && z < I.nz - 1 && (size_t)Q * I.ps * sizeof(S) <= 0xFFFFFFFFull;
+    const bool fits = (size_t)Q * I.ps * sizeof(S) <= 0xFFFFFFFFull;
+    const bool inner = y > 0 && y < ny - 1 && z > 0 && z < I.nz - 1 && fits;
     // decided per wavefront, so that exactly one of the two load paths runs
     const bool row = __builtin_amdgcn_readfirstlane((int)(__ballot(!inner) == 0ull)) != 0;
     const bool xlo = x == 0, xhi = x == nx - 1;
@@ -216,17 +229,37 @@ __device__ __forceinline__ bool bulk_cell(const Inst& I, const S* __restrict__ s
         return (X | Y | Z) >= 0 ? X + nx * (Y + ny * Z) : -1;
     };
     if (row) {
-        const uint32_t ps = (uint32_t)I.ps, uid = (uint32_t)id;
-        const uint32_t wrap = (uint32_t)nx;
+        // Buffer loads: the source of link i is plane i at this cell's byte
+        // offset ub, shifted by the link: a uniform offset per link.  An
+        // x-face lane takes its periodic image (ub +- one row) or, at a wall,
+        // its own f_ibar (plane ibar at ub); for walls the uniform offset is
+        // the smaller of the two planes' so that both lane offsets are
+        // non-negative.
+        const uint32_t psb = (uint32_t)(I.ps * sizeof(S));
+        const auto rs = buf_rsrc(src, (uint32_t)Q * psb);
+        const uint32_t ub = (uint32_t)id * (uint32_t)sizeof(S);
+        const uint32_t wrapb = (uint32_t)nx * (uint32_t)sizeof(S);
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-            // element offset of the source population from plane 0
-            uint32_t e = (uint32_t)i * ps + uid - (uint32_t)(cx(i) + sxy * cy(i) + sz * cz(i));
-            const uint32_t wall = (uint32_t)opp(i) * ps + uid;
-            if (cx(i) == 1) e = xlo ? (px ? e + wrap : wall) : e;
-            if (cx(i) == -1) e = xhi ? (px ? e - wrap : wall) : e;
-            d[i] = Store<S>::load((const S*)((const char*)src + e * (uint32_t)sizeof(S)), 0, I.inv_scale);
+            const int sh = (cx(i) + sxy * cy(i) + sz * cz(i)) * (int)sizeof(S);
+            const uint32_t bn = (uint32_t)i * psb - (uint32_t)sh;
+            if (cx(i) == 0) {
+                d[i] = BufIO<S>::load(rs, ub, bn, I.inv_scale);
+            } else {
+                const bool face = cx(i) == 1 ? xlo : xhi;
+                uint32_t vo, so;
+                if (px) {
+                    so = bn;
+                    vo = face ? (cx(i) == 1 ? ub + wrapb : ub - wrapb) : ub;
+                } else {
+                    const uint32_t bw = (uint32_t)opp(i) * psb;
+                    so = bn < bw ? bn : bw;
+                    vo = ub + ((face ? bw : bn) - so);
+                }
+                d[i] = BufIO<S>::load(rs, vo, so, I.inv_scale);
+            }
         }
+        d[0] = BufIO<S>::load(rs, ub, 0u, I.inv_scale);
     } else {
         // a wall source is the halfway bounce-back: this cell's own f_ibar
 #pragma unroll
@@ -235,8 +268,8 @@ __device__ __forceinline__ bool bulk_cell(const Inst& I, const S* __restrict__ s
             d[i] = Store<S>::load(src + (size_t)(s >= 0 ? i : opp(i)) * I.ps, (unsigned)(s >= 0 ? s : id),
                                   I.inv_scale);
         }
+        d[0] = Store<S>::load(src, (size_t)id, I.inv_scale);
     }
-    d[0] = Store<S>::load(src, id, I.inv_scale);
     if (chk) {
         uint32_t bad = 0;
 #pragma unroll
@@ -249,7 +282,7 @@ __device__ __forceinline__ bool bulk_cell(const Inst& I, const S* __restrict__ s
         if (bad) return true;
         I.nearo[id] = 0;
     }
-    collide_store<S, NT>(I, d, dst, id);
+    collide_store<S, NT>(I, d, dst, id, fits);
     return false;
 }
 

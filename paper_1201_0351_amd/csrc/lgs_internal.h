@@ -244,6 +244,49 @@ struct Store<__hip_bfloat16> {
     __device__ static inline void st(__hip_bfloat16* p, size_t k, float v, float) { ((U*)p)[k] = f2b(v); }
 };
 
+// Buffer access to the population planes of one lattice: a gfx9 buffer
+// resource (base, byte range, default format word) with a per-lane byte
+// offset (VGPR) and a uniform byte offset (SGPR), so that the 19 planes of a
+// cell share one per-lane offset and a plane costs no per-lane address
+// arithmetic.  The planes must span less than 2^32 bytes.
+constexpr int BUF_RSRC_WORD3 = 0x00020000;
+constexpr int BUF_NT = 2;  // the nt (non-temporal) cache-policy bit of gfx94x / gfx950 buffer accesses
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, BUF_RSRC_WORD3);
+}
+template <typename S>
+struct BufIO;
+template <>
+struct BufIO<float> {
+    __device__ static inline float load(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
+    }
+    template <bool NT>
+    __device__ static inline void store(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float v, float) {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)vo, (int)so, NT ? BUF_NT : 0);
+    }
+};
+template <>
+struct BufIO<__half> {
+    __device__ static inline float load(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float inv) {
+        return h2f(__builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, 0)) * inv;
+    }
+    template <bool NT>
+    __device__ static inline void store(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float v, float sc) {
+        __builtin_amdgcn_raw_buffer_store_b16(f2h(v * sc), r, (int)vo, (int)so, NT ? BUF_NT : 0);
+    }
+};
+template <>
+struct BufIO<__hip_bfloat16> {
+    __device__ static inline float load(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float) {
+        return b2f(__builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, 0));
+    }
+    template <bool NT>
+    __device__ static inline void store(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float v, float) {
+        __builtin_amdgcn_raw_buffer_store_b16(f2b(v), r, (int)vo, (int)so, NT ? BUF_NT : 0);
+    }
+};
+
 // --------------------------------------------------------------------------
 // neighbour arithmetic: coordinate of x + d on an axis of length n, or -1
 // beyond a wall
