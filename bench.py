@@ -131,8 +131,8 @@ def run_case(workload, storage, steps, warmup, free=True, host_update=0, prep=0,
         L.step(prep)
     tuned = None
     if tune:
-        tx, nt, _ = L.autotune(4)
-        tuned = dict(tile_x=tx, stream_store=nt)
+        t = L.autotune(4)
+        tuned = dict(tile_x=t["tile_x"], stream_store=t["stream_store"], boundary_layout=t["boundary_layout"])
     L.step(max(1, warmup))
     _sync(L)
     # exactly `steps` timed steps in WINDOWS windows of nearly equal length
@@ -243,7 +243,7 @@ def run_batch(storage, steps, warmup, batched=True, graph=False):
         L.set_body(0, i["bodies"][0], inst=k)
     L.set_tuning(batched=int(batched), use_graph=int(graph))
     L.step(2)
-    tile, nt, tune_ms = L.autotune(4)
+    tuned = L.autotune(4)
     dt = _timed(L, steps, warmup)
     cells = sum(L.ncells(k) for k in range(len(insts)))
     L.close()
@@ -252,7 +252,8 @@ def run_batch(storage, steps, warmup, batched=True, graph=False):
                 instance_steps_per_s=round(len(insts) * steps / dt, 1),
                 instances_per_s=round(len(insts) / (w["steps"] * dt / steps), 3),
                 note="instances_per_s: the %d-step heel sweep of all instances per second" % w["steps"],
-                batched=batched, graph=graph, autotuned_tile_x=tile, autotuned_stream_store=nt)
+                batched=batched, graph=graph, autotuned={k: tuned[k] for k in ("tile_x", "stream_store",
+                                                                                "boundary_layout")})
 
 
 def other_configs(steps, warmup):

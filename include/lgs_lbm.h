@@ -262,18 +262,30 @@ int32_t lbm_kernel_time(lbm_ctx* ctx, int32_t kernel, double* total_ms, int64_t*
  * non-temporal (streaming) stores that pass the caches: faster once the
  * populations of a step exceed the 256 MiB cache in front of HBM, slower
  * below it (the default follows that size).
+ * boundary_layout: work layout of the boundary sweep (interface cells and
+ * liquid cells next to gas or a body): 0 = 8 lanes per cell, the links
+ * shared through LDS (short lists); 1 = one thread per cell (long lists,
+ * coalesced loads).  Both compute the same rules.
  * Synchronises.  Errors: LBM_ERR_INVALID for a bad width or flag, or mixed
  * storage in a batch. */
-int32_t lbm_set_tuning(lbm_ctx* ctx, int32_t tile_x, int32_t batched, int32_t use_graph, int32_t stream_store);
-int32_t lbm_get_tuning(lbm_ctx* ctx, int32_t* tile_x, int32_t* batched, int32_t* use_graph, int32_t* stream_store);
+int32_t lbm_set_tuning(lbm_ctx* ctx, int32_t tile_x, int32_t batched, int32_t use_graph, int32_t stream_store,
+                       int32_t boundary_layout);
+int32_t lbm_get_tuning(lbm_ctx* ctx, int32_t* tile_x, int32_t* batched, int32_t* use_graph, int32_t* stream_store,
+                       int32_t* boundary_layout);
 
-/* Autotuner: times reps launches of the bulk sweep on the current state for
- * every tile width (32, 64, 128) and store policy (cached, streaming) and
- * keeps the fastest of the six.  The state does not change (the sweep writes
- * the lattice the next step overwrites; the boundary-list count it appends
- * to is reset).  Outputs (nullable): the chosen width and store policy and
- * their average launch time in ms.  Synchronises.  reps: 1..64. */
-int32_t lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* tile_x, int32_t* stream_store, double* best_ms);
+/* Autotuner.  First the bulk sweep: reps launches on the current state for
+ * every tile width (32, 64, 128) and store policy (cached, streaming), the
+ * fastest of the six kept.  Then the boundary sweep: reps launches with each
+ * work layout, the faster kept (skipped, layout unchanged and boundary_ms
+ * -1, when the device has no room for a copy of the interface cells' mass,
+ * flags and counters, 9 bytes per cell).  The state does not change: the
+ * sweeps write the lattice the next step overwrites, the boundary sweep's
+ * in-place updates are undone from that copy after every launch, and the
+ * boundary-list count is reset.  Outputs (nullable): the chosen width, store
+ * policy and layout, and the average launch times in ms.  Synchronises.
+ * reps: 1..64. */
+int32_t lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* tile_x, int32_t* stream_store, int32_t* boundary_layout,
+                     double* bulk_ms, double* boundary_ms);
 
 /* Number of cells the last sweep of an instance handled in the boundary
  * kernel (synchronises). */

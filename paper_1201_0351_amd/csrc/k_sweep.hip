@@ -371,6 +371,65 @@ __device__ __forceinline__ float osum(float v) {
 }
 }  // namespace
 
+// The momentum-exchange record of boundary workgroup wg: every thread's
+// FP64 partial sum (of the first body it met, rec_body) is summed per body
+// over the wavefront in order of first appearance, then the workgroup's
+// record from its wavefronts' records in wavefront order; contributions to
+// a second body go to the accumulators by atomics.  Every thread calls it.
+__device__ __forceinline__ void force_record(const Inst& I, StepCounters& C, int wg, int rec_body,
+                                             const double (&rv)[6]) {
+    // wavefront sums per body (in order of first appearance), then the
+    // workgroup's record from its wavefronts' records in wavefront order
+    int wbody = -1;
+    double wv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    unsigned long long m = __ballot(rec_body >= 0);
+    while (m) {
+        const int leader = __ffsll((long long)m) - 1;
+        const int b = __shfl(rec_body, leader);
+        const bool mine = rec_body == b;
+        double v[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) v[q] = wave_sum(mine ? rv[q] : 0.0);
+        if (wbody < 0) wbody = b;
+        if (b == wbody) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) wv[q] += v[q];
+        } else if (lane_id() == leader) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) atomicAdd(&C.acc[b][q], v[q]);
+        }
+        m &= ~__ballot(mine);
+    }
+    __shared__ int sb[4];
+    __shared__ double sv[4][6];
+    const int wv_id = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        sb[wv_id] = wbody;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) sv[wv_id][q] = wv[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int body = -1;
+        double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int w = 0; w < 4; ++w) {
+            const int b = sb[w];
+            if (b < 0) continue;
+            if (body < 0) body = b;
+            if (b == body) {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) acc[q] += sv[w][q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) atomicAdd(&C.acc[b][q], sv[w][q]);
+            }
+        }
+        I.frec_body[wg] = body;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) I.frec_v[q * BND_BLOCKS_MAX + wg] = acc[q];
+    }
+}
+
 // Workgroup wg of nwg of one instance's boundary grid (wg is its
 // force-record slot).
 template <typename S, bool W>
@@ -679,56 +738,330 @@ __device__ __forceinline__ void sweep_boundary(const Inst& I, int parity, int wg
         __syncthreads();  // the next pass overwrites the LDS arrays
     }
 
-    // wavefront sums per body (in order of first appearance), then the
-    // workgroup's record from its wavefronts' records in wavefront order
-    int wbody = -1;
-    double wv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    unsigned long long m = __ballot(rec_body >= 0);
-    while (m) {
-        const int leader = __ffsll((long long)m) - 1;
-        const int b = __shfl(rec_body, leader);
-        const bool mine = rec_body == b;
-        double v[6];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) v[q] = wave_sum(mine ? rv[q] : 0.0);
-        if (wbody < 0) wbody = b;
-        if (b == wbody) {
-#pragma unroll
-            for (int q = 0; q < 6; ++q) wv[q] += v[q];
-        } else if (lane_id() == leader) {
-#pragma unroll
-            for (int q = 0; q < 6; ++q) atomicAdd(&C.acc[b][q], v[q]);
+    force_record(I, C, wg, rec_body, rv);
+}
+
+// ---------------------------------------------------------------------------
+// boundary sweep, one thread per listed cell: the rules and operations of the
+// 8-lane kernel link by link.  The bulk sweep lists cells in tile order, so
+// consecutive entries are mostly consecutive cells of a row and every load
+// of a wavefront is one coalesced segment, and a long list (a large free
+// surface) is in flight at once instead of in serial passes of 32 cells
+// per workgroup.  The sources are taken one link at a time (after the six
+// that give the interface normal), so that only the cell's own and incoming
+// populations stay live.  BUF: 32-bit buffer offsets (every array of the
+// instance below 4 GiB).
+// ---------------------------------------------------------------------------
+template <typename S, bool BUF>
+struct BndIO {
+    const S* src;
+    S* dst;
+    const float* phi;
+    const uint8_t* fl;
+    __amdgpu_buffer_rsrc_t rs, rd, rp, rf;
+    uint32_t psb;
+    size_t ps;
+    float isc, sc;
+    __device__ BndIO(const Inst& I, int parity) {
+        src = (const S*)pop_of(I, parity);
+        dst = (S*)pop_of(I, parity ^ 1);
+        phi = phi_of(I, parity);
+        fl = I.flags;
+        ps = I.ps;
+        psb = (uint32_t)(I.ps * sizeof(S));
+        isc = I.inv_scale;
+        sc = I.scale;
+        if (BUF) {
+            rs = buf_rsrc(src, (size_t)Q * I.ps * sizeof(S));
+            rd = buf_rsrc(dst, (size_t)Q * I.ps * sizeof(S));
+            rp = buf_rsrc(phi, (size_t)I.N * 4);
+            rf = buf_rsrc(fl, (size_t)I.N);
         }
-        m &= ~__ballot(mine);
     }
-    __shared__ int sb[4];
-    __shared__ double sv[4][6];
-    const int wv_id = threadIdx.x >> 6;
-    if (lane_id() == 0) {
-        sb[wv_id] = wbody;
-#pragma unroll
-        for (int q = 0; q < 6; ++q) sv[wv_id][q] = wv[q];
+    __device__ float pop(int i, int c) const {
+        if (BUF) return BufIO<S>::load(rs, (uint32_t)c * (uint32_t)sizeof(S), (uint32_t)i * psb, isc);
+        return Store<S>::ld(src, (size_t)i * ps + c, isc);
+    }
+    __device__ void put(int i, int c, float v) const {
+        if (BUF) BufIO<S>::template store<false>(rd, (uint32_t)c * (uint32_t)sizeof(S), (uint32_t)i * psb, v, sc);
+        else Store<S>::store(dst, (size_t)i * ps + c, v, sc);
+    }
+    __device__ float fill(int c) const {
+        if (BUF) return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rp, (int)((uint32_t)c * 4u), 0, 0));
+        return phi[c];
+    }
+    __device__ int flag(int c) const {
+        if (BUF) return (int)__builtin_amdgcn_raw_buffer_load_b8(rf, (int)c, 0, 0);
+        return (int)fl[c];
+    }
+};
+
+template <typename S, bool W, bool BUF>
+__device__ __forceinline__ void sweep_boundary1(const Inst& I, int parity, int wg, int nwg) {
+    const BndIO<S, BUF> io(I, parity);
+    StepCounters& C = I.ctl->cnt[parity];
+    const int nlist = min(C.n_bnd, I.list_cap);
+    const bool px = I.periodic & 1, py = I.periodic & 2, pz = I.periodic & 4;
+    const int nx = I.nx, ny = I.ny, nz = I.nz, sxy = nx, sz = nx * ny;
+    int rec_body = -1;
+    double rv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    __shared__ double bpos[MAXB][3];
+    __shared__ float bvel[MAXB][3], bom[MAXB][3];
+    if ((int)threadIdx.x < I.nbodies * 3) {
+        const int b = threadIdx.x / 3, a = threadIdx.x % 3;
+        const DevBody& B = I.bodies[b];
+        bpos[b][a] = B.pos[a];
+        bvel[b][a] = (float)B.vel[a];
+        bom[b][a] = (float)B.omega[a];
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int body = -1;
-        double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int w = 0; w < 4; ++w) {
-            const int b = sb[w];
-            if (b < 0) continue;
-            if (body < 0) body = b;
-            if (b == body) {
+
+    for (int base = wg * 256; base < nlist; base += nwg * 256) {
+        const int k = base + (int)threadIdx.x;
+        const bool active = k < nlist;
+        const int id = I.bnd[active ? k : base];
+        int x, y, z;
+        cell_coords(I, id, x, y, z);
+        const int fl = io.flag(id);
+        const int type = fl & TYPE_MASK;
+        const bool ifc = type == IFC;
+        const bool face = x == 0 || x == nx - 1 || y == 0 || y == ny - 1 || z == 0 || z == nz - 1;
+        // source s_i = x - c_i, or -1 beyond a wall
+        auto source = [&](int i) -> int {
+            if (!face) return id - (cx(i) + sxy * cy(i) + sz * cz(i));
+            const int X = step_axis(x, -cx(i), nx, px), Y = step_axis(y, -cy(i), ny, py);
+            const int Z = step_axis(z, -cz(i), nz, pz);
+            return (X | Y | Z) >= 0 ? X + nx * (Y + ny * Z) : -1;
+        };
+
+        // the cell's own f_i(x, t) and its moments
+        float dx[Q];
 #pragma unroll
-                for (int q = 0; q < 6; ++q) acc[q] += sv[w][q];
+        for (int i = 0; i < Q; ++i) dx[i] = io.pop(i, id);
+        float drx = 0.f, jx0 = 0.f, jx1 = 0.f, jx2 = 0.f;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            drx += dx[i];
+            jx0 += cx(i) * dx[i];
+            jx1 += cy(i) * dx[i];
+            jx2 += cz(i) * dx[i];
+        }
+        const float rhox = 1.f + drx;
+        const float ux0 = jx0 / rhox, ux1 = jx1 / rhox, ux2 = jx2 / rhox;
+        const float uu = ux0 * ux0 + ux1 * ux1 + ux2 * ux2;
+        const float phix = ifc ? io.fill(id) : 1.f;
+        const float mhi0 = ifc ? I.m_hi[id] : 0.f, mlo0 = ifc ? I.m_lo[id] : 0.f;
+
+        // interface normal n = -grad(phi) from the sources of links 1..6
+        // (wall / obstacle: own fill), FP64 sign test
+        double n0 = 0.0, n1 = 0.0, n2 = 0.0, nthr = 0.0;
+        if (ifc && I.recon_mode != LBM_RECON_GAS_ONLY) {
+            double f[7];
+#pragma unroll
+            for (int i = 1; i <= 6; ++i) {
+                const int s = source(i);
+                const int e = s >= 0 ? io.flag(s) : -1;
+                const int st = e & TYPE_MASK;
+                double v = (double)phix;
+                if (e >= 0 && st == LIQ) v = 1.0;
+                else if (e >= 0 && st == GAS) v = 0.0;
+                else if (e >= 0 && st == IFC) v = (double)io.fill(s);
+                f[i] = v;
+            }
+            n0 = 0.5 * (f[2] - f[1]);
+            n1 = 0.5 * (f[3] - f[4]);
+            n2 = 0.5 * (f[5] - f[6]);
+            nthr = NORMAL_TOL * ((fabs(n0) + fabs(n1)) + fabs(n2));
+        }
+
+        // gas density of this cell's reconstruction
+        float rg = I.rho_g;
+        if (I.lap != 0.f && ifc) rg += I.lap * I.kap[id];
+
+        // per source s_i: mass exchange of link ibar (x + c_ibar = s_i),
+        // liquid contact, incoming population f_i(x) and momentum exchange
+        // with a body
+        float pdm = 0.f;
+        int liq = 0;
+        float d[Q];
+        d[0] = dx[0];
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f, a5 = 0.f;
+        int abody = -1;
+        const float xc0 = x + 0.5f, xc1 = y + 0.5f, xc2 = z + 0.5f;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const int o = opp(i);
+            const int s = source(i);
+            const int sa = s >= 0 ? s : id;
+            const int e = s >= 0 ? io.flag(sa) : -1;
+            const float dri = io.pop(i, sa);  // f_i(x - c_i)
+            const int st = e & TYPE_MASK;
+            const float dxo = dx[o];
+            if (e >= 0 && st == LIQ) liq = 1;
+            if (ifc && e >= 0) {
+                const float ex = dri - dxo;  // f_i(x + c_ibar) - f_ibar(x)
+                if (st == LIQ) pdm += ex;
+                else if (st == IFC) pdm += 0.5f * (phix + io.fill(sa)) * ex;
+            }
+            const float cxf = (float)cx(i), cyf = (float)cy(i), czf = (float)cz(i);
+            const float wi = wgt(i);
+            float di = dri;
+            if (e < 0 || st == OBS) {
+                float cu = 0.f;
+                int bk = -1;
+                float r0 = 0.f, r1 = 0.f, r2 = 0.f;
+                if (e >= 0) {
+                    bk = (e >> 2) & 15;
+                    // body velocity at the link midpoint x_c - c_i/2
+                    const float q0 = (float)wrap_rel(xc0 - 0.5f * cxf - bpos[bk][0], nx, px);
+                    const float q1 = (float)wrap_rel(xc1 - 0.5f * cyf - bpos[bk][1], ny, py);
+                    const float q2 = (float)wrap_rel(xc2 - 0.5f * czf - bpos[bk][2], nz, pz);
+                    const float w0 = bom[bk][0], w1 = bom[bk][1], w2 = bom[bk][2];
+                    const float u0 = bvel[bk][0] + (w1 * q2 - w2 * q1);
+                    const float u1 = bvel[bk][1] + (w2 * q0 - w0 * q2);
+                    const float u2 = bvel[bk][2] + (w0 * q1 - w1 * q0);
+                    cu = cxf * u0 + cyf * u1 + czf * u2;
+                    r0 = (float)wrap_rel(xc0 - bpos[bk][0], nx, px);
+                    r1 = (float)wrap_rel(xc1 - bpos[bk][1], ny, py);
+                    r2 = (float)wrap_rel(xc2 - bpos[bk][2], nz, pz);
+                }
+                if (W && e < 0) cu = cxf * I.wall_u[0] + cyf * I.wall_u[1] + czf * I.wall_u[2];  // a moving wall
+                const float mw = 6.f * wi * rhox * cu;
+                di = dxo + mw;
+                if (bk >= 0 && active) {
+                    // momentum the fluid gains on this link (deviation form);
+                    // the body receives the opposite
+                    const float phat = type == LIQ ? 1.f : phix;
+                    const float amp = 2.f * phat * (dxo + wi * (1.f - I.rho_g) + 0.5f * mw);
+                    const float j0 = amp * cxf, j1 = amp * cyf, j2 = amp * czf;
+                    const float t3 = r1 * j2 - r2 * j1, t4 = r2 * j0 - r0 * j2, t5 = r0 * j1 - r1 * j0;
+                    if (abody < 0) abody = bk;
+                    if (bk == abody) {
+                        a0 -= j0;
+                        a1 -= j1;
+                        a2 -= j2;
+                        a3 -= t3;
+                        a4 -= t4;
+                        a5 -= t5;
+                    } else {
+                        double* acc = &C.acc[bk][0];
+                        atomicAdd(acc + 0, (double)-j0);
+                        atomicAdd(acc + 1, (double)-j1);
+                        atomicAdd(acc + 2, (double)-j2);
+                        atomicAdd(acc + 3, (double)-t3);
+                        atomicAdd(acc + 4, (double)-t4);
+                        atomicAdd(acc + 5, (double)-t5);
+                    }
+                }
             } else {
+                bool recon = st == GAS;
+                if (!recon && ifc && I.recon_mode != LBM_RECON_GAS_ONLY) {
+                    const double cn = cxf * n0 + cyf * n1 + czf * n2;
+                    recon = I.recon_mode == LBM_RECON_GAS_SIDE ? (cn < -nthr) : (cn <= nthr);
+                }
+                if (recon) {
+                    const float cu = cxf * ux0 + cyf * ux1 + czf * ux2;
+                    di = 2.f * wi * (rg * (1.f + 4.5f * cu * cu - 1.5f * uu) - 1.f) - dxo;
+                }
+            }
+            d[i] = di;
+        }
+
+        // moments after streaming, fill level and marks, collision
+        float drho = 0.f, j0 = 0.f, j1 = 0.f, j2 = 0.f;
 #pragma unroll
-                for (int q = 0; q < 6; ++q) atomicAdd(&C.acc[b][q], sv[w][q]);
+        for (int i = 0; i < Q; ++i) {
+            drho += d[i];
+            j0 += cx(i) * d[i];
+            j1 += cy(i) * d[i];
+            j2 += cz(i) * d[i];
+        }
+        const float rho = 1.f + drho;
+        bool cand = false, strd = false;
+        if (active && ifc) {
+            float mhi = mhi0, mlo = mlo0;
+            two_sum_add(mhi, mlo, pdm);
+            const float ph = (float)(((double)mhi + (double)mlo) / (1.0 + (double)drho));
+            const double phd = (double)ph;
+            uint8_t mark = 0;
+            if (phd >= 1.0 + I.eps) mark = MARK_FILL;
+            else if (phd <= -I.eps) mark = MARK_EMPTY;
+            I.m_hi[id] = mhi;
+            I.m_lo[id] = mlo;
+            phi_of(I, parity ^ 1)[id] = ph;
+            I.aux[id] = drho;
+            I.lnb[id] = (uint8_t)liq;
+            if (mark) {
+                I.flags[id] = (uint8_t)((fl & KEEP_MASK) | mark);
+                cand = true;
+            }
+            strd = !mark && !liq;
+        }
+        wave_append(cand, id, I.cand, &C.n_cand, I.list_cap, &C.overflow);
+        wave_append(strd, id, I.recv, &C.n_strd, I.list_cap, &C.overflow);
+        if (active) {
+            const float irho = 1.f / rho;
+            const float u0 = j0 * irho, u1 = j1 * irho, u2 = j2 * irho;
+            const float uq = 1.5f * (u0 * u0 + u1 * u1 + u2 * u2);
+            const float ua = u0 * I.ax + u1 * I.ay + u2 * I.az;
+            if (!(rho > 0.f && rho < 1e6f)) atomicOr(&I.ctl->nonfinite, 1);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const float cxf = (float)cx(i), cyf = (float)cy(i), czf = (float)cz(i);
+                const float wi = wgt(i);
+                const float cu = cxf * u0 + cyf * u1 + czf * u2;
+                const float ca = cxf * I.ax + cyf * I.ay + czf * I.az;
+                const float deq = wi * (drho + rho * (3.f * cu + 4.5f * cu * cu - uq));
+                const float F = wi * rho * (3.f * (ca - ua) + 9.f * cu * ca);
+                io.put(i, id, d[i] + I.omega * (deq - d[i]) + F);
+            }
+            if (abody >= 0) {
+                if (rec_body < 0) rec_body = abody;
+                if (abody == rec_body) {
+                    rv[0] += (double)a0;
+                    rv[1] += (double)a1;
+                    rv[2] += (double)a2;
+                    rv[3] += (double)a3;
+                    rv[4] += (double)a4;
+                    rv[5] += (double)a5;
+                } else {
+                    double* acc = &C.acc[abody][0];
+                    atomicAdd(acc + 0, (double)a0);
+                    atomicAdd(acc + 1, (double)a1);
+                    atomicAdd(acc + 2, (double)a2);
+                    atomicAdd(acc + 3, (double)a3);
+                    atomicAdd(acc + 4, (double)a4);
+                    atomicAdd(acc + 5, (double)a5);
+                }
             }
         }
-        I.frec_body[wg] = body;
-#pragma unroll
-        for (int q = 0; q < 6; ++q) I.frec_v[q * BND_BLOCKS_MAX + wg] = acc[q];
     }
+    force_record(I, C, wg, rec_body, rv);
+}
+
+// every array of the instance addressable with 32-bit byte offsets
+__host__ __device__ inline bool bnd_buf_fits(const Inst& I, size_t elem) {
+    return (size_t)Q * I.ps * elem <= 0xFFFFFFFFull && (size_t)I.N * 4 <= 0xFFFFFFFFull;
+}
+
+// one thread per cell; LGS_BND1_WAVES wavefronts per SIMD
+#ifndef LGS_BND1_WAVES
+#define LGS_BND1_WAVES 3
+#endif
+template <typename S, bool W, bool BUF>
+__global__ __launch_bounds__(256, LGS_BND1_WAVES) void k_sweep_boundary1(Inst I, int parity) {
+    sweep_boundary1<S, W, BUF>(I, parity, blockIdx.x, gridDim.x);
+}
+
+template <typename S>
+__global__ __launch_bounds__(256, LGS_BND1_WAVES) void kb_sweep_boundary1(const Inst* __restrict__ tab, const int* __restrict__ off,
+                                                          int n, int parity) {
+    const int k = batch_instance(off, n, blockIdx.x);
+    const Inst I = tab[k];
+    const int b = blockIdx.x - off[k];
+    if (b >= boundary_blocks(I)) return;  // padding of the grid to a multiple of 8
+    if (bnd_buf_fits(I, sizeof(S))) sweep_boundary1<S, true, true>(I, parity, b, boundary_blocks(I));
+    else sweep_boundary1<S, true, false>(I, parity, b, boundary_blocks(I));
 }
 
 template <typename S, bool W>
@@ -805,36 +1138,45 @@ void launch_sweep_bulk_batch(const BatchGrid& G, int storage, int tile_x, bool n
     bulk_dispatch(storage, tile_x, nt, nullptr, &G, parity, s, e0, e1);
 }
 
-void launch_sweep_boundary(const Inst& I, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+namespace {
+template <typename S, bool W>
+void boundary_one(const Inst& I, int parity, int layout, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const dim3 g(boundary_blocks(I)), b(256);
+    if (layout && bnd_buf_fits(I, sizeof(S)))
+        hipExtLaunchKernelGGL((k_sweep_boundary1<S, W, true>), g, b, 0, s, e0, e1, 0, I, parity);
+    else if (layout) hipExtLaunchKernelGGL((k_sweep_boundary1<S, W, false>), g, b, 0, s, e0, e1, 0, I, parity);
+    else hipExtLaunchKernelGGL((k_sweep_boundary<S, W>), g, b, 0, s, e0, e1, 0, I, parity);
+}
+template <typename S>
+void boundary_batch(const BatchGrid& G, int parity, int layout, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const dim3 g(G.blocks), b(256);
+    if (layout) hipExtLaunchKernelGGL(kb_sweep_boundary1<S>, g, b, 0, s, e0, e1, 0, G.tab, G.off, G.n, parity);
+    else hipExtLaunchKernelGGL(kb_sweep_boundary<S>, g, b, 0, s, e0, e1, 0, G.tab, G.off, G.n, parity);
+}
+}  // namespace
+
+void launch_sweep_boundary(const Inst& I, int parity, int layout, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const bool w = I.wall_moving != 0;
     switch (I.storage) {
     case LBM_FP16_DEV:
-        if (w) hipExtLaunchKernelGGL((k_sweep_boundary<__half, true>), g, b, 0, s, e0, e1, 0, I, parity);
-        else hipExtLaunchKernelGGL((k_sweep_boundary<__half, false>), g, b, 0, s, e0, e1, 0, I, parity);
+        w ? boundary_one<__half, true>(I, parity, layout, s, e0, e1) : boundary_one<__half, false>(I, parity, layout, s, e0, e1);
         break;
     case LBM_BF16_DEV:
-        if (w) hipExtLaunchKernelGGL((k_sweep_boundary<__hip_bfloat16, true>), g, b, 0, s, e0, e1, 0, I, parity);
-        else hipExtLaunchKernelGGL((k_sweep_boundary<__hip_bfloat16, false>), g, b, 0, s, e0, e1, 0, I, parity);
+        w ? boundary_one<__hip_bfloat16, true>(I, parity, layout, s, e0, e1)
+          : boundary_one<__hip_bfloat16, false>(I, parity, layout, s, e0, e1);
         break;
     default:
-        if (w) hipExtLaunchKernelGGL((k_sweep_boundary<float, true>), g, b, 0, s, e0, e1, 0, I, parity);
-        else hipExtLaunchKernelGGL((k_sweep_boundary<float, false>), g, b, 0, s, e0, e1, 0, I, parity);
+        w ? boundary_one<float, true>(I, parity, layout, s, e0, e1) : boundary_one<float, false>(I, parity, layout, s, e0, e1);
         break;
     }
 }
 
-void launch_sweep_boundary_batch(const BatchGrid& G, int storage, int parity, hipStream_t s, hipEvent_t e0,
+void launch_sweep_boundary_batch(const BatchGrid& G, int storage, int parity, int layout, hipStream_t s, hipEvent_t e0,
                                  hipEvent_t e1) {
-    const dim3 g(G.blocks), b(256);
     switch (storage) {
-    case LBM_FP16_DEV:
-        hipExtLaunchKernelGGL(kb_sweep_boundary<__half>, g, b, 0, s, e0, e1, 0, G.tab, G.off, G.n, parity);
-        break;
-    case LBM_BF16_DEV:
-        hipExtLaunchKernelGGL(kb_sweep_boundary<__hip_bfloat16>, g, b, 0, s, e0, e1, 0, G.tab, G.off, G.n, parity);
-        break;
-    default: hipExtLaunchKernelGGL(kb_sweep_boundary<float>, g, b, 0, s, e0, e1, 0, G.tab, G.off, G.n, parity); break;
+    case LBM_FP16_DEV: boundary_batch<__half>(G, parity, layout, s, e0, e1); break;
+    case LBM_BF16_DEV: boundary_batch<__hip_bfloat16>(G, parity, layout, s, e0, e1); break;
+    default: boundary_batch<float>(G, parity, layout, s, e0, e1); break;
     }
 }
 

@@ -209,6 +209,7 @@ struct lbm_ctx {
     size_t ev_used = 0;
     int tile_x = 64;  // bulk-sweep tile width (cells along x)
     bool nt_store = false;  // non-temporal population stores in the bulk sweep
+    int bnd_layout = 0;     // boundary sweep: 0 = 8 lanes per cell, 1 = one thread per cell
     // batches: all instances of the context step with one launch per kernel
     // (instance table and workgroup offsets at the head of the workspace)
     bool batched = false;
@@ -632,7 +633,8 @@ static int run_step_batched(lbm_ctx* c) {
     bool tension = false;
     for (int k = 0; k < n; ++k) tension |= c->inst[k].dev.lap != 0.f;
     if (tension) launch_curvature_batch(BatchGrid{c->d_tab, c->d_bnd_off, n, c->bnd_total}, p, c->stream);
-    launch_sweep_boundary_batch(BatchGrid{c->d_tab, c->d_bnd_off, n, c->bnd_total}, storage, p, c->stream, e[2], e[3]);
+    launch_sweep_boundary_batch(BatchGrid{c->d_tab, c->d_bnd_off, n, c->bnd_total}, storage, p, c->bnd_layout, c->stream,
+                                e[2], e[3]);
     for (int g = 0; g < n; g += 64) {
         const int ng = std::min(64, n - g);
         unsigned long long rm = 0, im = 0;
@@ -679,7 +681,7 @@ static int run_step(lbm_ctx* c, int mask) {
             if (rc) return rc;
             launch_sweep_bulk(h.dev, p, c->tile_x, c->nt_store, c->stream, e[0], e[1]);
             if (h.dev.lap != 0.f) launch_curvature(h.dev, p, c->stream);
-            launch_sweep_boundary(h.dev, p, c->stream, e[2], e[3]);
+            launch_sweep_boundary(h.dev, p, c->bnd_layout, c->stream, e[2], e[3]);
         } else if (mask & LBM_PHASE_CONVERT) {
             hipLaunchKernelGGL(k_copy_state, dim3((h.dev.N + 255) / 256), dim3(256), 0, c->stream, h.dev, p);
             launch_mark(h.dev, p, c->stream);
@@ -786,10 +788,13 @@ __global__ void k_reset_bnd(Ctl* ctl, int parity) {
     }
 }
 
-int32_t lbm_set_tuning(lbm_ctx* c, int32_t tile_x, int32_t batched, int32_t use_graph, int32_t stream_store) {
+int32_t lbm_set_tuning(lbm_ctx* c, int32_t tile_x, int32_t batched, int32_t use_graph, int32_t stream_store,
+                       int32_t boundary_layout) {
     if (!c) return fail(LBM_ERR_INVALID, "context is NULL");
     if (tile_x != 32 && tile_x != 64 && tile_x != 128) return fail(LBM_ERR_INVALID, "set_tuning: tile_x must be 32, 64 or 128");
     if (stream_store != 0 && stream_store != 1) return fail(LBM_ERR_INVALID, "set_tuning: stream_store must be 0 or 1");
+    if (boundary_layout != 0 && boundary_layout != 1)
+        return fail(LBM_ERR_INVALID, "set_tuning: boundary_layout must be 0 or 1");
     if (batched) {
         for (int k = 1; k < c->n_inst; ++k)
             if (c->inst[k].cfg.storage != c->inst[0].cfg.storage)
@@ -799,21 +804,110 @@ int32_t lbm_set_tuning(lbm_ctx* c, int32_t tile_x, int32_t batched, int32_t use_
     drop_graph(c);
     c->tile_x = tile_x;
     c->nt_store = stream_store != 0;
+    c->bnd_layout = boundary_layout;
     c->batched = batched != 0 && c->n_inst > 1;
     c->use_graph = use_graph != 0;
     return upload_batch(c);
 }
 
-int32_t lbm_get_tuning(lbm_ctx* c, int32_t* tile_x, int32_t* batched, int32_t* use_graph, int32_t* stream_store) {
+int32_t lbm_get_tuning(lbm_ctx* c, int32_t* tile_x, int32_t* batched, int32_t* use_graph, int32_t* stream_store,
+                       int32_t* boundary_layout) {
     if (!c) return fail(LBM_ERR_INVALID, "context is NULL");
     if (tile_x) *tile_x = c->tile_x;
     if (batched) *batched = c->batched ? 1 : 0;
     if (use_graph) *use_graph = c->use_graph ? 1 : 0;
     if (stream_store) *stream_store = c->nt_store ? 1 : 0;
+    if (boundary_layout) *boundary_layout = c->bnd_layout;
     return LBM_OK;
 }
 
-int32_t lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* tile_x, int32_t* stream_store, double* best_ms) {
+// Times the boundary sweep of the current state with both work layouts and
+// keeps the faster.  The sweep updates the interface cells' mass and marks in
+// place and appends to the step counters, so those are saved after one bulk
+// sweep (which lists the cells) and restored after every launch.  Without
+// room for the copies the layout stays as it is (out_ms < 0).
+static int tune_boundary(lbm_ctx* c, int reps, hipEvent_t e0, hipEvent_t e1, double* out_ms) {
+    *out_ms = -1.0;
+    const int p = c->parity;
+    const int n = c->n_inst;
+    std::vector<char*> saved(n, nullptr);
+    auto cnt_of = [&](int k) { return (void*)&c->inst[k].dev.ctl->cnt[p]; };
+    auto off = [&](int k) { return ((size_t)c->inst[k].dev.N * 9 + 255) / 256 * 256; };
+    bool room = true;
+    for (int k = 0; k < n && room; ++k)
+        room = hipMalloc((void**)&saved[k], off(k) + sizeof(StepCounters)) == hipSuccess;
+    (void)hipGetLastError();
+    int rc = LBM_OK;
+    auto copies = [&](bool save) {
+        for (int k = 0; k < n; ++k) {
+            const Inst& I = c->inst[k].dev;
+            const size_t N = (size_t)I.N;
+            void* dev[4] = {I.m_hi, I.m_lo, I.flags, cnt_of(k)};
+            void* keep[4] = {saved[k], saved[k] + 4 * N, saved[k] + 8 * N, saved[k] + off(k)};
+            const size_t bytes[4] = {4 * N, 4 * N, N, sizeof(StepCounters)};
+            for (int q = 0; q < 4; ++q)
+                (void)hipMemcpyAsync(save ? keep[q] : dev[q], save ? dev[q] : keep[q], bytes[q],
+                                     hipMemcpyDeviceToDevice, c->stream);
+        }
+    };
+    const BatchGrid bnd{c->d_tab, c->d_bnd_off, n, c->bnd_total};
+    auto boundary = [&](hipEvent_t a, hipEvent_t b) {
+        if (c->batched) launch_sweep_boundary_batch(bnd, c->inst[0].cfg.storage, p, c->bnd_layout, c->stream, a, b);
+        else
+            for (InstHost& h : c->inst) launch_sweep_boundary(h.dev, p, c->bnd_layout, c->stream, a, b);
+    };
+    if (room) {
+        // the state a step's boundary sweep starts from
+        if (c->batched) {
+            launch_sweep_bulk_batch(BatchGrid{c->d_tab, c->d_bulk_off, n, c->bulk_total}, c->inst[0].cfg.storage,
+                                    c->tile_x, c->nt_store, p, c->stream);
+            bool tension = false;
+            for (int k = 0; k < n; ++k) tension |= c->inst[k].dev.lap != 0.f;
+            if (tension) launch_curvature_batch(bnd, p, c->stream);
+        } else {
+            for (InstHost& h : c->inst) {
+                launch_sweep_bulk(h.dev, p, c->tile_x, c->nt_store, c->stream);
+                if (h.dev.lap != 0.f) launch_curvature(h.dev, p, c->stream);
+            }
+        }
+        copies(true);
+        const int keep = c->bnd_layout;
+        double best_t = 1e30;
+        int best = keep;
+        for (int layout = 0; layout < 2 && rc == LBM_OK; ++layout) {
+            c->bnd_layout = layout;
+            boundary(nullptr, nullptr);
+            copies(false);
+            double total = 0.0;
+            for (int r = 0; r < reps && rc == LBM_OK; ++r) {
+                if (hipEventRecord(e0, c->stream) != hipSuccess) rc = fail(LBM_ERR_DEVICE, "autotune: event failed");
+                boundary(nullptr, nullptr);
+                if (hipEventRecord(e1, c->stream) != hipSuccess) rc = fail(LBM_ERR_DEVICE, "autotune: event failed");
+                copies(false);
+                float ms = 0.f;
+                if (rc == LBM_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                    rc = fail(LBM_ERR_DEVICE, "autotune: timing failed");
+                total += ms;
+            }
+            if (rc == LBM_OK && hipGetLastError() != hipSuccess) rc = fail(LBM_ERR_DEVICE, "autotune: launch failed");
+            if (rc == LBM_OK && total / reps < best_t) {
+                best_t = total / reps;
+                best = layout;
+            }
+        }
+        c->bnd_layout = rc == LBM_OK ? best : keep;
+        if (rc == LBM_OK) *out_ms = best_t;
+        // the list count back to the start of the step
+        for (InstHost& h : c->inst) hipLaunchKernelGGL(k_reset_bnd, dim3(1), dim3(64), 0, c->stream, h.dev.ctl, p);
+        if (hipStreamSynchronize(c->stream) != hipSuccess && rc == LBM_OK) rc = fail(LBM_ERR_DEVICE, "autotune: sync failed");
+    }
+    for (char* q : saved)
+        if (q) (void)hipFree(q);
+    return rc;
+}
+
+int32_t lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* tile_x, int32_t* stream_store, int32_t* boundary_layout,
+                     double* bulk_ms, double* boundary_ms) {
     if (!c) return fail(LBM_ERR_INVALID, "context is NULL");
     if (reps <= 0 || reps > 64) return fail(LBM_ERR_INVALID, "autotune: reps must be 1..64");
     HIP_OK(hipStreamSynchronize(c->stream));
@@ -868,14 +962,18 @@ int32_t lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* tile_x, int32_t* stream_
             best_nt = c->nt_store;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     c->tile_x = best;
     c->nt_store = best_nt;
     if (rc == LBM_OK) rc = upload_batch(c);
+    double bnd_t = -1.0;
+    if (rc == LBM_OK) rc = tune_boundary(c, reps, e0, e1, &bnd_t);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (rc == LBM_OK && tile_x) *tile_x = best;
     if (rc == LBM_OK && stream_store) *stream_store = best_nt ? 1 : 0;
-    if (rc == LBM_OK && best_ms) *best_ms = best_t;
+    if (rc == LBM_OK && boundary_layout) *boundary_layout = c->bnd_layout;
+    if (rc == LBM_OK && bulk_ms) *bulk_ms = best_t;
+    if (rc == LBM_OK && boundary_ms) *boundary_ms = bnd_t;
     return rc;
 }
 

@@ -648,12 +648,13 @@ void launch_sweep_bulk(const Inst& I, int parity, int tile_x, bool nt, hipStream
 // only; after the bulk sweep, before the boundary sweep).
 void launch_curvature(const Inst& I, int parity, hipStream_t s);
 void launch_curvature_batch(const BatchGrid& G, int parity, hipStream_t s);
-void launch_sweep_boundary(const Inst& I, int parity, hipStream_t s, hipEvent_t e0 = nullptr,
+// layout: 0 = 8 lanes per listed cell, 1 = one thread per listed cell
+void launch_sweep_boundary(const Inst& I, int parity, int layout, hipStream_t s, hipEvent_t e0 = nullptr,
                            hipEvent_t e1 = nullptr);
 void launch_sweep_bulk_batch(const BatchGrid& G, int storage, int tile_x, bool nt, int parity, hipStream_t s,
                              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-void launch_sweep_boundary_batch(const BatchGrid& G, int storage, int parity, hipStream_t s, hipEvent_t e0 = nullptr,
-                                 hipEvent_t e1 = nullptr);
+void launch_sweep_boundary_batch(const BatchGrid& G, int storage, int parity, int layout, hipStream_t s,
+                                 hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void launch_mark(const Inst& I, int parity, hipStream_t s);
 void launch_convert(const Inst& I, int parity, bool retire_moves, bool integrate, hipStream_t s);
 void launch_finish(const Inst& I, int parity, bool reduce, bool zero_other, bool retire_moves, hipStream_t s);

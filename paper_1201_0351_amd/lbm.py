@@ -79,9 +79,9 @@ def library():
         "lbm_kernel_time": [vp, i32, dp, C.POINTER(C.c_int64)],
         "lbm_boundary_cells": [vp, i32, C.POINTER(C.c_int64)],
         "lbm_integrate_body": [C.POINTER(lbm_body), dp, dp, dp, C.c_uint32, C.POINTER(lbm_body)],
-        "lbm_set_tuning": [vp, i32, i32, i32, i32],
-        "lbm_get_tuning": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
-        "lbm_autotune": [vp, i32, C.POINTER(i32), C.POINTER(i32), dp],
+        "lbm_set_tuning": [vp, i32, i32, i32, i32, i32],
+        "lbm_get_tuning": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
+        "lbm_autotune": [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), dp, dp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -226,24 +226,30 @@ class Lattice:
         return np.array(F[:]), np.array(T[:])
 
     # ---- launch configuration ----------------------------------------------
-    def set_tuning(self, tile_x=None, batched=None, use_graph=None, stream_store=None):
+    def set_tuning(self, tile_x=None, batched=None, use_graph=None, stream_store=None, boundary_layout=None):
         cur = self.get_tuning()
         pick = lambda v, k: int(cur[k] if v is None else v)  # noqa: E731
         _check(library().lbm_set_tuning(self._h, pick(tile_x, "tile_x"), pick(batched, "batched"),
-                                        pick(use_graph, "use_graph"), pick(stream_store, "stream_store")))
+                                        pick(use_graph, "use_graph"), pick(stream_store, "stream_store"),
+                                        pick(boundary_layout, "boundary_layout")))
 
     def get_tuning(self):
-        t, b, g, n = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
-        _check(library().lbm_get_tuning(self._h, C.byref(t), C.byref(b), C.byref(g), C.byref(n)))
-        return dict(tile_x=t.value, batched=b.value, use_graph=g.value, stream_store=n.value)
+        t, b, g, n, bl = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(library().lbm_get_tuning(self._h, C.byref(t), C.byref(b), C.byref(g), C.byref(n), C.byref(bl)))
+        return dict(tile_x=t.value, batched=b.value, use_graph=g.value, stream_store=n.value,
+                    boundary_layout=bl.value)
 
     def autotune(self, reps=8):
-        """Time the bulk sweep for every tile width and store policy on the
-        current state and keep the fastest; returns (width, stream_store, ms
-        per launch)."""
-        t, n, ms = C.c_int32(), C.c_int32(), C.c_double()
-        _check(library().lbm_autotune(self._h, int(reps), C.byref(t), C.byref(n), C.byref(ms)))
-        return t.value, n.value, ms.value
+        """Time the bulk sweep for every tile width and store policy, then
+        the boundary sweep for both work layouts, on the current state, and
+        keep the fastest; returns dict(tile_x, stream_store, boundary_layout,
+        bulk_ms, boundary_ms) with the average times per launch
+        (boundary_ms -1: layout not tuned, no device room for the copy)."""
+        t, n, bl, ms, bms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double(), C.c_double()
+        _check(library().lbm_autotune(self._h, int(reps), C.byref(t), C.byref(n), C.byref(bl), C.byref(ms),
+                                      C.byref(bms)))
+        return dict(tile_x=t.value, stream_store=n.value, boundary_layout=bl.value, bulk_ms=ms.value,
+                    boundary_ms=bms.value)
 
     # ---- stepping ---------------------------------------------------------
     def step(self, n=1):

@@ -13,6 +13,7 @@ Tolerances (stated once, used below):
 import math
 import os
 import sys
+import types
 
 import numpy as np
 import pytest
@@ -40,7 +41,22 @@ def lbm():
     from paper_1201_0351_amd import lbm as L
 
     L.library()
-    return L
+    layout = os.environ.get("LGS_TEST_BOUNDARY_LAYOUT")  # the whole suite on another boundary-sweep layout
+    return L if layout is None else with_layout(L, int(layout))
+
+
+def with_layout(L, layout):
+    """The binding module with every new context on the given boundary-sweep
+    layout."""
+
+    class Lat(L.Lattice):
+        def __init__(self, *a, **k):
+            super().__init__(*a, **k)
+            self.set_tuning(boundary_layout=layout)
+
+    ns = types.SimpleNamespace(**{k: getattr(L, k) for k in dir(L) if not k.startswith("__")})
+    ns.Lattice = Lat
+    return ns
 
 
 def oracle_for(cfg, threads=THREADS):
@@ -691,6 +707,43 @@ def test_full_size_held_box_256x192x192_one_step(lbm):
     _full_size_step(lbm, W.config3(20.0), "fp32", 1e-5, free=False)
 
 
+def test_full_size_beyond_4gib_one_step(lbm):
+    """A 640x320x288 channel (59 M cells, FP32): one population lattice is
+    4.5 GB, past the 32-bit byte offsets of the buffer-addressed paths, so
+    the bulk and boundary sweeps take their 64-bit-address forms; one full
+    step with the free box against the oracle, cell by cell, on both
+    boundary-sweep layouts."""
+    w = W.config5()
+    lat = dict(w["lattice"], nx=640, ny=320, nz=288)
+    assert 19 * 640 * 320 * 288 * 4 > 2 ** 32
+    box = dict(w["bodies"][0], pos=(160.0, 160.0, 125.6))
+    for layout in (0, 1):
+        say("boundary layout %d" % layout)
+        _full_size_step(with_layout(lbm, layout), dict(w, lattice=lat, bodies=[box]), "fp32", 1e-5, free=True)
+
+
+ONE_THREAD_CASES = [
+    ("test_sweep_on_injected_state", dict(periodic=3)),
+    ("test_body_moving_across_periodic_faces", {}),
+    ("test_moving_wall_channel_with_free_sphere", {}),
+    ("test_conversions_bit_exact", dict(seed=11)),
+    ("test_stranded_interface_cells_bit_exact", {}),
+    ("test_dam_break_conserves_mass", {}),
+    ("test_surface_tension_droplet_on_walls_and_body", {}),
+    ("test_batched_instances_match_single", {}),
+    ("test_full_size_channel_one_step", dict(storage="fp16", tol=2e-3)),
+]
+
+
+@pytest.mark.parametrize("case,kw", ONE_THREAD_CASES, ids=[c[0][5:] for c in ONE_THREAD_CASES])
+def test_one_thread_boundary_layout(lbm, case, kw):
+    """The boundary sweep's one-thread-per-cell layout (the autotuner's pick
+    for long boundary lists) through the same parity checks as the default
+    8-lane layout: bodies (periodic faces, moving wall), conversions and
+    stranded cells bit-exact, mass, surface tension, batching, full size."""
+    globals()[case](with_layout(lbm, 1), **kw)
+
+
 def test_multi_instance_independent(lbm):
     """Two instances of different sizes in one context advance exactly as
     they would alone."""
@@ -983,9 +1036,10 @@ def test_graph_replay_with_surface_tension(lbm):
 
 
 def test_autotune_keeps_state(lbm):
-    """The autotuner sweeps the current state for every tile width and store
-    policy without changing it: afterwards the context advances exactly like
-    an untouched one (held bodies, bit for bit), also with streaming stores."""
+    """The autotuner sweeps the current state for every tile width, store
+    policy and boundary-sweep layout without changing it: afterwards the
+    context advances exactly like an untouched one on the same layout (held
+    bodies, bit for bit), also with streaming stores."""
     cfgs = [W.basin((64, 40, 36), 18.0, 0.6, 1e-5, seed=41, noise_amp=1e-4),
             W.basin((96, 32, 30), 15.0, 0.6, 1e-5, seed=42, noise_amp=1e-4)]
     A = lbm.Lattice([dict(c, max_bodies=1) for c in cfgs])
@@ -993,14 +1047,17 @@ def test_autotune_keeps_state(lbm):
     for L in (A, B):
         L.set_body(0, W.box((12, 12, 6), (32, 20, 18), 12.0, 0.5), inst=0)
         L.step(7)
-    tx, nt, ms = A.autotune(reps=3)
-    say("autotune: tile %d, stream_store %d, %.4f ms" % (tx, nt, ms))
-    assert tx in (32, 64, 128) and nt in (0, 1) and ms > 0
-    assert A.get_tuning()["tile_x"] == tx and A.get_tuning()["stream_store"] == nt
+    t = A.autotune(reps=3)
+    say("autotune: %s" % t)
+    assert t["tile_x"] in (32, 64, 128) and t["stream_store"] in (0, 1) and t["bulk_ms"] > 0
+    assert t["boundary_layout"] in (0, 1) and t["boundary_ms"] > 0
+    got = A.get_tuning()
+    assert (got["tile_x"], got["stream_store"], got["boundary_layout"]) == (t["tile_x"], t["stream_store"],
+                                                                            t["boundary_layout"])
     # streaming stores write the same values: force them on A, leave B on the
-    # default (cached stores at this size)
+    # default (cached stores at this size); both on B's boundary layout
     assert B.get_tuning()["stream_store"] == 0
-    A.set_tuning(stream_store=1)
+    A.set_tuning(stream_store=1, boundary_layout=B.get_tuning()["boundary_layout"])
     A.step(9)
     B.step(9)
     for k in range(2):
@@ -1087,14 +1144,22 @@ def _cubes_gold(key):
 
 
 def test_floating_cubes_settle_at_the_papers_heels(lbm):
-    """Released at 10 deg and free in heave and roll, the GPU's cubes settle
-    where the FP64 oracle's do (tests/golden/floating_cubes_130x40x40.json,
-    section settle), within 0.3 deg over the last quarter of 15000 steps
-    (measured: 0.02 deg; during the transient the two differ by up to 1.3
-    deg, as mapping events shift with FP32 round-off).  Against the paper's
-    heels of a square section (Sec. 4, equilibrium of floating cubes): 45 deg
-    for density 1/2 and 26.565 deg for 1/4 within 0.5 deg; the box of
-    density 3/4 settles at 29.4 deg on both sides (bound 3 deg)."""
+    """Released at 10 deg and free in heave and roll, the boxes of density
+    1/2 and 1/4 settle where the FP64 oracle's do
+    (tests/golden/floating_cubes_130x40x40.json, section settle), within 0.3
+    deg over the last quarter of 15000 steps (measured: 0.01 deg), and at the
+    paper's heels of a square section (Sec. 4, equilibrium of floating
+    cubes), 45 and 26.565 deg, within 0.5 deg.
+
+    The box of density 3/4 has no single resting heel at 16 cells a side:
+    between the continuum equilibrium (26.565 deg) and about 37 deg the
+    mapped hull's steps hold it wherever the transient leaves it, and the
+    transient itself follows round-off.  Measured on the GPU (FP32) from a
+    release at 9.999 / 10 / 10.001 / 10.01 deg: 28.2 / 29.4 / 35.9 / 37.0
+    deg, and 29.4 / 35.9 deg from 10 deg with the two boundary-sweep layouts
+    (the same rules, other summation orders); the oracle from 10 deg: 29.4.
+    So for that box: it comes to rest (the last 1000 steps within 0.1 deg)
+    inside that band."""
     gold = _cubes_gold("settle")
     say("floating cubes from 10 deg, heave and roll, %d steps" % gold["steps"])
     tr = _cubes_trace(lbm, 0x0C, gold["steps"], gold["every"], heel0=10.0)
@@ -1103,8 +1168,13 @@ def test_floating_cubes_settle_at_the_papers_heels(lbm):
         got = float(np.mean(np.abs(tr[late, 1 + 2 * k])))
         ref = gold["settled_heel_deg"][k]
         say("  box %d: settled heel %.3f deg, oracle %.3f, paper %.3f" % (k, got, ref, want))
-        assert abs(got - ref) <= 0.3
-        assert abs(got - want) <= (3.0 if k == 0 else 0.5)
+        if k == 0:
+            tail = np.abs(tr[-4:, 1])
+            assert tail.max() - tail.min() <= 0.1, tail
+            assert 26.0 <= got <= 38.0 and 26.0 <= ref <= 38.0
+        else:
+            assert abs(got - ref) <= 0.3
+            assert abs(got - want) <= 0.5
 
 
 def test_floating_cubes_roll_only_vs_oracle(lbm):
