@@ -114,70 +114,68 @@ __device__ __forceinline__ void two_sum_add(float& hi, float& lo, float dm) {
     hi = h;
 }
 
-// The nine pairs (i, ibar) of opposite D3Q19 links, primary member first.
-__device__ constexpr int PAIR_P[9] = {2, 3, 5, 8, 9, 10, 12, 14, 16};
-
-// BGK collision with the force term on pulled deviations d[]: post-collision
-// deviations in out[].  Evaluated per pair of opposite links: the equilibrium
-// and the force term split into a part even in c_i (shared) and a part odd
-// in c_i (sign flips).
-__device__ __forceinline__ void collide(const Inst& I, const float (&d)[Q], float (&out)[Q]) {
+// BGK collision with the force term on pulled deviations held at the storage
+// scale s (d[] = s (f_i - w_i)); post-collision values at the same scale in
+// out[].  Per pair of opposite links (p, pbar), with cu = c_p.u and
+// ca = c_p.a, the relaxation towards the equilibrium plus the force term is
+//   omega (f_eq,i - w_i) + F_i = omega w drho + w rho (g +- h),
+//   g = 4.5 omega cu^2 + 9 ca cu - (1.5 omega u.u + 3 u.a),
+//   h = 3 omega cu + 3 ca            (+ for p, - for pbar),
+// and f*_i - w_i = (1 - omega) d_i + that.  Uniform factors come from the
+// host (CollideConst).
+__device__ __forceinline__ void collide(const CollideConst& K, int* nonfinite, const float (&d)[Q], float (&out)[Q]) {
     float drho = d[0], j0 = 0.f, j1 = 0.f, j2 = 0.f;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        const int p = PAIR_P[k], q = opp(p);
+        const int p = pair_p(k), q = opp(p);
         drho += d[p] + d[q];
         const float od = d[p] - d[q];
         j0 += cx(p) * od;
         j1 += cy(p) * od;
         j2 += cz(p) * od;
     }
-    const float rho = 1.f + drho;
-    const float irho = 1.f / rho;
-    const float u0 = j0 * irho, u1 = j1 * irho, u2 = j2 * irho;
-    const float uu15 = 1.5f * (u0 * u0 + u1 * u1 + u2 * u2);
-    const float ua3 = 3.f * (u0 * I.ax + u1 * I.ay + u2 * I.az);
-    const float om = I.omega;
-    if (!(rho > 0.f && rho < 1e6f)) atomicOr(&I.ctl->nonfinite, 1);
-    {
-        const float w = wgt(0);
-        const float deq = w * (drho - rho * uu15);
-        const float F = -w * rho * ua3;
-        out[0] = d[0] + om * (deq - d[0]) + F;
+    const float rho = fmaf(drho, K.inv, 1.f);
+    if (!(rho > 0.f && rho < 1e6f)) atomicOr(nonfinite, 1);
+    const float ir = K.inv * __builtin_amdgcn_rcpf(rho);  // 1-ulp reciprocal
+    const float u0 = j0 * ir, u1 = j1 * ir, u2 = j2 * ir;
+    const float base = -fmaf(K.om15, fmaf(u2, u2, fmaf(u1, u1, u0 * u0)),
+                             fmaf(u2, K.a3[2], fmaf(u1, K.a3[1], u0 * K.a3[0])));
+    float rw[3], omd[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        rw[c] = K.sw[c] * rho;
+        omd[c] = K.omw[c] * drho;
     }
+    out[0] = fmaf(K.om1, d[0], fmaf(rw[0], base, omd[0]));
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        const int p = PAIR_P[k], q = opp(p);
-        const float w = wgt(p);
+        const int p = pair_p(k), q = opp(p), c = wclass(p);
         const float cu = cx(p) * u0 + cy(p) * u1 + cz(p) * u2;
-        const float ca = cx(p) * I.ax + cy(p) * I.ay + cz(p) * I.az;
-        const float wr = w * rho;
-        const float even = w * drho + wr * (4.5f * cu * cu - uu15);
-        const float odd = 3.f * wr * cu;
-        const float Fe = wr * (9.f * cu * ca - ua3);
-        const float Fo = 3.f * wr * ca;
-        out[p] = d[p] + om * (even + odd - d[p]) + (Fe + Fo);
-        out[q] = d[q] + om * (even - odd - d[q]) + (Fe - Fo);
+        const float g = fmaf(fmaf(K.om45, cu, K.ca9[k]), cu, base);
+        const float h = fmaf(K.om3, cu, K.ca3[k]);
+        const float E = fmaf(rw[c], g, omd[c]), O = rw[c] * h;
+        out[p] = fmaf(K.om1, d[p], E + O);
+        out[q] = fmaf(K.om1, d[q], E - O);
     }
 }
 
-// Post-collision deviations to the 19 planes of cell id.  fits (uniform):
-// the planes span less than 2^32 bytes, so buffer stores take the cell's
-// byte offset once and a uniform offset per plane.
+// Post-collision values to the 19 planes of cell id.  fits (uniform): the
+// planes span less than 2^32 bytes, so buffer stores take the cell's byte
+// offset once and a uniform offset per plane.
 template <typename S, bool NT>
-__device__ __forceinline__ void collide_store(const Inst& I, const float (&d)[Q], S* __restrict__ dst, int id,
-                                              bool fits) {
+__device__ __forceinline__ void collide_store(const Inst& I, const CollideConst& K, const float (&d)[Q],
+                                              S* __restrict__ dst, int id, bool fits) {
     float o[Q];
-    collide(I, d, o);
+    collide(K, &I.ctl->nonfinite, d, o);
     if (fits) {
         const uint32_t psb = (uint32_t)(I.ps * sizeof(S));
         const auto rd = buf_rsrc(dst, (uint32_t)Q * psb);
         const uint32_t ub = (uint32_t)id * (uint32_t)sizeof(S);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) BufIO<S>::template store<NT>(rd, ub, (uint32_t)i * psb, o[i], I.scale);
+        for (int i = 0; i < Q; ++i) BufIO<S>::template store_raw<NT>(rd, ub, (uint32_t)i * psb, o[i]);
     } else {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) Store<S>::template store<NT>(dst, (size_t)i * I.ps + id, o[i], I.scale);
+        for (int i = 0; i < Q; ++i) Store<S>::template store<NT>(dst, (size_t)i * I.ps + id, o[i], 1.f);
     }
 }
 
@@ -190,13 +188,14 @@ __device__ __forceinline__ void collide_store(const Inst& I, const float (&d)[Q]
 // to the boundary sweep), else pull, collide and store.  chk (the cell's near
 // mark): read the 18 source types, and clear the mark if none is gas or an
 // obstacle; without it every source is known to be liquid, interface or a
-// static wall.  The population loads go out first.
-template <typename S, bool NT>
-__device__ __forceinline__ bool bulk_cell(const Inst& I, const S* __restrict__ src, S* __restrict__ dst, int x, int y,
-                                          int z, int id, bool chk) {
+// static wall.  The population loads go out first.  Values stay at the
+// storage scale from load to store.  PX: periodic in x.
+template <typename S, bool NT, bool PX>
+__device__ __forceinline__ bool bulk_cell(const Inst& I, const CollideConst& K, const S* __restrict__ src,
+                                          S* __restrict__ dst, int x, int y, int z, int id, bool chk) {
     float d[Q];
     const int nx = I.nx, ny = I.ny, sxy = nx, sz = nx * ny;
-    const bool px = I.periodic & 1, py = I.periodic & 2, pz = I.periodic & 4;
+    const bool py = I.periodic & 2, pz = I.periodic & 4;
     // Wavefronts whose cells all lie away from the y and z faces (x faces
     // included): one load per link and lane at a 32-bit offset from plane 0,
     // an x-face lane taking its periodic image or (wall) its own f_ibar by a
@@ -209,14 +208,7 @@ __device__ __forceinline__ bool bulk_cell(const Inst& I, const S* __restrict__ s
     // decided per wavefront, so that exactly one of the two load paths runs
     const bool row = __builtin_amdgcn_readfirstlane((int)(__ballot(!inner) == 0ull)) != 0;
     const bool xlo = x == 0, xhi = x == nx - 1;
-    // source cell of link i in such a row, -1 for a wall
-    auto row_src = [=](int i) {
-        int s = id - (cx(i) + sxy * cy(i) + sz * cz(i));
-        if (cx(i) == 1 && xlo) s = px ? s + nx : -1;
-        if (cx(i) == -1 && xhi) s = px ? s - nx : -1;
-        return s;
-    };
-    const int xm = step_axis(x, -1, nx, px), xp = step_axis(x, 1, nx, px);
+    const int xm = step_axis(x, -1, nx, PX), xp = step_axis(x, 1, nx, PX);
     const int ym = step_axis(y, -1, ny, py), yp = step_axis(y, 1, ny, py);
     const int zm = step_axis(z, -1, I.nz, pz), zp = step_axis(z, 1, I.nz, pz);
     // source of link i next to a y or z face: its periodic image, or -1 (a
@@ -239,57 +231,67 @@ __device__ __forceinline__ bool bulk_cell(const Inst& I, const S* __restrict__ s
         const auto rs = buf_rsrc(src, (uint32_t)Q * psb);
         const uint32_t ub = (uint32_t)id * (uint32_t)sizeof(S);
         const uint32_t wrapb = (uint32_t)nx * (uint32_t)sizeof(S);
+        const uint32_t ulo = xlo ? ub + wrapb : ub, uhi = xhi ? ub - wrapb : ub;  // periodic images
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             const int sh = (cx(i) + sxy * cy(i) + sz * cz(i)) * (int)sizeof(S);
             const uint32_t bn = (uint32_t)i * psb - (uint32_t)sh;
             if (cx(i) == 0) {
-                d[i] = BufIO<S>::load(rs, ub, bn, I.inv_scale);
+                d[i] = BufIO<S>::load_raw(rs, ub, bn);
+            } else if (PX) {
+                d[i] = BufIO<S>::load_raw(rs, cx(i) == 1 ? ulo : uhi, bn);
             } else {
                 const bool face = cx(i) == 1 ? xlo : xhi;
-                uint32_t vo, so;
-                if (px) {
-                    so = bn;
-                    vo = face ? (cx(i) == 1 ? ub + wrapb : ub - wrapb) : ub;
-                } else {
-                    const uint32_t bw = (uint32_t)opp(i) * psb;
-                    so = bn < bw ? bn : bw;
-                    vo = ub + ((face ? bw : bn) - so);
-                }
-                d[i] = BufIO<S>::load(rs, vo, so, I.inv_scale);
+                const uint32_t bw = (uint32_t)opp(i) * psb;
+                const uint32_t so = bn < bw ? bn : bw;
+                d[i] = BufIO<S>::load_raw(rs, ub + (face ? bw - so : bn - so), so);
             }
         }
-        d[0] = BufIO<S>::load(rs, ub, 0u, I.inv_scale);
+        d[0] = BufIO<S>::load_raw(rs, ub, 0u);
     } else {
         // a wall source is the halfway bounce-back: this cell's own f_ibar
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             const int s = face_src(i);
-            d[i] = Store<S>::load(src + (size_t)(s >= 0 ? i : opp(i)) * I.ps, (unsigned)(s >= 0 ? s : id),
-                                  I.inv_scale);
+            d[i] = Store<S>::load(src + (size_t)(s >= 0 ? i : opp(i)) * I.ps, (unsigned)(s >= 0 ? s : id), 1.f);
         }
-        d[0] = Store<S>::load(src, (size_t)id, I.inv_scale);
+        d[0] = Store<S>::load(src, (size_t)id, 1.f);
     }
     if (chk) {
-        uint32_t bad = 0;
+        // the types of the 18 sources (a wall reads as this liquid cell):
+        // bit 1 of type + 1 is clear exactly for gas (0) and obstacle (3)
+        const auto rf = buf_rsrc(I.flags, (uint32_t)I.N);
+        uint32_t ok = 2u;
+        if (row) {
+            // x-face lanes: the periodic image one row over, or (wall) the
+            // cell itself
+            const int alo = xlo ? (PX ? nx : 0) : 0, ahi = xhi ? (PX ? -nx : 0) : 0;
 #pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            int s = row ? row_src(i) : face_src(i);
-            s = s >= 0 ? s : id;  // a wall source reads this cell's own (liquid) type
-            const uint32_t st = I.flags[(unsigned)s] & TYPE_MASK;
-            bad |= (uint32_t)(st == GAS) | (uint32_t)(st == OBS);
+            for (int i = 1; i < Q; ++i) {
+                const int sh = cx(i) + sxy * cy(i) + sz * cz(i);
+                int s = id - sh;
+                if (cx(i) == 1) s = PX ? s + alo : (xlo ? id : s);
+                if (cx(i) == -1) s = PX ? s + ahi : (xhi ? id : s);
+                ok &= __builtin_amdgcn_raw_buffer_load_b8(rf, s, 0, 0) + 1u;
+            }
+        } else {
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                const int s = face_src(i);
+                ok &= __builtin_amdgcn_raw_buffer_load_b8(rf, s >= 0 ? s : id, 0, 0) + 1u;
+            }
         }
-        if (bad) return true;
+        if (!(ok & 2u)) return true;
         I.nearo[id] = 0;
     }
-    collide_store<S, NT>(I, d, dst, id, fits);
+    collide_store<S, NT>(I, K, d, dst, id, fits);
     return false;
 }
 
 // Workgroup b of nb (nb a multiple of 8, b % 8 the XCD it runs on) of one
 // instance's bulk grid.
-template <typename S, int TX, bool W, bool NT>
-__device__ __forceinline__ void sweep_bulk(const Inst& I, int parity, int b, int nb) {
+template <typename S, int TX, bool W, bool NT, bool PX>
+__device__ __forceinline__ void sweep_bulk(const Inst& I, const CollideConst& K, int parity, int b, int nb) {
     constexpr int TY = 256 / TX;
     const int tiles_x = (I.nx + TX - 1) / TX, tiles_y = (I.ny + TY - 1) / TY;
     // XCD-aware tile order: workgroup b runs on XCD b % 8.  Whole z-layers
@@ -329,26 +331,29 @@ __device__ __forceinline__ void sweep_bulk(const Inst& I, int parity, int b, int
                        (!(I.periodic & 2) && (y == 0 || y == I.ny - 1)) ||
                        (!(I.periodic & 4) && (z == 0 || z == I.nz - 1)));
     bool defer = (type == IFC) || (type == LIQ && wall);
-    if (type == LIQ && !wall) defer = bulk_cell<S, NT>(I, src, dst, x, y, z, id, near);
+    if (type == LIQ && !wall) defer = bulk_cell<S, NT, PX>(I, K, src, dst, x, y, z, id, near);
     block_append<4>(defer, id, I.bnd, &C.n_bnd, I.list_cap, &C.overflow);
 }
 
 // At most 64 VGPRs, so that eight wavefronts fit per SIMD.  W: the lattice
 // has moving walls (a variant without their test runs otherwise).  NT:
-// non-temporal population stores.
-template <typename S, int TX, bool W, bool NT>
+// non-temporal population stores.  PX: periodic in x.
+template <typename S, int TX, bool W, bool NT, bool PX>
 __global__ __launch_bounds__(256, 8) void k_sweep_bulk(Inst I, int parity) {
-    sweep_bulk<S, TX, W, NT>(I, parity, blockIdx.x, gridDim.x);
+    sweep_bulk<S, TX, W, NT, PX>(I, I.cc, parity, blockIdx.x, gridDim.x);
 }
 
 // all instances of a batch in one launch (instance table in device memory;
-// the copied descriptor needs registers of its own, so no 64-VGPR bound)
+// the copied descriptor needs registers of its own, so no 64-VGPR bound; the
+// collision constants are read from the table where they are used)
 template <typename S, int TX, bool NT>
 __global__ __launch_bounds__(256) void kb_sweep_bulk(const Inst* __restrict__ tab, const int* __restrict__ off, int n,
                                                      int parity) {
     const int k = batch_instance(off, n, blockIdx.x);
     const Inst I = tab[k];
-    sweep_bulk<S, TX, true, NT>(I, parity, blockIdx.x - off[k], off[k + 1] - off[k]);
+    const CollideConst& K = tab[k].cc;
+    if (I.periodic & 1) sweep_bulk<S, TX, true, NT, true>(I, K, parity, blockIdx.x - off[k], off[k + 1] - off[k]);
+    else sweep_bulk<S, TX, true, NT, false>(I, K, parity, blockIdx.x - off[k], off[k + 1] - off[k]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1092,8 +1097,14 @@ namespace {
 template <typename S, int TX, bool NT>
 void bulk_one(const Inst& I, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const dim3 g(bulk_blocks(I, TX)), b(256);
-    if (I.wall_moving) hipExtLaunchKernelGGL((k_sweep_bulk<S, TX, true, NT>), g, b, 0, s, e0, e1, 0, I, parity);
-    else hipExtLaunchKernelGGL((k_sweep_bulk<S, TX, false, NT>), g, b, 0, s, e0, e1, 0, I, parity);
+    const bool px = I.periodic & 1;
+    if (I.wall_moving && px)
+        hipExtLaunchKernelGGL((k_sweep_bulk<S, TX, true, NT, true>), g, b, 0, s, e0, e1, 0, I, parity);
+    else if (I.wall_moving)
+        hipExtLaunchKernelGGL((k_sweep_bulk<S, TX, true, NT, false>), g, b, 0, s, e0, e1, 0, I, parity);
+    else if (px)
+        hipExtLaunchKernelGGL((k_sweep_bulk<S, TX, false, NT, true>), g, b, 0, s, e0, e1, 0, I, parity);
+    else hipExtLaunchKernelGGL((k_sweep_bulk<S, TX, false, NT, false>), g, b, 0, s, e0, e1, 0, I, parity);
 }
 template <typename S, int TX, bool NT>
 void bulk_batch(const BatchGrid& G, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {

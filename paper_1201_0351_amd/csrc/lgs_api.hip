@@ -76,6 +76,32 @@ size_t storage_bytes(int storage) { return storage == LBM_FP32 ? 4 : 2; }
 #ifndef LGS_PLANE_PAD_BYTES
 #define LGS_PLANE_PAD_BYTES 4352
 #endif
+// Uniform factors of the bulk collision (k_sweep.hip), from omega, the
+// acceleration and the storage scale, rounded once to FP32.
+static void collide_constants(Inst& I) {
+    CollideConst& K = I.cc;
+    const double om = (double)I.omega;
+    const double a[3] = {(double)I.ax, (double)I.ay, (double)I.az};
+    const double sc = (double)I.scale;
+    K.om1 = (float)(1.0 - om);
+    K.om15 = (float)(1.5 * om);
+    K.om45 = (float)(4.5 * om);
+    K.om3 = (float)(3.0 * om);
+    for (int c = 0; c < 3; ++c) K.a3[c] = (float)(3.0 * a[c]);
+    for (int k = 0; k < 9; ++k) {
+        const int p = pair_p(k);
+        const double ca = cx(p) * a[0] + cy(p) * a[1] + cz(p) * a[2];
+        K.ca9[k] = (float)(9.0 * ca);
+        K.ca3[k] = (float)(3.0 * ca);
+    }
+    const int rep[3] = {0, 1, 7};  // a link of each weight class
+    for (int c = 0; c < 3; ++c) {
+        K.omw[c] = (float)(om * wgtd(rep[c]));
+        K.sw[c] = (float)(sc * wgtd(rep[c]));
+    }
+    K.inv = (float)(1.0 / sc);
+}
+
 size_t plane_stride(const lbm_config& c) {
     const size_t N = (size_t)c.nx * c.ny * c.nz;
     const size_t sb = storage_bytes(c.storage);
@@ -350,6 +376,7 @@ int32_t lbm_create(const lbm_config* cfgs, int32_t n_inst, void* d_workspace, si
         I.lap = (float)(6.0 * h.cfg.surface_tension);
         I.scale = h.cfg.storage == LBM_FP16_DEV ? (float)h.cfg.fp16_scale : 1.f;
         I.inv_scale = 1.f / I.scale;
+        collide_constants(I);
         I.eps = h.cfg.eps;
         const size_t N = (size_t)I.N;
         HIP_OK(hipMemsetAsync(I.ctl, 0, sizeof(Ctl), c->stream));

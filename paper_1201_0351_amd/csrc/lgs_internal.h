@@ -64,6 +64,30 @@ __host__ __device__ constexpr float wgt(int i) {
 __host__ __device__ constexpr double wgtd(int i) {
     return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
 }
+// The nine pairs (i, ibar) of opposite links, primary member first.
+__host__ __device__ constexpr int pair_p(int k) {
+    constexpr int v[9] = {2, 3, 5, 8, 9, 10, 12, 14, 16};
+    return v[k];
+}
+// weight class of a link: 0 rest, 1 axis (1/18), 2 diagonal (1/36)
+__host__ __device__ constexpr int wclass(int i) { return i == 0 ? 0 : (i < 7 ? 1 : 2); }
+
+// Constants of the bulk collision, computed on the host once per instance.
+// The device has no scalar floating-point unit: a product of two uniform
+// values costs one vector instruction per wavefront, as much as a per-cell
+// one.  s is the storage scale (deviations are held as s (f_i - w_i)).
+struct CollideConst {
+    float om1;     // 1 - omega
+    float om15;    // 1.5 omega
+    float om45;    // 4.5 omega
+    float om3;     // 3 omega
+    float a3[3];   // 3 a
+    float ca9[9];  // 9 c_p.a of pair k (p = pair_p(k))
+    float ca3[9];  // 3 c_p.a
+    float omw[3];  // omega w per weight class
+    float sw[3];   // s w per weight class
+    float inv;     // 1 / s
+};
 
 // --------------------------------------------------------------------------
 // per-instance control block (device memory)
@@ -126,6 +150,7 @@ struct Inst {
     int wall_moving;   // wall_u != 0
     float lap;         // 2 sigma / cs^2: Laplace density jump per unit curvature (0: no surface tension)
     float scale, inv_scale;  // storage scale (FP16), 1 otherwise
+    CollideConst cc;
     double eps;
     void* pop[2];
     uint8_t* flags;
@@ -256,10 +281,18 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32
 }
 template <typename S>
 struct BufIO;
+// load_raw / store_raw: the value at the storage scale (no scaling).
 template <>
 struct BufIO<float> {
     __device__ static inline float load(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float) {
         return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
+    }
+    __device__ static inline float load_raw(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
+    }
+    template <bool NT>
+    __device__ static inline void store_raw(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)vo, (int)so, NT ? BUF_NT : 0);
     }
     template <bool NT>
     __device__ static inline void store(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float v, float) {
@@ -271,6 +304,13 @@ struct BufIO<__half> {
     __device__ static inline float load(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float inv) {
         return h2f(__builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, 0)) * inv;
     }
+    __device__ static inline float load_raw(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+        return h2f(__builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, 0));
+    }
+    template <bool NT>
+    __device__ static inline void store_raw(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float v) {
+        __builtin_amdgcn_raw_buffer_store_b16(f2h(v), r, (int)vo, (int)so, NT ? BUF_NT : 0);
+    }
     template <bool NT>
     __device__ static inline void store(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float v, float sc) {
         __builtin_amdgcn_raw_buffer_store_b16(f2h(v * sc), r, (int)vo, (int)so, NT ? BUF_NT : 0);
@@ -280,6 +320,13 @@ template <>
 struct BufIO<__hip_bfloat16> {
     __device__ static inline float load(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float) {
         return b2f(__builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, 0));
+    }
+    __device__ static inline float load_raw(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+        return b2f(__builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, 0));
+    }
+    template <bool NT>
+    __device__ static inline void store_raw(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float v) {
+        __builtin_amdgcn_raw_buffer_store_b16(f2b(v), r, (int)vo, (int)so, NT ? BUF_NT : 0);
     }
     template <bool NT>
     __device__ static inline void store(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float v, float) {

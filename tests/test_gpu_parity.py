@@ -1181,8 +1181,10 @@ def test_floating_cubes_roll_only_vs_oracle(lbm):
     """Roll only (centres held at the upright draft) from 15 deg: the GPU
     follows the oracle's 3000-step trajectory (section roll_only).  The roll
     is a lightly damped oscillation, so FP32 round-off accumulates as a phase
-    shift: every 250 steps the heels agree within 2 deg (measured: 1.6 deg at
-    step 3000, 0.4 deg up to step 1500)."""
+    shift: every 250 steps the heels agree within 2 deg, and within 1.2 deg
+    up to step 1500.  Measured over four FP32 round-off realisations (two
+    groupings of the bulk collision, two boundary-sweep layouts): 0.84 to
+    1.63 deg over the run, 0.37 to 0.97 deg up to step 1500."""
     gold = _cubes_gold("roll_only")
     ref = np.array(gold["trace"])
     say("floating cubes from 15 deg, roll only, %d steps" % gold["steps"])
@@ -1190,7 +1192,7 @@ def test_floating_cubes_roll_only_vs_oracle(lbm):
     assert got.shape == ref.shape and np.array_equal(got[:, 0], ref[:, 0])
     dh = np.abs(got[:, 1::2] - ref[:, 1::2])
     say("  max |d heel| %.3f deg (to step 1500: %.3f)" % (dh.max(), dh[got[:, 0] <= 1500].max()))
-    assert dh.max() <= 2.0 and dh[got[:, 0] <= 1500].max() <= 0.6
+    assert dh.max() <= 2.0 and dh[got[:, 0] <= 1500].max() <= 1.2
     assert np.array_equal(got[:, 2::2], ref[:, 2::2])  # the held centres
 
 
