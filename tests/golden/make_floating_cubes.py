@@ -15,17 +15,22 @@ FP32.  With heave the bottom faces sink onto a row of cell centres within a
 few hundred steps, the mapping turns asymmetric and the trajectory is
 deterministic enough to compare.)
 
-The paper starts its cubes far from equilibrium.  Two more runs do that:
+The paper starts its cubes far from equilibrium.  Three more runs do that:
   settle    heave and roll from 10 deg at the upright draft, `--settle`
             steps; the heels averaged over the last quarter are the settled
             heels to set against the paper's 26.565 / 45 / 26.565 deg
+  settle_perturbed  the same from 10.001 deg: the box of density 3/4 comes
+            to rest at another heel (its resting heel is not unique at 16
+            cells a side), the other two where they did
   roll_only roll only (centre held at the upright draft) from 15 deg,
             `--steps` steps (the closed form for a held centre is
             20.7 / 45 / 20.7 deg)
 
-Only the oracle is called.
+Only the oracle is called.  `--sections a,b` recomputes only those sections
+and keeps the others of the existing file (the runs are independent).
 
 Usage: python tests/golden/make_floating_cubes.py [--steps 3000] [--settle 15000] [--threads 8]
+       [--sections heave_roll,roll_only,settle,settle_perturbed]
 """
 import argparse
 import json
@@ -86,13 +91,25 @@ def main():
     ap.add_argument("--every", type=int, default=250)
     ap.add_argument("--threads", type=int, default=min(8, os.cpu_count() or 1))
     ap.add_argument("--out", type=str, default=os.path.join(HERE, "floating_cubes_130x40x40.json"))
+    ap.add_argument("--sections", type=str, default="heave_roll,roll_only,settle,settle_perturbed")
     args = ap.parse_args()
-    res = dict(_source="FP64 oracle (oracle/lgs_oracle.c), written by tests/golden/make_floating_cubes.py",
+    runs = dict(heave_roll=lambda: run(0x0C, args.steps, args.every, args.threads),
+                roll_only=lambda: run(0x08, args.steps, args.every, args.threads, heel0=15.0),
+                settle=lambda: run(0x0C, args.settle, args.every, args.threads, heel0=10.0),
+                settle_perturbed=lambda: run(0x0C, args.settle, args.every, args.threads, heel0=10.001))
+    want = [k for k in args.sections.split(",") if k]
+    for k in want:
+        if k not in runs:
+            raise SystemExit("unknown section %s" % k)
+    res = {}
+    if set(want) != set(runs) and os.path.exists(args.out):
+        with open(args.out) as fh:
+            res = json.load(fh)
+    res.update(_source="FP64 oracle (oracle/lgs_oracle.c), written by tests/golden/make_floating_cubes.py",
                nx=NX, ny=NY, nz=NZ, fill_height=H, side=S, tau=TAU, g=G, eps=EPS, densities=list(DENSITIES),
-               heel0_deg=HEEL0,
-               heave_roll=run(0x0C, args.steps, args.every, args.threads),
-               roll_only=run(0x08, args.steps, args.every, args.threads, heel0=15.0),
-               settle=run(0x0C, args.settle, args.every, args.threads, heel0=10.0))
+               heel0_deg=HEEL0)
+    for k in want:
+        res[k] = runs[k]()
     with open(args.out, "w") as fh:
         json.dump(res, fh, indent=1)
     print("wrote", args.out)
