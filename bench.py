@@ -284,14 +284,31 @@ def run_batch(storage, steps, warmup, batched=True, graph=False):
     tuned = L.autotune(4)
     dt = _timed(L, steps, warmup)
     cells = sum(L.ncells(k) for k in range(len(insts)))
+    res = dict(instances=len(insts), cells=cells, steps=steps, ms_per_step=round(1e3 * dt / steps, 4),
+               aggregate_mlups=round(cells * steps / dt / 1e6, 1),
+               instance_steps_per_s=round(len(insts) * steps / dt, 1),
+               instances_per_s=round(len(insts) / (w["steps"] * dt / steps), 3),
+               note="instances_per_s: the %d-step heel sweep of all instances per second" % w["steps"],
+               batched=batched, graph=graph, autotuned={k: tuned[k] for k in ("tile_x", "stream_store",
+                                                                               "boundary_layout")})
+    if batched and not graph:
+        # the two sweeps' event-timed launches against the bytes of all instances
+        L.enable_kernel_timing(True)
+        n = max(10, min(steps, 100))
+        L.step(n)
+        _sync(L)
+        bulk_ms, launches = L.kernel_time(0)
+        bnd_ms, _ = L.kernel_time(1)
+        L.enable_kernel_timing(False)
+        alg = dict(bulk=0, boundary=0)
+        for k in range(len(insts)):
+            a, _ = algorithmic_bytes(L.types(k), STORAGE_BYTES[storage], L.boundary_cells(k))
+            alg["bulk"] += a["bulk"]
+            alg["boundary"] += a["boundary"]
+        res["kernels"] = kernel_rooflines(dict(alg_bytes=alg, bulk_ms=bulk_ms / launches,
+                                               boundary_ms=bnd_ms / launches), storage)
     L.close()
-    return dict(instances=len(insts), cells=cells, steps=steps, ms_per_step=round(1e3 * dt / steps, 4),
-                aggregate_mlups=round(cells * steps / dt / 1e6, 1),
-                instance_steps_per_s=round(len(insts) * steps / dt, 1),
-                instances_per_s=round(len(insts) / (w["steps"] * dt / steps), 3),
-                note="instances_per_s: the %d-step heel sweep of all instances per second" % w["steps"],
-                batched=batched, graph=graph, autotuned={k: tuned[k] for k in ("tile_x", "stream_store",
-                                                                                "boundary_layout")})
+    return res
 
 
 def other_configs(steps, warmup):
@@ -527,7 +544,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="only the headline and its FP16 / BF16 / host-update runs")
     ap.add_argument("--profile", choices=["channel-fp32", "channel-fp16", "channel-bf16", "basin128-fp32",
-                                          "basin256-fp32", "basin256-fp16"],
+                                          "basin256-fp32", "basin256-fp16", "batch48-fp32", "batch48-fp16"],
                     help="only run this timed case (for the profiler) and print its summary")
     ap.add_argument("--free-advection", action="store_true",
                     help="only run the paper's free advection sweep (Table tab:velocities) and print it as JSON")
@@ -551,6 +568,10 @@ def main():
         sys.exit(2)
     from paper_1201_0351_amd import workloads as W
 
+    if args.profile and args.profile.startswith("batch48"):
+        st = args.profile.split("-")[1]
+        print(json.dumps(dict(case=args.profile, **run_batch(st, args.steps, args.warmup))))
+        return
     if args.profile:
         name, st = args.profile.split("-")
         wl = {"channel": (W.config5(), True, PREP_STEPS), "basin128": (W.config2(20.0, released=True), True, 0),

@@ -157,7 +157,7 @@ __device__ __forceinline__ void reduce_forces(const Inst& I, int parity, double 
     constexpr int PER = BND_BLOCKS_MAX / CT;
     static_assert(PER * CT == BND_BLOCKS_MAX, "force records per thread");
     __shared__ double part[CW][MAXB][6];
-    const int nrec = boundary_blocks(I);
+    const int nrec = min(boundary_blocks(I), I.ctl->cnt[parity].n_frec);
     int rb[PER];
     double rv[PER][6];
 #pragma unroll

@@ -376,6 +376,17 @@ __device__ __forceinline__ float osum(float v) {
 }
 }  // namespace
 
+// Workgroup wg of nwg takes list entries wg * per, wg * per + nwg * per, ...:
+// the first ceil(nlist / per) workgroups have cells and write force records
+// (their number goes to the counters for the reduction); the others leave at
+// once, so that a grid sized for the lattice costs little when the list is
+// short (a batch of small instances).
+__device__ __forceinline__ bool active_workgroup(StepCounters& C, int wg, int nwg, int nlist, int per) {
+    const int active = min(nwg, (nlist + per - 1) / per);
+    if (wg == 0 && threadIdx.x == 0 && active > 0) C.n_frec = active;
+    return wg < active;
+}
+
 // The momentum-exchange record of boundary workgroup wg: every thread's
 // FP64 partial sum (of the first body it met, rec_body) is summed per body
 // over the wavefront in order of first appearance, then the workgroup's
@@ -444,6 +455,7 @@ __device__ __forceinline__ void sweep_boundary(const Inst& I, int parity, int wg
     const float isc = I.inv_scale;
     StepCounters& C = I.ctl->cnt[parity];
     const int nlist = min(C.n_bnd, I.list_cap);
+    if (!active_workgroup(C, wg, nwg, nlist, BCELLS)) return;
     const bool px = I.periodic & 1, py = I.periodic & 2, pz = I.periodic & 4;
     const float* __restrict__ phi_t = phi_of(I, parity);
     const int l = threadIdx.x & (BL - 1);
@@ -806,6 +818,7 @@ __device__ __forceinline__ void sweep_boundary1(const Inst& I, int parity, int w
     const BndIO<S, BUF> io(I, parity);
     StepCounters& C = I.ctl->cnt[parity];
     const int nlist = min(C.n_bnd, I.list_cap);
+    if (!active_workgroup(C, wg, nwg, nlist, 256)) return;
     const bool px = I.periodic & 1, py = I.periodic & 2, pz = I.periodic & 4;
     const int nx = I.nx, ny = I.ny, nz = I.nz, sxy = nx, sz = nx * ny;
     int rec_body = -1;

@@ -98,6 +98,7 @@ struct StepCounters {
     int overflow, n_bnd;
     int n_strd;  // stranded candidates the sweep listed (in Inst::recv)
     int n_se;    // of those, the ones that empty (listed after the sweep's candidates)
+    int n_frec;  // force records the boundary sweep wrote (its workgroups that had listed cells)
     double acc[MAXB][6];  // per body: F (3), T (3), FP64
 };
 

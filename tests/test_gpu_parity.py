@@ -1065,12 +1065,12 @@ def test_autotune_keeps_state(lbm):
         assert np.array_equal(A.flags(k), B.flags(k)), k
 
 
-@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+@pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
 def test_righting_moment_vs_oracle(lbm, storage):
     """The benchmark box held at 10, 20 and 30 deg on the 128^3 basin: the
     righting moment -T_x averaged over the last 1000 of 5000 steps (every 10
     steps) agrees with the FP64 oracle's (tests/golden/righting_moment_128.json)
-    within 1%, in FP32 and in FP16 deviation storage."""
+    within 1%, in FP32, FP16 and BF16 deviation storage."""
     import json
 
     with open(os.path.join(os.path.dirname(__file__), "golden", "righting_moment_128.json")) as f:
@@ -1089,6 +1089,40 @@ def test_righting_moment_vs_oracle(lbm, storage):
         ms = float(np.mean(samples))
         err = abs(ms - run["m_s"]) / abs(run["m_s"])
         say("  %s heel %g: m_s %.6e oracle %.6e rel err %.2e" % (storage, run["heel_deg"], ms, run["m_s"], err))
+        assert err <= 1e-2
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+def test_batch48_righting_moment_vs_oracle(lbm, storage):
+    """The 48-instance heel sweep stepped as one batched context: for four of
+    its instances (the smallest, the largest, the furthest heeled and the
+    furthest heeled of density 0.7) the righting moment averaged over the
+    last 1000 of 3000 steps agrees with the FP64 oracle's run of that
+    instance alone (tests/golden/batch48_righting.json) within 1%."""
+    import json
+
+    with open(os.path.join(os.path.dirname(__file__), "golden", "batch48_righting.json")) as f:
+        gold = json.load(f)
+    insts = W.config4(storage=storage)["instances"]
+    L = lbm.Lattice([dict(i["lattice"], max_bodies=1) for i in insts])
+    for k, i in enumerate(insts):
+        L.set_body(0, i["bodies"][0], inst=k)
+    L.set_tuning(batched=1)
+    samples = {r["instance"]: [] for r in gold["runs"]}
+    done = 0
+    while done < gold["steps"]:
+        L.step(gold["every"])
+        done += gold["every"]
+        if done > gold["steps"] - gold["window"]:
+            for k in samples:
+                samples[k].append(-L.body_forces(0, inst=k)[1][0])
+    L.sync()
+    L.close()
+    for r in gold["runs"]:
+        ms = float(np.mean(samples[r["instance"]]))
+        err = abs(ms - r["m_s"]) / abs(r["m_s"])
+        say("  %s instance %d %s heel %.1f rho_s %.1f: m_s %.6e oracle %.6e rel err %.2e" % (
+            storage, r["instance"], "x".join(map(str, r["shape"])), r["heel_deg"], r["density"], ms, r["m_s"], err))
         assert err <= 1e-2
 
 
