@@ -252,7 +252,9 @@ int32_t lbm_kernel_time(lbm_ctx* ctx, int32_t kernel, double* total_ms, int64_t*
 
 /* Launch configuration of a context (not a quantity of the method).
  * tile_x: width along x of the bulk-sweep tiles, 32, 64 or 128 cells
- * (256 / tile_x rows).  batched: step all instances with one launch per
+ * (256 / tile_x rows), or 0: tiles of 256 consecutive cells of a z-layer
+ * (rows packed end to end; every lane holds a cell for widths that are not
+ * a multiple of the tile width).  batched: step all instances with one launch per
  * kernel (all instances must share one storage type; no effect with one
  * instance; the default for several instances of one storage type).
  * use_graph: lbm_step replays pairs of full steps from a captured HIP graph
@@ -274,8 +276,8 @@ int32_t lbm_get_tuning(lbm_ctx* ctx, int32_t* tile_x, int32_t* batched, int32_t*
                        int32_t* boundary_layout);
 
 /* Autotuner.  First the bulk sweep: reps launches on the current state for
- * every tile width (32, 64, 128) and store policy (cached, streaming), the
- * fastest of the six kept.  Then the boundary sweep: reps launches with each
+ * every tile width (32, 64, 128, and 0: packed rows) and store policy
+ * (cached, streaming), the fastest of the eight kept.  Then the boundary sweep: reps launches with each
  * work layout, the faster kept (skipped, layout unchanged and boundary_ms
  * -1, when the device has no room for a copy of the interface cells' mass,
  * flags and counters, 9 bytes per cell).  The state does not change: the

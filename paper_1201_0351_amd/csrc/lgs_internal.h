@@ -685,7 +685,8 @@ struct BatchGrid {
 };
 
 // workgroups of one instance's bulk grid for a tile width (32, 64 or 128
-// cells along x, 256 / width rows), padded to a multiple of 8
+// cells along x, 256 / width rows; 0: 256 consecutive cells of a layer),
+// padded to a multiple of 8
 int bulk_blocks(const Inst& I, int tile_x);
 
 // e0 / e1: optional events recorded at the start / end of the kernel itself;

@@ -48,11 +48,17 @@ def lbm():
 def with_layout(L, layout):
     """The binding module with every new context on the given boundary-sweep
     layout."""
+    return with_tuning(L, boundary_layout=layout)
+
+
+def with_tuning(L, **tuning):
+    """The binding module with every new context on the given launch
+    configuration."""
 
     class Lat(L.Lattice):
         def __init__(self, *a, **k):
             super().__init__(*a, **k)
-            self.set_tuning(boundary_layout=layout)
+            self.set_tuning(**tuning)
 
     ns = types.SimpleNamespace(**{k: getattr(L, k) for k in dir(L) if not k.startswith("__")})
     ns.Lattice = Lat
@@ -744,6 +750,27 @@ def test_one_thread_boundary_layout(lbm, case, kw):
     globals()[case](with_layout(lbm, 1), **kw)
 
 
+RECT_TILE_CASES = [
+    ("test_bulk_sweep_16bit_shapes", dict(n=(130, 20, 18), periodic=0, storage="fp16")),
+    ("test_bulk_sweep_16bit_shapes", dict(n=(64, 24, 20), periodic=1, storage="bf16")),
+    ("test_sweep_on_injected_state", dict(periodic=3)),
+    ("test_body_moving_across_periodic_faces", {}),
+    ("test_moving_wall_channel_with_free_sphere", {}),
+    ("test_batched_instances_match_single", {}),
+    ("test_basin_steps_without_body", dict(storage="fp32", tol=1e-5)),
+]
+
+
+@pytest.mark.parametrize("tile_x", [32, 64, 128])
+@pytest.mark.parametrize("case,kw", RECT_TILE_CASES, ids=["%s-%d" % (c[0][5:], k) for k, c in enumerate(RECT_TILE_CASES)])
+def test_rectangular_tiles(lbm, case, kw, tile_x):
+    """The bulk sweep on the rectangular tiles (tile_x x 256 / tile_x cells of
+    a layer; partial tiles at x faces for widths such as 130) through the same
+    parity checks as the default packed-row tiles (256 consecutive cells of a
+    layer, wavefronts crossing row ends)."""
+    globals()[case](with_tuning(lbm, tile_x=tile_x), **kw)
+
+
 def test_multi_instance_independent(lbm):
     """Two instances of different sizes in one context advance exactly as
     they would alone."""
@@ -1049,7 +1076,7 @@ def test_autotune_keeps_state(lbm):
         L.step(7)
     t = A.autotune(reps=3)
     say("autotune: %s" % t)
-    assert t["tile_x"] in (32, 64, 128) and t["stream_store"] in (0, 1) and t["bulk_ms"] > 0
+    assert t["tile_x"] in (0, 32, 64, 128) and t["stream_store"] in (0, 1) and t["bulk_ms"] > 0
     assert t["boundary_layout"] in (0, 1) and t["boundary_ms"] > 0
     got = A.get_tuning()
     assert (got["tile_x"], got["stream_store"], got["boundary_layout"]) == (t["tile_x"], t["stream_store"],
