@@ -510,13 +510,37 @@ def channel_accuracy(ref, storages=("fp32", "fp16", "bf16")):
     return out
 
 
+def basin256_oracle(steps=2):
+    """The FP64 oracle on the 256x192x192 held-box basin (truncated run): one
+    untimed step (it maps the box), then `steps` steps on all host cores."""
+    from oracle.oracle import Oracle
+    from paper_1201_0351_amd import workloads as W
+
+    threads = min(16, os.cpu_count() or 1)
+    w = W.config3(20.0)
+    c, b = w["lattice"], w["bodies"][0]
+    o = Oracle(c["nx"], c["ny"], c["nz"], c["tau"], accel=c["accel"], eps=c["eps"], threads=threads)
+    o.init_basin(c["fill_height"])
+    o.set_body(0, b["half"], b["pos"], b["quat"], density=b["density"], fixed=1)
+    o.step(1)
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    n = o.ncells
+    o.close()
+    return dict(value=n * steps / dt / 1e6, unit="MLUPS", cores=threads,
+                sample="%d steps of the 256x192x192 basin with its held box (after one untimed mapping step), FP64"
+                       % steps)
+
+
 def cpu_baseline(ref):
     n = ref["n"]
     return dict(value=n * ref["steps_all"] / ref["t_all"] / 1e6, unit="MLUPS", cores=ref["threads"], kind="oracle",
                 sample="%d steps of the 512x256x256 channel with its free box (after one untimed mapping step), "
                        "FP64, %d OpenMP threads; one_thread: %d more step(s) on 1 thread" % (
                            ref["steps_all"], ref["threads"], ref["steps_one"]),
-                one_thread=dict(value=n * ref["steps_one"] / ref["t_one"] / 1e6, cores=1))
+                one_thread=dict(value=n * ref["steps_one"] / ref["t_one"] / 1e6, cores=1),
+                basin256=basin256_oracle())
 
 
 def copy_probe(mib):
