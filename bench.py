@@ -33,12 +33,16 @@ bytes per launch the profiler counted for the same kernel and workload
 kernel source is the one that was profiled.  `channel` repeats the timed run
 with FP16 and BF16 deviation storage and with the rigid-body update on the
 host; `accuracy` compares the channel's body force and torque after four
-steps with the FP64 oracle's; `righting_moment` holds the 128^3 box at the
-heel angles of the oracle's golden run and compares the averaged -T_x
+steps with the FP64 oracle's, and `accuracy_basin256` those of the
+256x192x192 held box after three (with the count of cells whose type
+differs); `righting_moment` holds the 128^3 box at the heel angles of the
+oracle's golden run and compares the averaged -T_x and the final cell types
 (tests/golden/righting_moment_128.json); `other_configs` times the 128^3
 basin (cache resident), the 256x192x192 held box and the 48-instance heel
-sweep.  `cpu_baseline` times the FP64 oracle on the host on a bounded sample
-of the headline workload, on all cores and on one thread.
+sweep, whose righting moment of four instances is compared with the oracle's
+(tests/golden/batch48_righting.json).  `cpu_baseline` times the FP64 oracle
+on the host on a bounded sample of the headline workload, on all cores and
+on one thread, and on two steps of the 256x192x192 basin.
 
 Side experiments, each printed as JSON instead of the benchmark line:
 `--free-advection` (the sphere in the moving-wall channel, for every tau and
@@ -66,6 +70,7 @@ METRIC = "MLUPS + % of HBM roofline (FP32 vs FP16-storage) at ≤1% righting-mom
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_bulk_channel512_traffic.txt")
 GOLDEN_RM = os.path.join(ROOT, "tests", "golden", "righting_moment_128.json")
+GOLDEN_BATCH = os.path.join(ROOT, "tests", "golden", "batch48_righting.json")
 SWEEP_SOURCES = ("paper_1201_0351_amd/csrc/k_sweep.hip", "paper_1201_0351_amd/csrc/lgs_internal.h")
 PREP_STEPS = 200
 WINDOWS = 5
@@ -251,10 +256,57 @@ def righting_moment(storage):
             done += k
             if done > run["steps"] - run["window"]:
                 samples.append(-L.body_forces(0)[1][0])
+        mism = None
+        if "final_types" in run:
+            mism = int((L.types() != unpack_types(run["final_types"], L.shape())).sum())
         L.close()
         ms = sum(samples) / len(samples)
         out.append(dict(heel_deg=run["heel_deg"], m_s=ms, m_s_oracle=run["m_s"],
-                        rel_err=abs(ms - run["m_s"]) / abs(run["m_s"]), analytic=run["analytic_polygon"]))
+                        rel_err=abs(ms - run["m_s"]) / abs(run["m_s"]), analytic=run["analytic_polygon"],
+                        type_mismatches=mism))
+    return out
+
+
+def unpack_types(s, shape):
+    """Cell types stored by the golden scripts: four 2-bit codes per byte, zlib, base64."""
+    import base64
+    import zlib
+
+    packed = np.frombuffer(zlib.decompress(base64.b64decode(s)), np.uint8)
+    t = np.stack([(packed >> k) & 3 for k in (0, 2, 4, 6)], axis=1).ravel()
+    return t[: int(np.prod(shape))].reshape(shape)
+
+
+def batch_righting(storage):
+    """The batched 48-instance context from its initial state for the
+    golden's steps: the righting moment of the four instances the oracle ran
+    alone (tests/golden/batch48_righting.json), averaged the same way."""
+    from paper_1201_0351_amd import lbm
+    from paper_1201_0351_amd import workloads as W
+
+    if not os.path.exists(GOLDEN_BATCH):
+        return None
+    with open(GOLDEN_BATCH) as f:
+        gold = json.load(f)
+    insts = W.config4(storage=storage)["instances"]
+    L = lbm.Lattice([dict(i["lattice"], max_bodies=1) for i in insts])
+    for k, i in enumerate(insts):
+        L.set_body(0, i["bodies"][0], inst=k)
+    L.set_tuning(batched=1)
+    samples = {r["instance"]: [] for r in gold["runs"]}
+    done = 0
+    while done < gold["steps"]:
+        L.step(gold["every"])
+        done += gold["every"]
+        if done > gold["steps"] - gold["window"]:
+            for k in samples:
+                samples[k].append(-L.body_forces(0, inst=k)[1][0])
+    L.close()
+    out = []
+    for r in gold["runs"]:
+        ms = sum(samples[r["instance"]]) / len(samples[r["instance"]])
+        out.append(dict(instance=r["instance"], shape=r["shape"], heel_deg=round(r["heel_deg"], 2), density=r["density"],
+                        m_s=ms, m_s_oracle=r["m_s"], rel_err=abs(ms - r["m_s"]) / abs(r["m_s"])))
     return out
 
 
@@ -335,6 +387,12 @@ def other_configs(steps, warmup):
                      "see righting_moment"
     out["basin256x192x192_box64x64x32_heel20_held"] = b3
     out["batch48_heel_sweep"] = {st: run_batch(st, steps, warmup) for st in ("fp32", "fp16")}
+    for st in ("fp32", "fp16"):
+        rt = batch_righting(st)
+        if rt is not None:
+            out["batch48_heel_sweep"][st]["righting_moment"] = dict(
+                runs=rt, max_rel_err=round(max(r["rel_err"] for r in rt), 5),
+                reference="FP64 oracle runs of four instances alone, tests/golden/batch48_righting.json")
     out["batch48_heel_sweep"]["fp32_one_launch_per_instance"] = run_batch("fp32", steps, warmup, batched=False)
     out["batch48_heel_sweep"]["fp32_graph"] = run_batch("fp32", steps, warmup, graph=True)
     return out
@@ -527,20 +585,51 @@ def basin256_oracle(steps=2):
     o.step(steps)
     dt = time.perf_counter() - t0
     n = o.ncells
+    F, T = o.body_forces(0)
+    flags = o.get_flags()
     o.close()
     return dict(value=n * steps / dt / 1e6, unit="MLUPS", cores=threads,
                 sample="%d steps of the 256x192x192 basin with its held box (after one untimed mapping step), FP64"
-                       % steps)
+                       % steps, state=dict(steps=1 + steps, F=F, T=T, flags=flags))
 
 
-def cpu_baseline(ref):
+def basin256_accuracy(ref, storages=("fp32", "fp16", "bf16")):
+    """The 256x192x192 held box on the GPU for the oracle's number of steps
+    from the same initial state: error of the force and torque of the last
+    sweep (relative to the oracle's vector and to the box's buoyancy scale)
+    and the cells whose type differs."""
+    from paper_1201_0351_amd import lbm
+    from paper_1201_0351_amd import workloads as W
+
+    w = W.config3(20.0)
+    b = w["bodies"][0]
+    g = abs(w["lattice"]["accel"][2])
+    scale = 8.0 * b["half"][0] * b["half"][1] * b["half"][2] * g * 0.5
+    out = {"steps": ref["steps"], "reference": "FP64 oracle, same initial state",
+           "oracle_force": [float(v) for v in ref["F"]], "oracle_torque": [float(v) for v in ref["T"]]}
+    for st in storages:
+        w = W.config3(20.0, st)
+        L = lbm.Lattice(dict(w["lattice"], max_bodies=1))
+        L.set_body(0, w["bodies"][0])
+        L.step(ref["steps"])
+        F, T = L.body_forces(0)
+        mism = int((L.flags() != ref["flags"]).sum())
+        L.close()
+        dF, dT = np.linalg.norm(F - ref["F"]), np.linalg.norm(T - ref["T"])
+        out[st] = dict(force_rel_err=float(dF / np.linalg.norm(ref["F"])),
+                       torque_rel_err=float(dT / np.linalg.norm(ref["T"])),
+                       force_err_of_half_weight=float(dF / scale), flag_mismatches=mism)
+    return out
+
+
+def cpu_baseline(ref, ref3):
     n = ref["n"]
     return dict(value=n * ref["steps_all"] / ref["t_all"] / 1e6, unit="MLUPS", cores=ref["threads"], kind="oracle",
                 sample="%d steps of the 512x256x256 channel with its free box (after one untimed mapping step), "
                        "FP64, %d OpenMP threads; one_thread: %d more step(s) on 1 thread" % (
                            ref["steps_all"], ref["threads"], ref["steps_one"]),
                 one_thread=dict(value=n * ref["steps_one"] / ref["t_one"] / 1e6, cores=1),
-                basin256=basin256_oracle())
+                basin256={k: v for k, v in ref3.items() if k != "state"})
 
 
 def copy_probe(mib):
@@ -660,7 +749,9 @@ def main():
     if not args.no_cpu:
         ref = channel_oracle()
         out["accuracy"] = channel_accuracy(ref)
-        out["cpu_baseline"] = cpu_baseline(ref)
+        ref3 = basin256_oracle()
+        out["accuracy_basin256"] = basin256_accuracy(ref3["state"])
+        out["cpu_baseline"] = cpu_baseline(ref, ref3)
         print("oracle done", file=sys.stderr, flush=True)
     print(json.dumps(out))
 

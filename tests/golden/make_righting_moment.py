@@ -4,16 +4,23 @@ Workload: 128^3 basin, tau 0.55, gravity 5e-6, liquid depth 64, a 32x32x16
 box (density 0.5) held with its centre on the water plane at a heel of 10,
 20 and 30 deg about x (the held form of the 128^3 heeled-box workload).  The
 righting moment m_s = -T_x is averaged over the last `window` of `steps`
-steps (sampled every `every` steps).  Only the oracle is called.
+steps (sampled every `every` steps).  The cell types after the last step
+are stored too (2 bits per cell, z-major, packed four to a byte, zlib,
+base64) so that a run of the same workload can count the cells whose type
+differs.  Only the oracle is called.
 
 Usage: python tests/golden/make_righting_moment.py [--steps 5000] [--threads 8]
 """
 import argparse
+import base64
 import json
 import math
 import os
 import sys
 import time
+import zlib
+
+import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
@@ -21,6 +28,20 @@ sys.path.insert(0, ROOT)
 
 from oracle import analytic as A  # noqa: E402
 from oracle.oracle import Oracle  # noqa: E402
+
+
+def pack_types(t):
+    """Cell types (0..3, [nz, ny, nx]) as base64 of zlib of four 2-bit codes per byte."""
+    flat = np.ascontiguousarray(t, dtype=np.uint8).ravel()
+    flat = np.concatenate([flat, np.zeros((-len(flat)) % 4, np.uint8)]).reshape(-1, 4)
+    packed = (flat[:, 0] | (flat[:, 1] << 2) | (flat[:, 2] << 4) | (flat[:, 3] << 6)).astype(np.uint8)
+    return base64.b64encode(zlib.compress(packed.tobytes(), 9)).decode("ascii")
+
+
+def unpack_types(s, shape):
+    packed = np.frombuffer(zlib.decompress(base64.b64decode(s)), np.uint8)
+    t = np.stack([(packed >> k) & 3 for k in (0, 2, 4, 6)], axis=1).ravel()
+    return t[: int(np.prod(shape))].reshape(shape)
 
 
 def run(heel, steps, window, every, threads):
@@ -44,6 +65,7 @@ def run(heel, steps, window, every, threads):
             print("heel %g step %d m_s %.6e (%.0f s)" % (heel, done, -T[0], time.time() - t0), flush=True)
     ms = sum(samples) / len(samples)
     return dict(heel_deg=heel, steps=steps, window=window, every=every, m_s=ms,
+                final_types=pack_types(o.types()),
                 analytic_polygon=A.righting_moment_polygon(32, 16, 32, a, g, zw=0.0),
                 trace=trace[:: max(1, len(trace) // 100)])
 

@@ -89,6 +89,27 @@ def test_golden_settled_heels_against_the_paper():
         assert abs(got - want) <= bound, (k, got, want)
 
 
+def test_golden_density_three_quarters_has_no_single_resting_heel():
+    """Released 0.001 deg further (section settle_perturbed), the oracle's box
+    of density 3/4 comes to rest at another heel, 6.5 deg away, while the
+    boxes of density 1/2 and 1/4 settle where they did to 0.01 deg: at 16 cells
+    a side the mapped hull's steps hold the 3/4 box anywhere between the
+    continuum equilibrium (26.565 deg) and about 37 deg, and the transient
+    decides where.  Both of its resting heels are at rest (the last 1000
+    steps within 0.1 deg) and inside that band."""
+    g = _gold()
+    a, b = g["settle"], g["settle_perturbed"]
+    assert b["dof"] == 0x0C and abs(b["heel0_deg"] - 10.001) < 1e-12 and b["steps"] == a["steps"]
+    ha, hb = a["settled_heel_deg"], b["settled_heel_deg"]
+    assert abs(ha[0] - hb[0]) > 5.0
+    for k in (1, 2):
+        assert abs(ha[k] - hb[k]) < 0.05, (k, ha[k], hb[k])
+    for r in (a, b):
+        tail = np.abs(np.array(r["trace"])[-5:, 1])
+        assert tail.max() - tail.min() <= 0.1
+        assert 26.0 <= r["settled_heel_deg"][0] <= 38.0
+
+
 def test_golden_roll_only_starts_far_from_equilibrium():
     r = _gold()["roll_only"]
     assert r["dof"] == 0x08 and r["heel0_deg"] == 15.0
