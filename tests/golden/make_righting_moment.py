@@ -10,6 +10,10 @@ base64) so that a run of the same workload can count the cells whose type
 differs.  Only the oracle is called.
 
 Usage: python tests/golden/make_righting_moment.py [--steps 5000] [--threads 8]
+       [--heels 10,20,30] [--out FILE]
+       python tests/golden/make_righting_moment.py --merge PART1 PART2 ... [--out FILE]
+(the heels are independent runs: --merge joins files this script wrote for
+some of them into one, in the order given)
 """
 import argparse
 import base64
@@ -78,10 +82,18 @@ def main():
     ap.add_argument("--threads", type=int, default=min(8, os.cpu_count() or 1))
     ap.add_argument("--heels", type=str, default="10,20,30")
     ap.add_argument("--out", type=str, default=os.path.join(HERE, "righting_moment_128.json"))
+    ap.add_argument("--merge", nargs="+", default=None)
     args = ap.parse_args()
     res = dict(_source="FP64 oracle (oracle/lgs_oracle.c), written by tests/golden/make_righting_moment.py",
-               workload="128^3 basin tau 0.55 g 5e-6 depth 64, box 32x32x16 rho_s 0.5 held, G on the water plane",
-               runs=[run(float(h), args.steps, args.window, args.every, args.threads) for h in args.heels.split(",")])
+               workload="128^3 basin tau 0.55 g 5e-6 depth 64, box 32x32x16 rho_s 0.5 held, G on the water plane")
+    if args.merge:
+        runs = []
+        for part in args.merge:
+            with open(part) as f:
+                runs += json.load(f)["runs"]
+        res["runs"] = runs
+    else:
+        res["runs"] = [run(float(h), args.steps, args.window, args.every, args.threads) for h in args.heels.split(",")]
     with open(args.out, "w") as f:
         json.dump(res, f, indent=1)
     print("wrote", args.out)
