@@ -400,9 +400,15 @@ __device__ __forceinline__ void conv_middle(const Inst& I, int parity, int blk, 
     S* pop = (S*)pop_of(I, parity ^ 1);
     float* phi = phi_of(I, parity ^ 1);
     const int j = g_lane();
-    const int g0 = blk * CG + (int)(threadIdx.x >> 5), ng = nblk * CG;
+    // The new cells from gas and the excess shares are independent chains of
+    // dependent loads: the first half of the workgroups takes the one, the
+    // second half the other, so that they run side by side.
+    const int half = max(1, nblk / 2);
+    const bool gas_part = blk < half;
+    const int pb = gas_part ? blk : blk - half, pn = gas_part ? half : nblk - half;
+    const int g0 = pb * CG + (int)(threadIdx.x >> 5), ng = pn * CG;
     // new interface cells from gas, one group each (lane j: neighbour j)
-    const int nng = list_len(&C.n_newg, I.list_cap);
+    const int nng = gas_part ? list_len(&C.n_newg, I.list_cap) : 0;
     for (int k = g0; k < nng; k += ng) {
         const int g = I.newg[k];
         int gx, gy, gz;
@@ -451,7 +457,7 @@ __device__ __forceinline__ void conv_middle(const Inst& I, int parity, int blk, 
         phi[id] = 1.f;
     }
     // excess shares, one group per converted cell (lane i: neighbour x + c_i)
-    const int nc = cand_len(C, I.list_cap);
+    const int nc = gas_part && nblk > 1 ? 0 : cand_len(C, I.list_cap);
     for (int k = g0; k < nc; k += ng) {
         const int id = I.cand[k];
         const uint8_t fl = I.flags[id];

@@ -890,11 +890,12 @@ __device__ __forceinline__ void sweep_boundary1(const Inst& I, int parity, int w
             for (int i = 1; i <= 6; ++i) {
                 const int s = source(i);
                 const int e = s >= 0 ? io.flag(s) : -1;
+                const float fs = io.fill(s >= 0 ? s : id);  // issued with the type, used for interface sources
                 const int st = e & TYPE_MASK;
                 double v = (double)phix;
                 if (e >= 0 && st == LIQ) v = 1.0;
                 else if (e >= 0 && st == GAS) v = 0.0;
-                else if (e >= 0 && st == IFC) v = (double)io.fill(s);
+                else if (e >= 0 && st == IFC) v = (double)fs;
                 f[i] = v;
             }
             n0 = 0.5 * (f[2] - f[1]);
@@ -924,13 +925,16 @@ __device__ __forceinline__ void sweep_boundary1(const Inst& I, int parity, int w
             const int sa = s >= 0 ? s : id;
             const int e = s >= 0 ? io.flag(sa) : -1;
             const float dri = io.pop(i, sa);  // f_i(x - c_i)
+            // the source's fill, issued with its type (not after it) for an
+            // interface cell; used only when the source is an interface cell
+            const float fs = ifc ? io.fill(sa) : 0.f;
             const int st = e & TYPE_MASK;
             const float dxo = dx[o];
             if (e >= 0 && st == LIQ) liq = 1;
             if (ifc && e >= 0) {
                 const float ex = dri - dxo;  // f_i(x + c_ibar) - f_ibar(x)
                 if (st == LIQ) pdm += ex;
-                else if (st == IFC) pdm += 0.5f * (phix + io.fill(sa)) * ex;
+                else if (st == IFC) pdm += 0.5f * (phix + fs) * ex;
             }
             const float cxf = (float)cx(i), cyf = (float)cy(i), czf = (float)cz(i);
             const float wi = wgt(i);
