@@ -143,52 +143,59 @@ __device__ __forceinline__ int cand_len(const StepCounters& C, int cap) { return
 // ---------------------------------------------------------------------------
 namespace {
 
-__device__ __forceinline__ double wave_sum_d(double v) {
+// Sum of the boundary sweep's force records per body, in fixed point
+// (fx_split): thread t takes records t + j CT, then wavefront butterflies,
+// then the wavefronts, then the atomics' sums; all integer sums, so the
+// result does not depend on their order.  F and T (FP64, formed once from
+// the totals) go to the accumulators and to sacc.
+__device__ __forceinline__ long long wave_sum_i(long long v) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
     return v;
 }
 
-// Fixed-order FP64 sum of the boundary sweep's force records, per body:
-// thread t takes records t + j CT in order j, then wavefront butterflies,
-// then acc = (entry the atomics left) + wavefront partials in wavefront
-// order.  The result is in the accumulators and in sacc.
 __device__ __forceinline__ void reduce_forces(const Inst& I, int parity, double (*sacc)[6]) {
     constexpr int PER = BND_BLOCKS_MAX / CT;
     static_assert(PER * CT == BND_BLOCKS_MAX, "force records per thread");
-    __shared__ double part[CW][MAXB][6];
-    const int nrec = min(boundary_blocks(I), I.ctl->cnt[parity].n_frec);
-    int rb[PER];
-    double rv[PER][6];
+    __shared__ long long part[CW][MAXB][FXW];
+    StepCounters& C = I.ctl->cnt[parity];
+    const int nrec = min(boundary_blocks(I), C.n_frec);
+    uint32_t mk[PER];
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         const int k = threadIdx.x + j * CT;
-        rb[j] = k < nrec ? I.frec_body[k] : -1;
-#pragma unroll
-        for (int q = 0; q < 6; ++q) rv[j][q] = k < nrec ? I.frec_v[q * BND_BLOCKS_MAX + k] : 0.0;
+        mk[j] = k < nrec ? I.frec_mask[k] : 0u;
     }
-    const int t = threadIdx.x;
-    const double acc0 = t < 6 * I.nbodies ? I.ctl->cnt[parity].acc[t / 6][t % 6] : 0.0;
     for (int b = 0; b < I.nbodies; ++b) {
-        double v[6] = {0, 0, 0, 0, 0, 0};
+        long long v[FXW];
+#pragma unroll
+        for (int q = 0; q < FXW; ++q) v[q] = 0;
 #pragma unroll
         for (int j = 0; j < PER; ++j)
-            if (rb[j] == b)
+            if ((mk[j] >> b) & 1u) {
+                const int k = threadIdx.x + j * CT;
 #pragma unroll
-                for (int q = 0; q < 6; ++q) v[q] += rv[j][q];
+                for (int q = 0; q < FXW; ++q) v[q] += I.frec_v[(b * FXW + q) * BND_BLOCKS_MAX + k];
+            }
 #pragma unroll
-        for (int q = 0; q < 6; ++q) v[q] = wave_sum_d(v[q]);
+        for (int q = 0; q < FXW; ++q) v[q] = wave_sum_i(v[q]);
         if ((threadIdx.x & 63) == 0)
 #pragma unroll
-            for (int q = 0; q < 6; ++q) part[threadIdx.x >> 6][b][q] = v[q];
+            for (int q = 0; q < FXW; ++q) part[threadIdx.x >> 6][b][q] = v[q];
     }
     __syncthreads();
+    const int t = threadIdx.x;
     if (t < 6 * I.nbodies) {
-        double s = acc0;
+        const int b = t / 6, q = t % 6;
+        long long h = C.facc[b][q], l = C.facc[b][6 + q];
 #pragma unroll
-        for (int w = 0; w < CW; ++w) s += part[w][t / 6][t % 6];
-        I.ctl->cnt[parity].acc[t / 6][t % 6] = s;
-        sacc[t / 6][t % 6] = s;
+        for (int w = 0; w < CW; ++w) {
+            h += part[w][b][q];
+            l += part[w][b][6 + q];
+        }
+        const double s = fx_value(h, l);
+        C.acc[b][q] = s;
+        sacc[b][q] = s;
     }
     __syncthreads();
 }
@@ -210,6 +217,7 @@ __device__ __forceinline__ void clear_other(const Inst& I, int parity, int tid, 
     const int nint = (int)(offsetof(StepCounters, acc) / sizeof(int));
     for (int q = tid; q < nint; q += nthr) ci[q] = 0;
     for (int q = tid; q < MAXB * 6; q += nthr) (&O.acc[0][0])[q] = 0.0;
+    for (int q = tid; q < MAXB * FXW; q += nthr) (&O.facc[0][0])[q] = 0;
 }
 
 // Bodies after the force reduction of a full step, run by one wavefront

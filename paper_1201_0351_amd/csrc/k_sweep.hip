@@ -398,63 +398,80 @@ __device__ __forceinline__ bool active_workgroup(StepCounters& C, int wg, int nw
     return wg < active;
 }
 
-// The momentum-exchange record of boundary workgroup wg: every thread's
-// FP64 partial sum (of the first body it met, rec_body) is summed per body
-// over the wavefront in order of first appearance, then the workgroup's
-// record from its wavefronts' records in wavefront order; contributions to
-// a second body go to the accumulators by atomics.  Every thread calls it.
-__device__ __forceinline__ void force_record(const Inst& I, StepCounters& C, int wg, int rec_body,
-                                             const double (&rv)[6]) {
-    // wavefront sums per body (in order of first appearance), then the
-    // workgroup's record from its wavefronts' records in wavefront order
-    int wbody = -1;
-    double wv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    unsigned long long m = __ballot(rec_body >= 0);
+// Momentum exchange per boundary workgroup and body, in fixed point
+// (fx_split): each pass's lane terms are summed per body over the wavefront
+// into the wavefront's slot in LDS, and at the end the slots into the
+// workgroup's record of each body it met.  Every sum is an integer sum.
+struct ForceLDS {
+    long long v[4][MAXB][FXW];
+    uint32_t mask[4];
+};
+
+__device__ __forceinline__ long long wave_sum_i(long long v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// every wavefront clears its own slot
+__device__ __forceinline__ void force_begin(ForceLDS& F) {
+    const int w = threadIdx.x >> 6, l = lane_id();
+    long long* v = &F.v[w][0][0];
+    for (int k = l; k < MAXB * FXW; k += 64) v[k] = 0;
+    if (l == 0) F.mask[w] = 0u;
+}
+
+// one pass: lane terms cv (force, torque) on body `body` (-1: none); every
+// lane of the wavefront calls it
+__device__ __forceinline__ void force_flush(ForceLDS& F, int body, const float (&cv)[6]) {
+    const int w = threadIdx.x >> 6;
+    unsigned long long m = __ballot(body >= 0);
+    if (!m) return;
+    long long h[6], l[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) fx_split(cv[q], h[q], l[q]);
     while (m) {
         const int leader = __ffsll((long long)m) - 1;
-        const int b = __shfl(rec_body, leader);
-        const bool mine = rec_body == b;
-        double v[6];
+        const int b = __shfl(body, leader);
+        const bool mine = body == b;
+        long long v[FXW];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) v[q] = wave_sum(mine ? rv[q] : 0.0);
-        if (wbody < 0) wbody = b;
-        if (b == wbody) {
+        for (int q = 0; q < 6; ++q) {
+            v[q] = wave_sum_i(mine ? h[q] : 0);
+            v[6 + q] = wave_sum_i(mine ? l[q] : 0);
+        }
+        if (lane_id() == 0) {
 #pragma unroll
-            for (int q = 0; q < 6; ++q) wv[q] += v[q];
-        } else if (lane_id() == leader) {
-#pragma unroll
-            for (int q = 0; q < 6; ++q) atomicAdd(&C.acc[b][q], v[q]);
+            for (int q = 0; q < FXW; ++q) F.v[w][b][q] += v[q];
+            F.mask[w] |= 1u << b;
         }
         m &= ~__ballot(mine);
     }
-    __shared__ int sb[4];
-    __shared__ double sv[4][6];
-    const int wv_id = threadIdx.x >> 6;
-    if (lane_id() == 0) {
-        sb[wv_id] = wbody;
+}
+
+// a term on a second body of one cell: integer atomics on the step's sums
+__device__ __forceinline__ void force_atomic(StepCounters& C, int b, const float (&t)[6]) {
+    unsigned long long* a = (unsigned long long*)&C.facc[b][0];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) sv[wv_id][q] = wv[q];
+    for (int q = 0; q < 6; ++q) {
+        long long h, l;
+        fx_split(t[q], h, l);
+        atomicAdd(a + q, (unsigned long long)h);
+        atomicAdd(a + 6 + q, (unsigned long long)l);
     }
+}
+
+// the workgroup's records (every thread calls it)
+__device__ __forceinline__ void force_record(const Inst& I, int wg, ForceLDS& F) {
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int body = -1;
-        double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int w = 0; w < 4; ++w) {
-            const int b = sb[w];
-            if (b < 0) continue;
-            if (body < 0) body = b;
-            if (b == body) {
-#pragma unroll
-                for (int q = 0; q < 6; ++q) acc[q] += sv[w][q];
-            } else {
-#pragma unroll
-                for (int q = 0; q < 6; ++q) atomicAdd(&C.acc[b][q], sv[w][q]);
-            }
-        }
-        I.frec_body[wg] = body;
-#pragma unroll
-        for (int q = 0; q < 6; ++q) I.frec_v[q * BND_BLOCKS_MAX + wg] = acc[q];
+    const uint32_t mask = F.mask[0] | F.mask[1] | F.mask[2] | F.mask[3];
+    const int t = threadIdx.x;
+    if (t < MAXB * FXW) {
+        const int b = t / FXW, q = t % FXW;
+        if ((mask >> b) & 1u)
+            I.frec_v[(b * FXW + q) * BND_BLOCKS_MAX + wg] = F.v[0][b][q] + F.v[1][b][q] + F.v[2][b][q] + F.v[3][b][q];
     }
+    if (t == 0) I.frec_mask[wg] = mask;
 }
 
 // Workgroup wg of nwg of one instance's boundary grid (wg is its
@@ -471,9 +488,9 @@ __device__ __forceinline__ void sweep_boundary(const Inst& I, int parity, int wg
     const float* __restrict__ phi_t = phi_of(I, parity);
     const int l = threadIdx.x & (BL - 1);
     const int cell = threadIdx.x / BL;
-    // this lane's momentum-exchange partial sum (first body it meets)
-    int rec_body = -1;
-    double rv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    // momentum exchange per pass and body, in a fixed order
+    __shared__ ForceLDS fsum;
+    force_begin(fsum);
     // the bodies' centre, velocity and angular velocity, read once per
     // workgroup
     __shared__ double bpos[MAXB][3];
@@ -491,6 +508,8 @@ __device__ __forceinline__ void sweep_boundary(const Inst& I, int parity, int wg
     }
 
     for (int base = wg * BCELLS; base < nlist; base += nwg * BCELLS) {
+        int cell_body = -1;
+        float cv[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         const int k = base + cell;
         const bool active = k < nlist;
         const int id = active ? I.bnd[k] : I.bnd[base];
@@ -661,13 +680,8 @@ __device__ __forceinline__ void sweep_boundary(const Inst& I, int parity, int wg
                         a5 -= t5;
                     } else {
                         // a second body on this lane's links
-                        double* acc = &C.acc[bk][0];
-                        atomicAdd(acc + 0, (double)-j0);
-                        atomicAdd(acc + 1, (double)-j1);
-                        atomicAdd(acc + 2, (double)-j2);
-                        atomicAdd(acc + 3, (double)-t3);
-                        atomicAdd(acc + 4, (double)-t4);
-                        atomicAdd(acc + 5, (double)-t5);
+                        const float tb[6] = {-j0, -j1, -j2, -t3, -t4, -t5};
+                        force_atomic(C, bk, tb);
                     }
                 }
             } else {
@@ -744,29 +758,20 @@ __device__ __forceinline__ void sweep_boundary(const Inst& I, int parity, int wg
                 Store<S>::store(dst, (size_t)i * I.ps + id, d[j] + I.omega * (deq - d[j]) + F, I.scale);
             }
             if (abody >= 0) {
-                if (rec_body < 0) rec_body = abody;
-                if (abody == rec_body) {
-                    rv[0] += (double)a0;
-                    rv[1] += (double)a1;
-                    rv[2] += (double)a2;
-                    rv[3] += (double)a3;
-                    rv[4] += (double)a4;
-                    rv[5] += (double)a5;
-                } else {
-                    double* acc = &C.acc[abody][0];
-                    atomicAdd(acc + 0, (double)a0);
-                    atomicAdd(acc + 1, (double)a1);
-                    atomicAdd(acc + 2, (double)a2);
-                    atomicAdd(acc + 3, (double)a3);
-                    atomicAdd(acc + 4, (double)a4);
-                    atomicAdd(acc + 5, (double)a5);
-                }
+                cell_body = abody;
+                cv[0] = a0;
+                cv[1] = a1;
+                cv[2] = a2;
+                cv[3] = a3;
+                cv[4] = a4;
+                cv[5] = a5;
             }
         }
+        force_flush(fsum, cell_body, cv);
         __syncthreads();  // the next pass overwrites the LDS arrays
     }
 
-    force_record(I, C, wg, rec_body, rv);
+    force_record(I, wg, fsum);
 }
 
 // ---------------------------------------------------------------------------
@@ -832,8 +837,8 @@ __device__ __forceinline__ void sweep_boundary1(const Inst& I, int parity, int w
     if (!active_workgroup(C, wg, nwg, nlist, 256)) return;
     const bool px = I.periodic & 1, py = I.periodic & 2, pz = I.periodic & 4;
     const int nx = I.nx, ny = I.ny, nz = I.nz, sxy = nx, sz = nx * ny;
-    int rec_body = -1;
-    double rv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    __shared__ ForceLDS fsum;
+    force_begin(fsum);
     __shared__ double bpos[MAXB][3];
     __shared__ float bvel[MAXB][3], bom[MAXB][3];
     if ((int)threadIdx.x < I.nbodies * 3) {
@@ -846,6 +851,8 @@ __device__ __forceinline__ void sweep_boundary1(const Inst& I, int parity, int w
     __syncthreads();
 
     for (int base = wg * 256; base < nlist; base += nwg * 256) {
+        int cell_body = -1;
+        float cv[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         const int k = base + (int)threadIdx.x;
         const bool active = k < nlist;
         const int id = I.bnd[active ? k : base];
@@ -977,13 +984,8 @@ __device__ __forceinline__ void sweep_boundary1(const Inst& I, int parity, int w
                         a4 -= t4;
                         a5 -= t5;
                     } else {
-                        double* acc = &C.acc[bk][0];
-                        atomicAdd(acc + 0, (double)-j0);
-                        atomicAdd(acc + 1, (double)-j1);
-                        atomicAdd(acc + 2, (double)-j2);
-                        atomicAdd(acc + 3, (double)-t3);
-                        atomicAdd(acc + 4, (double)-t4);
-                        atomicAdd(acc + 5, (double)-t5);
+                        const float tb[6] = {-j0, -j1, -j2, -t3, -t4, -t5};  // a second body
+                        force_atomic(C, bk, tb);
                     }
                 }
             } else {
@@ -1049,27 +1051,18 @@ __device__ __forceinline__ void sweep_boundary1(const Inst& I, int parity, int w
                 io.put(i, id, d[i] + I.omega * (deq - d[i]) + F);
             }
             if (abody >= 0) {
-                if (rec_body < 0) rec_body = abody;
-                if (abody == rec_body) {
-                    rv[0] += (double)a0;
-                    rv[1] += (double)a1;
-                    rv[2] += (double)a2;
-                    rv[3] += (double)a3;
-                    rv[4] += (double)a4;
-                    rv[5] += (double)a5;
-                } else {
-                    double* acc = &C.acc[abody][0];
-                    atomicAdd(acc + 0, (double)a0);
-                    atomicAdd(acc + 1, (double)a1);
-                    atomicAdd(acc + 2, (double)a2);
-                    atomicAdd(acc + 3, (double)a3);
-                    atomicAdd(acc + 4, (double)a4);
-                    atomicAdd(acc + 5, (double)a5);
-                }
+                cell_body = abody;
+                cv[0] = a0;
+                cv[1] = a1;
+                cv[2] = a2;
+                cv[3] = a3;
+                cv[4] = a4;
+                cv[5] = a5;
             }
         }
+        force_flush(fsum, cell_body, cv);
     }
-    force_record(I, C, wg, rec_body, rv);
+    force_record(I, wg, fsum);
 }
 
 // every array of the instance addressable with 32-bit byte offsets

@@ -151,8 +151,8 @@ size_t layout(const lbm_config& c, Inst* I, char* base) {
     char* l2 = take(4 * N);
     char* l3 = take(4 * N);
     char* l4 = take(4 * N);
-    char* fb = take(sizeof(int) * BND_BLOCKS_MAX);
-    char* fv = take(sizeof(double) * 6 * BND_BLOCKS_MAX);
+    char* fb = take(sizeof(uint32_t) * BND_BLOCKS_MAX);
+    char* fv = take(sizeof(long long) * FXW * MAXB * BND_BLOCKS_MAX);
     char* mp = take(sizeof(double) * mass_parts((int)N));
     char* ct = take(sizeof(Ctl));
     char* bd = take(sizeof(DevBody) * MAXB);
@@ -177,8 +177,8 @@ size_t layout(const lbm_config& c, Inst* I, char* base) {
         I->newl = (int*)l2;
         I->recv = (int*)l3;
         I->bnd = (int*)l4;
-        I->frec_body = (int*)fb;
-        I->frec_v = (double*)fv;
+        I->frec_mask = (uint32_t*)fb;
+        I->frec_v = (long long*)fv;
         I->mass_part = (double*)mp;
         I->ctl = (Ctl*)ct;
         I->bodies = (DevBody*)bd;

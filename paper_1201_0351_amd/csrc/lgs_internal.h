@@ -99,8 +99,30 @@ struct StepCounters {
     int n_strd;  // stranded candidates the sweep listed (in Inst::recv)
     int n_se;    // of those, the ones that empty (listed after the sweep's candidates)
     int n_frec;  // force records the boundary sweep wrote (its workgroups that had listed cells)
-    double acc[MAXB][6];  // per body: F (3), T (3), FP64
+    double acc[MAXB][6];  // per body: F (3), T (3), FP64, formed from the fixed-point sums
+    long long facc[MAXB][12];  // fixed-point sums added by atomics (a cell touching a second body)
 };
+
+// Momentum exchange in fixed point.  A term x (an FP32 partial sum over one
+// lane's links) is carried as two 64-bit integers, h = rint(x 2^24) and
+// l = rint((x - h 2^-24) 2^60): exactly for every FP32 term of magnitude at
+// least 2^-36, to within 2^-61 below that.  Integer sums are exact and do
+// not depend on their order (wrap-around included), so a body's force and
+// torque are the same however the boundary list was split among workgroups
+// and whichever atomic lands first; h 2^-24 + l 2^-60 is formed once, from
+// the totals.  Range: a total below 2^39 in magnitude, at most 2^27 terms
+// per body and step.  Words of one body: h of F, T (6), then l of F, T (6).
+constexpr int FXW = 12;
+__device__ __forceinline__ void fx_split(float x, long long& h, long long& l) {
+    // fmaxf / fminf map NaN to a bound: the sweep flags a non-finite cell itself
+    const double xd = (double)fminf(fmaxf(x, -0x1p38f), 0x1p38f);
+    const double hd = rint(xd * 0x1p24);
+    h = (long long)hd;
+    l = (long long)rint((xd - hd * 0x1p-24) * 0x1p60);
+}
+__host__ __device__ inline double fx_value(long long h, long long l) {
+    return (double)h * 0x1p-24 + (double)l * 0x1p-60;
+}
 
 struct Ctl {
     StepCounters cnt[2];  // by step parity
@@ -183,14 +205,14 @@ struct Inst {
     int* recv;
     int* bnd;  // cells the bulk sweep leaves to the boundary sweep
     // Momentum-exchange partial sums of the boundary sweep, one record per
-    // workgroup of its grid (structure of arrays): the body the workgroup's
-    // first contributing wavefront met (-1: none) and F (3), T (3) in FP64
-    // at frec_v[q * BND_BLOCKS_MAX + block].  Contributions of the
-    // workgroup to any other body go to the FP64 accumulators by atomics.
-    // Records are summed in slot order, so with one body per workgroup the
-    // sums do not depend on scheduling.
-    int* frec_body;
-    double* frec_v;
+    // workgroup of its grid and body: bit b of frec_mask[block] says the
+    // workgroup met body b, whose fixed-point words (FXW of them, see
+    // fx_split) sit at frec_v[(b * FXW + q) * BND_BLOCKS_MAX + block].  (A
+    // cell touching two bodies at once adds to the second by integer atomics
+    // on StepCounters::facc; the pose checks keep bodies three cells apart,
+    // so none does.)
+    uint32_t* frec_mask;
+    long long* frec_v;
     // FP64 partial sums of the liquid-mass total, one per chunk of
     // MASS_CHUNK cells (mass_parts(N) of them)
     double* mass_part;

@@ -1210,6 +1210,33 @@ def _cubes_trace(lbm, dof, steps, every, heel0=2.86):
     return np.array(trace)
 
 
+@pytest.mark.parametrize("layout", [0, 1])
+def test_three_bodies_bit_reproducible(lbm, layout):
+    """Three free bodies in one lattice (the floating cubes, heave and roll,
+    boundary lists long enough for wavefronts and workgroups that meet two
+    boxes): the momentum exchange is summed per body in a fixed order (per
+    workgroup record and body, records in slot order), so two runs of 600
+    coupled steps give bit-identical forces, torques and poses, on either
+    boundary-sweep layout."""
+    L_ = with_layout(lbm, layout)
+    runs = []
+    for rep in range(2):
+        w = W.floating_cubes(dof=0x0C, heel0=10.0)
+        L = L_.Lattice(dict(w["lattice"], max_bodies=3))
+        for k, b in enumerate(w["bodies"]):
+            L.set_body(k, dict(b, dof=w["dof"]))
+        L.step(600)
+        out = []
+        for k in range(3):
+            F, T = L.body_forces(k)
+            bd = L.get_body(k)
+            out.append(np.concatenate([F, T, np.asarray(bd["pos"]), np.asarray(bd["quat"])]))
+        L.close()
+        runs.append(np.array(out))
+    say("  heels after 600 steps: %s" % [round(math.degrees(2 * math.atan2(r[10], r[9])), 3) for r in runs[0]])
+    assert np.array_equal(runs[0], runs[1]), np.abs(runs[0] - runs[1]).max()
+
+
 def test_floating_cubes_heave_roll_vs_oracle(lbm):
     """Three free cubes (densities 0.75, 0.5, 0.25) in one 130x40x40 basin,
     heave and roll, 3000 steps against the FP64 oracle's trajectory
