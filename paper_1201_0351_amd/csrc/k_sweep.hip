@@ -870,10 +870,26 @@ __device__ __forceinline__ void sweep_boundary1(const Inst& I, int parity, int w
             return (X | Y | Z) >= 0 ? X + nx * (Y + ny * Z) : -1;
         };
 
-        // the cell's own f_i(x, t) and its moments
+        // the cell's own f_i(x, t); then, for the sources s_i of links
+        // 1..18 (the cell itself beyond a wall), their types, incoming
+        // populations f_i(x - c_i) and fills, all issued before any is used
+        // so that the cell waits for one round trip, not one per link
         float dx[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) dx[i] = io.pop(i, id);
+        const float phr = io.fill(id);
+        const float mhr = I.m_hi[id], mlr = I.m_lo[id];
+        int sq[Q], eq[Q];
+        float pq[Q], fq[Q];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const int s = source(i);
+            const int sa = s >= 0 ? s : id;
+            sq[i] = s;
+            eq[i] = io.flag(sa);
+            pq[i] = io.pop(i, sa);
+            fq[i] = io.fill(sa);
+        }
         float drx = 0.f, jx0 = 0.f, jx1 = 0.f, jx2 = 0.f;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
@@ -885,8 +901,8 @@ __device__ __forceinline__ void sweep_boundary1(const Inst& I, int parity, int w
         const float rhox = 1.f + drx;
         const float ux0 = jx0 / rhox, ux1 = jx1 / rhox, ux2 = jx2 / rhox;
         const float uu = ux0 * ux0 + ux1 * ux1 + ux2 * ux2;
-        const float phix = ifc ? io.fill(id) : 1.f;
-        const float mhi0 = ifc ? I.m_hi[id] : 0.f, mlo0 = ifc ? I.m_lo[id] : 0.f;
+        const float phix = ifc ? phr : 1.f;
+        const float mhi0 = ifc ? mhr : 0.f, mlo0 = ifc ? mlr : 0.f;
 
         // interface normal n = -grad(phi) from the sources of links 1..6
         // (wall / obstacle: own fill), FP64 sign test
@@ -895,14 +911,12 @@ __device__ __forceinline__ void sweep_boundary1(const Inst& I, int parity, int w
             double f[7];
 #pragma unroll
             for (int i = 1; i <= 6; ++i) {
-                const int s = source(i);
-                const int e = s >= 0 ? io.flag(s) : -1;
-                const float fs = io.fill(s >= 0 ? s : id);  // issued with the type, used for interface sources
+                const int e = sq[i] >= 0 ? eq[i] : -1;
                 const int st = e & TYPE_MASK;
                 double v = (double)phix;
                 if (e >= 0 && st == LIQ) v = 1.0;
                 else if (e >= 0 && st == GAS) v = 0.0;
-                else if (e >= 0 && st == IFC) v = (double)fs;
+                else if (e >= 0 && st == IFC) v = (double)fq[i];
                 f[i] = v;
             }
             n0 = 0.5 * (f[2] - f[1]);
@@ -928,13 +942,9 @@ __device__ __forceinline__ void sweep_boundary1(const Inst& I, int parity, int w
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             const int o = opp(i);
-            const int s = source(i);
-            const int sa = s >= 0 ? s : id;
-            const int e = s >= 0 ? io.flag(sa) : -1;
-            const float dri = io.pop(i, sa);  // f_i(x - c_i)
-            // the source's fill, issued with its type (not after it) for an
-            // interface cell; used only when the source is an interface cell
-            const float fs = ifc ? io.fill(sa) : 0.f;
+            const int e = sq[i] >= 0 ? eq[i] : -1;
+            const float dri = pq[i];  // f_i(x - c_i)
+            const float fs = fq[i];   // used only when the source is an interface cell
             const int st = e & TYPE_MASK;
             const float dxo = dx[o];
             if (e >= 0 && st == LIQ) liq = 1;
@@ -1065,29 +1075,72 @@ __device__ __forceinline__ void sweep_boundary1(const Inst& I, int parity, int w
     force_record(I, wg, fsum);
 }
 
-// every array of the instance addressable with 32-bit byte offsets
-__host__ __device__ inline bool bnd_buf_fits(const Inst& I, size_t elem) {
-    return (size_t)Q * I.ps * elem <= 0xFFFFFFFFull && (size_t)I.N * 4 <= 0xFFFFFFFFull;
-}
-
-// one thread per cell; LGS_BND1_WAVES wavefronts per SIMD
+// one thread per cell; LGS_BND1_WAVES wavefronts per SIMD (two: the 18 sources of
+// a cell are loaded at once, which takes some 220 registers)
 #ifndef LGS_BND1_WAVES
-#define LGS_BND1_WAVES 3
+#define LGS_BND1_WAVES 2
 #endif
 template <typename S, bool W, bool BUF>
 __global__ __launch_bounds__(256, LGS_BND1_WAVES) void k_sweep_boundary1(Inst I, int parity) {
     sweep_boundary1<S, W, BUF>(I, parity, blockIdx.x, gridDim.x);
 }
 
-template <typename S>
-__global__ __launch_bounds__(256, LGS_BND1_WAVES) void kb_sweep_boundary1(const Inst* __restrict__ tab, const int* __restrict__ off,
-                                                          int n, int parity) {
-    const int k = batch_instance(off, n, blockIdx.x);
-    const Inst I = tab[k];
-    const int b = blockIdx.x - off[k];
-    if (b >= boundary_blocks(I)) return;  // padding of the grid to a multiple of 8
-    if (bnd_buf_fits(I, sizeof(S))) sweep_boundary1<S, true, true>(I, parity, b, boundary_blocks(I));
-    else sweep_boundary1<S, true, false>(I, parity, b, boundary_blocks(I));
+// Batched boundary sweep on a persistent grid.  A work item is one active
+// slot of one instance's boundary grid (slot s of instance k takes the list
+// cells, and writes the force record, that workgroup s of the instance's
+// own grid would); items are numbered in instance order and workgroup g
+// takes items g, g + G, ...  The list lengths are known only on the
+// device, so a grid of every instance's full boundary grid would launch
+// mostly workgroups without cells; this grid is sized to what the chip
+// holds at once and launches none.  body(k, s) runs one item; every thread
+// of the workgroup calls it with the same arguments.
+template <typename F>
+__device__ __forceinline__ void batch_items(const Inst* __restrict__ tab, int n, int parity, int per, F&& body) {
+    __shared__ int pre[256];
+    const int t = threadIdx.x;
+    int before = 0;  // items of the instances before this chunk of 256
+    for (int k0 = 0; k0 < n; k0 += 256) {
+        int a = 0;
+        if (k0 + t < n) {
+            const Inst& J = tab[k0 + t];
+            const int nlist = min(J.ctl->cnt[parity].n_bnd, J.list_cap);
+            a = min(boundary_blocks(J), (nlist + per - 1) / per);
+        }
+        __syncthreads();  // the last chunk's items have read pre
+        pre[t] = a;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {  // inclusive scan
+            const int v = t >= o ? pre[t - o] : 0;
+            __syncthreads();
+            pre[t] += v;
+            __syncthreads();
+        }
+        const int total = __builtin_amdgcn_readfirstlane(pre[255]);
+        const int G = (int)gridDim.x, g = (int)blockIdx.x;
+        for (int i = before + (g - before % G + G) % G; i < before + total; i += G) {
+            const int loc = i - before;
+            int lo = 0, hi = 255;  // first instance j of the chunk with pre[j] > loc
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (pre[mid] > loc) hi = mid;
+                else lo = mid + 1;
+            }
+            const int j = __builtin_amdgcn_readfirstlane(lo);
+            const int sl = __builtin_amdgcn_readfirstlane(loc - (j ? pre[j - 1] : 0));
+            __syncthreads();  // the last item's readers of the sweep's LDS are done
+            body(k0 + j, sl);
+        }
+        before += total;
+    }
+}
+
+// BUF: every instance of the batch addressable with 32-bit buffer offsets
+template <typename S, bool BUF>
+__global__ __launch_bounds__(256, LGS_BND1_WAVES) void kb_sweep_boundary1(const Inst* __restrict__ tab, int n, int parity) {
+    batch_items(tab, n, parity, 256, [&](int k, int sl) {
+        const Inst& I = tab[k];  // fields read from the table as needed
+        sweep_boundary1<S, true, BUF>(I, parity, sl, boundary_blocks(I));
+    });
 }
 
 template <typename S, bool W>
@@ -1096,13 +1149,11 @@ __global__ __launch_bounds__(256, 3) void k_sweep_boundary(Inst I, int parity) {
 }
 
 template <typename S>
-__global__ __launch_bounds__(256, 3) void kb_sweep_boundary(const Inst* __restrict__ tab, const int* __restrict__ off,
-                                                         int n, int parity) {
-    const int k = batch_instance(off, n, blockIdx.x);
-    const Inst I = tab[k];
-    const int b = blockIdx.x - off[k];
-    if (b >= boundary_blocks(I)) return;  // padding of the grid to a multiple of 8
-    sweep_boundary<S, true>(I, parity, b, boundary_blocks(I));
+__global__ __launch_bounds__(256, 3) void kb_sweep_boundary(const Inst* __restrict__ tab, int n, int parity) {
+    batch_items(tab, n, parity, BCELLS, [&](int k, int sl) {
+        const Inst& I = tab[k];  // fields read from the table as needed
+        sweep_boundary<S, true>(I, parity, sl, boundary_blocks(I));
+    });
 }
 
 // The sweep kernels go through the extended launch, which records the
@@ -1185,11 +1236,28 @@ void boundary_one(const Inst& I, int parity, int layout, hipStream_t s, hipEvent
     else if (layout) hipExtLaunchKernelGGL((k_sweep_boundary1<S, W, false>), g, b, 0, s, e0, e1, 0, I, parity);
     else hipExtLaunchKernelGGL((k_sweep_boundary<S, W>), g, b, 0, s, e0, e1, 0, I, parity);
 }
+
+// workgroups of the persistent batch boundary grid: what the chip holds at
+// once (one workgroup per CU per wavefront a SIMD keeps), at most one per
+// slot of the instances' grids
+int persistent_blocks(const BatchGrid& G, int per_cu) {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        ncu <= 0)
+        ncu = 256;
+    return std::max(1, std::min(G.blocks, ncu * per_cu));
+}
+
 template <typename S>
 void boundary_batch(const BatchGrid& G, int parity, int layout, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    const dim3 g(G.blocks), b(256);
-    if (layout) hipExtLaunchKernelGGL(kb_sweep_boundary1<S>, g, b, 0, s, e0, e1, 0, G.tab, G.off, G.n, parity);
-    else hipExtLaunchKernelGGL(kb_sweep_boundary<S>, g, b, 0, s, e0, e1, 0, G.tab, G.off, G.n, parity);
+    const dim3 b(256);
+    if (layout && G.buf_fits)
+        hipExtLaunchKernelGGL((kb_sweep_boundary1<S, true>), dim3(persistent_blocks(G, LGS_BND1_WAVES)), b, 0, s, e0, e1, 0, G.tab,
+                              G.n, parity);
+    else if (layout)
+        hipExtLaunchKernelGGL((kb_sweep_boundary1<S, false>), dim3(persistent_blocks(G, LGS_BND1_WAVES)), b, 0, s, e0, e1, 0, G.tab,
+                              G.n, parity);
+    else hipExtLaunchKernelGGL(kb_sweep_boundary<S>, dim3(persistent_blocks(G, 3)), b, 0, s, e0, e1, 0, G.tab, G.n, parity);
 }
 }  // namespace
 

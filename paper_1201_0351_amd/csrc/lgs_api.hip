@@ -243,6 +243,7 @@ struct lbm_ctx {
     int* d_bulk_off = nullptr;
     int* d_bnd_off = nullptr;
     int bulk_total = 0, bnd_total = 0;
+    bool bnd_fits = false;  // every instance addressable with 32-bit offsets
     // graph replay of two full steps (captured on a private stream)
     bool use_graph = false;
     hipStream_t cap_stream = nullptr;
@@ -287,6 +288,9 @@ static int upload_batch(lbm_ctx* c) {
     }
     c->bulk_total = bo[n];
     c->bnd_total = bb[n];
+    c->bnd_fits = true;
+    for (int k = 0; k < n; ++k)
+        c->bnd_fits = c->bnd_fits && bnd_buf_fits(tab[k], storage_bytes(c->inst[k].cfg.storage));
     HIP_OK(hipStreamSynchronize(c->stream));
     HIP_OK(hipMemcpy(c->d_tab, tab.data(), sizeof(Inst) * n, hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(c->d_bulk_off, bo.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
@@ -662,8 +666,8 @@ static int run_step_batched(lbm_ctx* c) {
     bool tension = false;
     for (int k = 0; k < n; ++k) tension |= c->inst[k].dev.lap != 0.f;
     if (tension) launch_curvature_batch(BatchGrid{c->d_tab, c->d_bnd_off, n, c->bnd_total}, p, c->stream);
-    launch_sweep_boundary_batch(BatchGrid{c->d_tab, c->d_bnd_off, n, c->bnd_total}, storage, p, c->bnd_layout, c->stream,
-                                e[2], e[3]);
+    launch_sweep_boundary_batch(BatchGrid{c->d_tab, c->d_bnd_off, n, c->bnd_total, c->bnd_fits}, storage, p, c->bnd_layout,
+                                c->stream, e[2], e[3]);
     for (int g = 0; g < n; g += 64) {
         const int ng = std::min(64, n - g);
         unsigned long long rm = 0, im = 0;
@@ -880,7 +884,7 @@ static int tune_boundary(lbm_ctx* c, int reps, hipEvent_t e0, hipEvent_t e1, dou
                                      hipMemcpyDeviceToDevice, c->stream);
         }
     };
-    const BatchGrid bnd{c->d_tab, c->d_bnd_off, n, c->bnd_total};
+    const BatchGrid bnd{c->d_tab, c->d_bnd_off, n, c->bnd_total, c->bnd_fits};
     auto boundary = [&](hipEvent_t a, hipEvent_t b) {
         if (c->batched) launch_sweep_boundary_batch(bnd, c->inst[0].cfg.storage, p, c->bnd_layout, c->stream, a, b);
         else

@@ -699,11 +699,18 @@ void launch_init(const Inst& I, const lbm_config& c, hipStream_t s);
 // first workgroup of its share of a grid (off[0..n], each share a multiple
 // of 8 workgroups so that a workgroup's XCD is its index modulo 8 in the
 // share as in the whole grid).
+// every array of the instance addressable with 32-bit byte offsets (elem:
+// bytes per stored population)
+__host__ __device__ inline bool bnd_buf_fits(const Inst& I, size_t elem) {
+    return (size_t)Q * I.ps * elem <= 0xFFFFFFFFull && (size_t)I.N * 4 <= 0xFFFFFFFFull;
+}
+
 struct BatchGrid {
     const Inst* tab;
     const int* off;
     int n;
-    int blocks;  // off[n]
+    int blocks;             // off[n]
+    bool buf_fits = false;  // every instance's arrays addressable with 32-bit offsets (boundary sweep)
 };
 
 // workgroups of one instance's bulk grid for a tile width (32, 64 or 128

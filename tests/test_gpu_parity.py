@@ -1000,10 +1000,12 @@ def test_surface_tension_batched_matches_single(lbm):
 
 def test_batched_instances_match_single(lbm):
     """A context of four instances steps all of them with one launch per
-    kernel (instance table, per-instance workgroup ranges).  Each instance
-    must advance as it does alone in its own context: held and free bodies,
-    device and host update, uneven sizes, FP32.  Populations and flags are
-    compared exactly for held bodies; free bodies to round-off."""
+    kernel (instance table, per-instance workgroup ranges, the boundary
+    sweep on a persistent grid over all instances' lists).  Each instance
+    must advance exactly as it does alone in its own context: held and free
+    bodies, device and host update, uneven sizes, FP32.  The momentum
+    exchange is an integer sum over the same per-cell terms, so free bodies
+    too match bit for bit."""
     cfgs = [W.basin((48, 40, 36), 18.0, 0.6, 1e-5, seed=21, noise_amp=1e-4),
             W.basin((64, 48, 40), 20.0, 0.55, 5e-6, seed=22, noise_amp=1e-4),
             W.basin((40, 40, 32), 16.0, 0.7, 1e-5, seed=23, noise_amp=1e-4),
@@ -1025,19 +1027,15 @@ def test_batched_instances_match_single(lbm):
     for S in singles:
         S.step(60)
     for k, S in enumerate(singles):
-        held = bodies[k] is None or bodies[k].get("fixed", 1) == 1
         assert np.array_equal(B.flags(k), S.flags(0)), k
-        if held:
-            assert np.array_equal(B.pop(k), S.pop(0)), k
-        else:
-            np.testing.assert_allclose(B.pop(k), S.pop(0), rtol=0, atol=1e-9)
-            bb, bs = B.get_body(0, inst=k), S.get_body(0)
-            np.testing.assert_allclose(bb["pos"], bs["pos"], rtol=0, atol=1e-9)
+        assert np.array_equal(B.pop(k), S.pop(0)), k
         if bodies[k] is not None:
+            bb, bs = B.get_body(0, inst=k), S.get_body(0)
+            for key in ("pos", "quat", "vel", "omega"):
+                assert np.array_equal(np.asarray(bb[key]), np.asarray(bs[key])), (k, key)
             Fb, Tb = B.body_forces(0, inst=k)
             Fs, Ts = S.body_forces(0)
-            assert_force_close(Fb, Fs, 1e-9, atol=1e-15)
-            assert_force_close(Tb, Ts, 1e-9, atol=1e-15)
+            assert np.array_equal(Fb, Fs) and np.array_equal(Tb, Ts), (k, Fb - Fs, Tb - Ts)
 
 
 def _graph_pair(lbm):
