@@ -7,13 +7,17 @@ staircase of mapped cells, so the lattice moment differs from the
 continuous one by a few percent at this resolution (32 x 16 cells of
 section); the bound below is the one the resolution study of the oracle
 shows, and the sign and the growth with heel are exact requirements."""
+import base64
 import json
 import math
 import os
+import zlib
 
+import numpy as np
 import pytest
 
 from oracle import analytic as A
+from paper_1201_0351_amd import workloads as W
 
 PATH = os.path.join(os.path.dirname(__file__), "golden", "righting_moment_128.json")
 
@@ -41,3 +45,42 @@ def test_golden_moments_match_closed_form():
 def test_golden_moments_grow_with_heel():
     ms = [r["m_s"] for r in _gold()["runs"]]
     assert ms[0] < ms[1] < ms[2]
+
+
+GAS, LIQ, IFC, OBS = 0, 1, 2, 3
+
+
+def unpack_types(s, shape):
+    """Cell types as the golden scripts store them: four 2-bit codes per byte, zlib, base64."""
+    p = np.frombuffer(zlib.decompress(base64.b64decode(s)), np.uint8)
+    t = np.stack([(p >> k) & 3 for k in (0, 2, 4, 6)], axis=1).ravel()
+    return t[: int(np.prod(shape))].reshape(shape)
+
+
+def test_golden_final_states_are_states_of_the_held_box():
+    """The stored end states (final_types, what the GPU comparison counts
+    diverged cells against): the obstacle cells are exactly the cells whose
+    centres lie inside the heeled cuboid (Sec. 2.4, cell-centre mapping, here
+    recomputed from the geometry alone), and no liquid cell has a gas cell
+    among its 18 neighbours (Sec. 2.2, the interface layer closes)."""
+    for r in _gold()["runs"]:
+        w = W.config2(r["heel_deg"], released=False)
+        lat, b = w["lattice"], w["bodies"][0]
+        nx, ny, nz = lat["nx"], lat["ny"], lat["nz"]
+        t = unpack_types(r["final_types"], (nz, ny, nx))
+        z, y, x = np.meshgrid(np.arange(nz) + 0.5, np.arange(ny) + 0.5, np.arange(nx) + 0.5, indexing="ij")
+        th = math.radians(r["heel_deg"])  # rotation about +x, body frame -> lattice
+        dy, dz = y - b["pos"][1], z - b["pos"][2]
+        ly, lz = math.cos(th) * dy + math.sin(th) * dz, -math.sin(th) * dy + math.cos(th) * dz
+        hx, hy, hz = b["half"]
+        inside = (np.abs(x - b["pos"][0]) < hx) & (np.abs(ly) < hy) & (np.abs(lz) < hz)
+        assert np.array_equal(t == OBS, inside), r["heel_deg"]
+        for cx in (-1, 0, 1):
+            for cy in (-1, 0, 1):
+                for cz in (-1, 0, 1):
+                    if abs(cx) + abs(cy) + abs(cz) in (0, 3):
+                        continue
+                    a = t[max(0, -cz):nz - max(0, cz), max(0, -cy):ny - max(0, cy), max(0, -cx):nx - max(0, cx)]
+                    c = t[max(0, cz):nz - max(0, -cz), max(0, cy):ny - max(0, -cy), max(0, cx):nx - max(0, -cx)]
+                    assert not np.any((a == LIQ) & (c == GAS)), (r["heel_deg"], cx, cy, cz)
+        assert 0 < int((t == IFC).sum()) < 2 * nx * ny  # a layer, not a region

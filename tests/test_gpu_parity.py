@@ -1128,12 +1128,28 @@ def test_autotune_keeps_state(lbm):
         assert np.array_equal(A.flags(k), B.flags(k)), k
 
 
+def _unpack_types(s, shape):
+    """Cell types as the golden scripts store them: four 2-bit codes per byte, zlib, base64."""
+    import base64
+    import zlib
+
+    p = np.frombuffer(zlib.decompress(base64.b64decode(s)), np.uint8)
+    t = np.stack([(p >> k) & 3 for k in (0, 2, 4, 6)], axis=1).ravel()
+    return t[: int(np.prod(shape))].reshape(shape)
+
+
 @pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
 def test_righting_moment_vs_oracle(lbm, storage):
     """The benchmark box held at 10, 20 and 30 deg on the 128^3 basin: the
     righting moment -T_x averaged over the last 1000 of 5000 steps (every 10
     steps) agrees with the FP64 oracle's (tests/golden/righting_moment_128.json)
-    within 1%, in FP32, FP16 and BF16 deviation storage."""
+    within 1%, in FP32, FP16 and BF16 deviation storage.  The cells whose type
+    differs from the oracle's at the end (conversions decided the other way
+    by round-off) are counted: none while the low deck edge stays over two
+    cells above the water (10, 20 deg), so the free surface ends cell for
+    cell as the oracle's; at 30 deg the edge lies a cell under the surface,
+    the film over it converts differently, and a fifth of the interface
+    cells end with another type while m_s still agrees."""
     import json
 
     with open(os.path.join(os.path.dirname(__file__), "golden", "righting_moment_128.json")) as f:
@@ -1148,11 +1164,20 @@ def test_righting_moment_vs_oracle(lbm, storage):
             done += run["every"]
             if done > run["steps"] - run["window"]:
                 samples.append(-L.body_forces(0)[1][0])
+        mism = int((L.types() != _unpack_types(run["final_types"], L.shape())).sum())
         L.close()
         ms = float(np.mean(samples))
         err = abs(ms - run["m_s"]) / abs(run["m_s"])
-        say("  %s heel %g: m_s %.6e oracle %.6e rel err %.2e" % (storage, run["heel_deg"], ms, run["m_s"], err))
+        say("  %s heel %g: m_s %.6e oracle %.6e rel err %.2e, cells of another type at the end %d"
+            % (storage, run["heel_deg"], ms, run["m_s"], err, mism))
         assert err <= 1e-2
+        # the low deck edge's height over the water plane (G on it), in cells
+        th = math.radians(run["heel_deg"])
+        edge = -16.0 * math.sin(th) + 8.0 * math.cos(th)
+        if edge > 2.0:
+            assert mism == 0  # measured: 0 at 10 and 20 deg in every storage
+        else:
+            assert mism <= 3500  # measured at 30 deg (edge 1.07 under): 2613 .. 2759 of some 15,000 interface cells
 
 
 @pytest.mark.parametrize("storage", ["fp32", "fp16"])
@@ -1181,12 +1206,14 @@ def test_batch48_righting_moment_vs_oracle(lbm, storage):
                 samples[k].append(-L.body_forces(0, inst=k)[1][0])
     L.sync()
     L.close()
+    errs = {}
     for r in gold["runs"]:
         ms = float(np.mean(samples[r["instance"]]))
-        err = abs(ms - r["m_s"]) / abs(r["m_s"])
+        errs[r["instance"]] = err = abs(ms - r["m_s"]) / abs(r["m_s"])
         say("  %s instance %d %s heel %.1f rho_s %.1f: m_s %.6e oracle %.6e rel err %.2e" % (
             storage, r["instance"], "x".join(map(str, r["shape"])), r["heel_deg"], r["density"], ms, r["m_s"], err))
-        assert err <= 1e-2
+    for k, err in errs.items():
+        assert err <= 1e-2, (k, err)
 
 
 def _cubes_trace(lbm, dof, steps, every, heel0=2.86):
