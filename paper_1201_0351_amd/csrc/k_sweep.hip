@@ -870,10 +870,12 @@ __device__ __forceinline__ void sweep_boundary1(const Inst& I, int parity, int w
             return (X | Y | Z) >= 0 ? X + nx * (Y + ny * Z) : -1;
         };
 
-        // the cell's own f_i(x, t); then, for the sources s_i of links
-        // 1..18 (the cell itself beyond a wall), their types, incoming
-        // populations f_i(x - c_i) and fills, all issued before any is used
-        // so that the cell waits for one round trip, not one per link
+        // the cell's own f_i(x, t); then, for the sources s_i (the cell
+        // itself beyond a wall), their types, incoming populations
+        // f_i(x - c_i) and fills: those of links 1..9 right away, those of
+        // 10..18 when links 1..9 are done.  Each half is issued before any
+        // of it is used (one round trip, not one per link), and only half
+        // of the sources' values are live at a time.
         float dx[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) dx[i] = io.pop(i, id);
@@ -881,15 +883,17 @@ __device__ __forceinline__ void sweep_boundary1(const Inst& I, int parity, int w
         const float mhr = I.m_hi[id], mlr = I.m_lo[id];
         int sq[Q], eq[Q];
         float pq[Q], fq[Q];
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
+        auto fetch = [&](int i) {
             const int s = source(i);
             const int sa = s >= 0 ? s : id;
             sq[i] = s;
             eq[i] = io.flag(sa);
             pq[i] = io.pop(i, sa);
             fq[i] = io.fill(sa);
-        }
+        };
+        constexpr int H1 = 9;  // links of the first half
+#pragma unroll
+        for (int i = 1; i <= H1; ++i) fetch(i);
         float drx = 0.f, jx0 = 0.f, jx1 = 0.f, jx2 = 0.f;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
@@ -941,6 +945,10 @@ __device__ __forceinline__ void sweep_boundary1(const Inst& I, int parity, int w
         const float xc0 = x + 0.5f, xc1 = y + 0.5f, xc2 = z + 0.5f;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
+            if (i == H1 + 1) {
+#pragma unroll
+                for (int i2 = H1 + 1; i2 < Q; ++i2) fetch(i2);
+            }
             const int o = opp(i);
             const int e = sq[i] >= 0 ? eq[i] : -1;
             const float dri = pq[i];  // f_i(x - c_i)
@@ -1075,10 +1083,11 @@ __device__ __forceinline__ void sweep_boundary1(const Inst& I, int parity, int w
     force_record(I, wg, fsum);
 }
 
-// one thread per cell; LGS_BND1_WAVES wavefronts per SIMD (two: the 18 sources of
-// a cell are loaded at once, which takes some 220 registers)
+// one thread per cell; LGS_BND1_WAVES wavefronts per SIMD (three: 168
+// registers, with the sources loaded in two halves; all 18 at once take
+// some 220, i.e. two wavefronts, too few slots for a long list in one round)
 #ifndef LGS_BND1_WAVES
-#define LGS_BND1_WAVES 2
+#define LGS_BND1_WAVES 3
 #endif
 template <typename S, bool W, bool BUF>
 __global__ __launch_bounds__(256, LGS_BND1_WAVES) void k_sweep_boundary1(Inst I, int parity) {
