@@ -121,6 +121,35 @@ __global__ __launch_bounds__(256) void k_init(Inst I, InitParams P) {
     phi_of(I, 0)[id] = phi_of(I, 1)[id] = (float)ph;
 }
 
+// Highest layer with a liquid or interface cell or a mark: each workgroup
+// scans a contiguous chunk of cells and adds one atomicMax.
+constexpr int ZTOP_CHUNK = 1 << 16;
+__global__ __launch_bounds__(256) void k_ztop(Inst I) {
+    const size_t c0 = (size_t)blockIdx.x * ZTOP_CHUNK;
+    const size_t c1 = c0 + ZTOP_CHUNK < (size_t)I.N ? c0 + ZTOP_CHUNK : (size_t)I.N;
+    const size_t layer = (size_t)I.nx * I.ny;
+    int top = -1;
+    for (size_t id = c0 + threadIdx.x; id < c1; id += 256) {
+        const uint8_t f = I.flags[id];
+        const int t = f & TYPE_MASK;
+        if (t == LIQ || t == IFC || (f & ~KEEP_MASK)) top = (int)(id / layer);  // ids ascend: the last is the highest
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) top = max(top, __shfl_xor(top, o));
+    __shared__ int wm[4];
+    if (__lane_id() == 0) wm[threadIdx.x >> 6] = top;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int m = max(max(wm[0], wm[1]), max(wm[2], wm[3]));
+        if (m >= 0) atomicMax(&I.ctl->ztop, m);
+    }
+}
+
+void launch_ztop(const Inst& I, hipStream_t s) {
+    const dim3 g((unsigned)(((size_t)I.N + ZTOP_CHUNK - 1) / ZTOP_CHUNK)), b(256);
+    hipLaunchKernelGGL(k_ztop, g, b, 0, s, I);
+}
+
 void launch_init(const Inst& I, const lbm_config& c, hipStream_t s) {
     InitParams P{c.fill_height, c.init_ux_surface, c.rho_gas, c.accel[2], c.noise_amp, c.seed};
     const dim3 g((I.N + 255) / 256), b(256);
@@ -289,6 +318,7 @@ __device__ __forceinline__ void remap_commit_cell(const Inst& I, int parity, int
     write_feq<S>(I, pop, id, rho, u);
     float hi, lo;
     double m;
+    atomicMax(&I.ctl->ztop, z);  // a fluid cell again
     if (r == 2) {
         I.flags[id] = LIQ;
         hi = 1.f;

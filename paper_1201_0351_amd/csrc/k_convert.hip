@@ -525,6 +525,7 @@ __device__ __forceinline__ void conv_commit(const Inst& I, int parity, int blk, 
             const int id = g ? I.newg[k - nc] : I.newl[k - nc - ng];
             I.flags[id] = IFC;
             unclaim_word(I.claim, id);
+            if (g) atomicMax(&I.ctl->ztop, id / (I.nx * I.ny));  // gas turned fluid
         }
         wave_count(f, &C.filled);
         wave_count(e, &C.emptied);

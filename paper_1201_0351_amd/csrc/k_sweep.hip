@@ -290,30 +290,23 @@ __device__ __forceinline__ bool bulk_cell(const Inst& I, const CollideConst& K, 
 
 // Workgroup b of nb (nb a multiple of 8, b % 8 the XCD it runs on) of one
 // instance's bulk grid.
-template <typename S, int TX, bool W, bool NT, bool PX>
-__device__ __forceinline__ void sweep_bulk(const Inst& I, const CollideConst& K, int parity, int b, int nb) {
-    // TX > 0: tiles of TX x (256 / TX) cells of a z-layer; TX = 0: 256
-    // consecutive cells of a z-layer (rows packed, wavefronts may cross a row
-    // end: every lane holds a cell when nx ny is a multiple of 256)
-    constexpr int TY = TX ? 256 / TX : 1;
-    const int tiles_x = TX ? (I.nx + TX - 1) / TX : (I.nx * I.ny + 255) / 256;
-    const int tiles_y = TX ? (I.ny + TY - 1) / TY : 1;
-    // XCD-aware tile order: workgroup b runs on XCD b % 8.  Whole z-layers
-    // (chunks of tiles_x * tiles_y tiles) go round-robin to the XCDs, so a
-    // layer's y-halo rows and flags stay in one L2 while liquid and gas layers
-    // spread evenly over all eight XCDs.
-    const int CH = tiles_x * tiles_y;
-    const int full = nb / (8 * CH) * (8 * CH);
-    int t = b;
-    if (b < full) {
-        const int xcd = b & 7, kk = b >> 3;
-        t = ((kk / CH) * 8 + xcd) * CH + kk % CH;
+// Tile c of layer z: TX > 0: TX x (256 / TX) cells; TX = 0: 256 consecutive
+// cells of the layer (rows packed, wavefronts may cross a row end: every
+// lane holds a cell when nx ny is a multiple of 256).
+template <int TX>
+struct BulkTiles {
+    static constexpr int TY = TX ? 256 / TX : 1;
+    int tiles_x, per_layer;
+    __device__ BulkTiles(const Inst& I) {
+        tiles_x = TX ? (I.nx + TX - 1) / TX : (I.nx * I.ny + 255) / 256;
+        per_layer = tiles_x * (TX ? (I.ny + TY - 1) / TY : 1);
     }
-    if (t >= CH * I.nz) return;  // padding of the grid to a multiple of 8
-    const int tx = t % tiles_x;
-    const int rest = t / tiles_x;
-    const int ty = rest % tiles_y;
-    const int z = rest / tiles_y;
+};
+
+template <typename S, int TX, bool W, bool NT, bool PX>
+__device__ __forceinline__ void bulk_tile(const Inst& I, const CollideConst& K, int parity, const BulkTiles<TX>& T,
+                                          int z, int c) {
+    const int tx = c % T.tiles_x, ty = c / T.tiles_x;
     int x, y;
     if constexpr (TX == 0) {
         const int off = tx * 256 + (int)threadIdx.x;
@@ -321,7 +314,7 @@ __device__ __forceinline__ void sweep_bulk(const Inst& I, const CollideConst& K,
         x = off - y * I.nx;
     } else {
         x = tx * TX + (threadIdx.x % TX);
-        y = ty * TY + (threadIdx.x / TX);
+        y = ty * BulkTiles<TX>::TY + (threadIdx.x / TX);
     }
 
     const S* __restrict__ src = (const S*)pop_of(I, parity);
@@ -344,6 +337,28 @@ __device__ __forceinline__ void sweep_bulk(const Inst& I, const CollideConst& K,
     bool defer = (type == IFC) || (type == LIQ && wall);
     if (type == LIQ && !wall) defer = bulk_cell<S, NT, PX>(I, K, src, dst, x, y, z, id, near);
     block_append<4>(defer, id, I.bnd, &C.n_bnd, I.list_cap, &C.overflow);
+}
+
+// Workgroup b of nb of an instance's bulk grid (one tile each).  XCD-aware
+// tile order: workgroup b runs on XCD b % 8.  Whole z-layers go round-robin
+// to the XCDs, so a layer's y-halo rows and flags stay in one L2 while liquid
+// and gas layers spread evenly over all eight XCDs.  Tiles above the highest
+// layer that may hold fluid (ctl->ztop) leave after one scalar load, without
+// touching their cells.
+template <typename S, int TX, bool W, bool NT, bool PX>
+__device__ __forceinline__ void sweep_bulk(const Inst& I, const CollideConst& K, int parity, int b, int nb) {
+    const BulkTiles<TX> T(I);
+    const int CH = T.per_layer;
+    const int full = nb / (8 * CH) * (8 * CH);
+    int t = b;
+    if (b < full) {
+        const int xcd = b & 7, kk = b >> 3;
+        t = ((kk / CH) * 8 + xcd) * CH + kk % CH;
+    }
+    if (t >= CH * I.nz) return;  // padding of the grid to a multiple of 8
+    const int z = t / CH;
+    if (z > I.ctl->ztop) return;  // gas (and bodies) only
+    bulk_tile<S, TX, W, NT, PX>(I, K, parity, T, z, t - z * CH);
 }
 
 // At most 64 VGPRs, so that eight wavefronts fit per SIMD.  W: the lattice
@@ -1168,6 +1183,15 @@ __global__ __launch_bounds__(256, 3) void kb_sweep_boundary(const Inst* __restri
 // The sweep kernels go through the extended launch, which records the
 // optional start / stop events with the dispatch itself (the kernel's own
 // execution, without separate marker packets).
+// compute units of the current device (256 if the query fails)
+int device_cus() {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        ncu <= 0)
+        ncu = 256;
+    return ncu;
+}
+
 int bulk_blocks(const Inst& I, int tile_x) {
     int n;
     if (tile_x == 0) {
@@ -1249,13 +1273,7 @@ void boundary_one(const Inst& I, int parity, int layout, hipStream_t s, hipEvent
 // workgroups of the persistent batch boundary grid: what the chip holds at
 // once (one workgroup per CU per wavefront a SIMD keeps), at most one per
 // slot of the instances' grids
-int persistent_blocks(const BatchGrid& G, int per_cu) {
-    int dev = 0, ncu = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        ncu <= 0)
-        ncu = 256;
-    return std::max(1, std::min(G.blocks, ncu * per_cu));
-}
+int persistent_blocks(const BatchGrid& G, int per_cu) { return std::max(1, std::min(G.blocks, device_cus() * per_cu)); }
 
 template <typename S>
 void boundary_batch(const BatchGrid& G, int parity, int layout, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {

@@ -390,6 +390,7 @@ int32_t lbm_create(const lbm_config* cfgs, int32_t n_inst, void* d_workspace, si
         HIP_OK(hipMemsetAsync(I.rule, 0, N, c->stream));
         HIP_OK(hipMemsetAsync(I.nearo, 0, N, c->stream));  // no bodies and a closed layer
         launch_init(I, h.cfg, c->stream);
+        launch_ztop(I, c->stream);
         HIP_OK(hipGetLastError());
     }
     // Bulk-sweep tiles of 256 consecutive cells of a layer: no idle lanes for
@@ -1333,6 +1334,10 @@ int32_t lbm_write_fields(lbm_ctx* c, int32_t inst, int32_t field, int32_t dtype,
             }
         }
         HIP_OK(hipMemcpy(I.flags, a.data(), N, hipMemcpyHostToDevice));
+        int ztop = 0;  // highest layer with a liquid or interface cell (the marks were dropped)
+        for (size_t k = 0; k < N; ++k)
+            if ((a[k] & TYPE_MASK) == LIQ || (a[k] & TYPE_MASK) == IFC) ztop = (int)(k / ((size_t)I.nx * I.ny));
+        HIP_OK(hipMemcpy(&I.ctl->ztop, &ztop, sizeof(int), hipMemcpyHostToDevice));
         const std::vector<uint8_t> nm = near_marks(I, a);
         HIP_OK(hipMemcpy(I.nearo, nm.data(), N, hipMemcpyHostToDevice));
         // the written obstacle cells are the bodies' mappings at their poses

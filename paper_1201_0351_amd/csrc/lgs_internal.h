@@ -131,6 +131,12 @@ struct Ctl {
     unsigned long long contacts;
     int nonfinite;
     int body_err;  // BODY_ERR_* bits of a rejected free-body update
+    // Highest z-layer that may hold a liquid or interface cell or a
+    // conversion mark: scanned after init, computed on the host when flags
+    // are written, raised by every step that turns a cell fluid (new
+    // interface cells from gas, refilled cells); never lowered by a step.
+    // The bulk sweep visits layers 0..ztop only.
+    int ztop;
 };
 
 // Reasons the device update of a free body was rejected (the body keeps its
@@ -695,6 +701,9 @@ __device__ __forceinline__ float g_bcastf(float v, int src) { return __shfl(v, g
 // kernel launchers (implemented in the .hip files)
 // --------------------------------------------------------------------------
 void launch_init(const Inst& I, const lbm_config& c, hipStream_t s);
+// raise ctl->ztop to the highest layer holding a liquid or interface cell or
+// a mark (ctl->ztop is zero after the workspace's clearing at creation)
+void launch_ztop(const Inst& I, hipStream_t s);
 // A batch: instance descriptors in device memory and, per instance, the
 // first workgroup of its share of a grid (off[0..n], each share a multiple
 // of 8 workgroups so that a workgroup's XCD is its index modulo 8 in the
