@@ -10,7 +10,14 @@ steps; the righting moment m_s = -T_x is averaged over the last 1000 steps
 (sampled every 10).  Only the oracle and the seeded workload generator are
 called.
 
+An instance whose low deck edge lies under the water plane by less than 1.5
+cells carries a thin film of liquid over the deck edge.  Conversions there
+turn on round-off, and m_s with them.  For such an instance --realisations N
+adds N more oracle runs from initial populations with noise of amplitude
+1e-7 (seeds 1..N) to an existing file, as the spread the oracle itself shows.
+
 Usage: python tests/golden/make_batch_righting.py [--threads 8]
+       python tests/golden/make_batch_righting.py --realisations 4 [--jobs 4]
 """
 import argparse
 import json
@@ -45,10 +52,25 @@ def chosen(insts):
     return picks
 
 
-def run(inst, threads):
+def deck_edge_depth(inst):
+    """Depth (cells) of the low deck edge under the water plane (negative:
+    above it) for the held box heeled about +x."""
+    c, b = inst["lattice"], inst["bodies"][0]
+    hy, hz = b["half"][1], b["half"][2]
+    th = math.radians(heel_of(inst))
+    edge = -hy * math.sin(th) + hz * math.cos(th)  # height over G
+    water = c["fill_height"] - b["pos"][2]  # water plane over G
+    return water - edge
+
+
+def thin_film(inst):
+    return 0.0 < deck_edge_depth(inst) < 1.5
+
+
+def run(inst, threads, seed=0, noise_amp=0.0):
     c, b = inst["lattice"], inst["bodies"][0]
     o = Oracle(c["nx"], c["ny"], c["nz"], c["tau"], accel=c["accel"], eps=c["eps"], threads=threads)
-    o.init_basin(c["fill_height"])
+    o.init_basin(c["fill_height"], seed=seed, noise_amp=noise_amp)
     o.set_body(0, b["half"], b["pos"], b["quat"], density=b["density"], fixed=1)
     samples, done, t0 = [], 0, time.time()
     while done < STEPS:
@@ -63,11 +85,41 @@ def run(inst, threads):
     return sum(samples) / len(samples)
 
 
+def _realisation(a):
+    k, seed, threads = a
+    return k, seed, run(W.config4()["instances"][k], threads, seed=seed, noise_amp=1e-7)
+
+
+def add_realisations(path, n, jobs, threads):
+    from concurrent.futures import ProcessPoolExecutor
+
+    with open(path) as f:
+        res = json.load(f)
+    insts = W.config4()["instances"]
+    work = [(r["instance"], seed, threads) for r in res["runs"] if thin_film(insts[r["instance"]])
+            for seed in range(1, n + 1)]
+    with ProcessPoolExecutor(jobs) as ex:
+        got = list(ex.map(_realisation, work))
+    for r in res["runs"]:
+        r["deck_edge_depth"] = deck_edge_depth(insts[r["instance"]])
+        mine = [m for k, _, m in sorted(got) if k == r["instance"]]
+        if mine:
+            r["m_s_noise_1e-7"] = mine
+    with open(path, "w") as f:
+        json.dump(res, f, indent=1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--threads", type=int, default=min(8, os.cpu_count() or 1))
     ap.add_argument("--out", type=str, default=os.path.join(HERE, "batch48_righting.json"))
+    ap.add_argument("--realisations", type=int, default=0)
+    ap.add_argument("--jobs", type=int, default=4)
     args = ap.parse_args()
+    if args.realisations:
+        add_realisations(args.out, args.realisations, args.jobs, args.threads)
+        print("wrote", args.out)
+        return
     insts = W.config4()["instances"]
     rows = []
     for k in chosen(insts):

@@ -49,3 +49,19 @@ def test_golden_batch_moments_match_closed_form():
         assert r["m_s"] > 0 and ana > 0
         bound = 0.20 if 2 * hy < 20 else 0.04
         assert abs(r["m_s"] - ana) / ana < bound, (r["instance"], r["m_s"], ana)
+
+
+def test_golden_batch_thin_film_realisations():
+    """Instances whose low deck edge lies less than 1.5 cells under the water
+    carry oracle runs from initial noise of 1e-7 (seeds 1..4), and those
+    spread by more than 1%: the reason such an instance is compared as an
+    ensemble on the GPU (measured: 3.9% for the 16 x 8 section at 29.6 deg).
+    The others are well clear of the waterline or deep under it."""
+    for r in _gold()["runs"]:
+        d = r["deck_edge_depth"]
+        if 0.0 < d < 1.5:
+            ens = [r["m_s"]] + r["m_s_noise_1e-7"]
+            assert len(ens) == 5
+            assert (max(ens) - min(ens)) / min(ens) > 0.01
+        else:
+            assert "m_s_noise_1e-7" not in r and abs(d) > 5.0

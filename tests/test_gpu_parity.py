@@ -1182,38 +1182,67 @@ def test_righting_moment_vs_oracle(lbm, storage):
 
 @pytest.mark.parametrize("storage", ["fp32", "fp16"])
 def test_batch48_righting_moment_vs_oracle(lbm, storage):
-    """The 48-instance heel sweep stepped as one batched context: for four of
-    its instances (the smallest, the largest, the furthest heeled and the
-    furthest heeled of density 0.7) the righting moment averaged over the
-    last 1000 of 3000 steps agrees with the FP64 oracle's run of that
-    instance alone (tests/golden/batch48_righting.json) within 1%."""
+    """The 48-instance heel sweep stepped as one batched context, against the
+    FP64 oracle's runs of four of its instances alone (the smallest, the
+    largest, the furthest heeled and the furthest heeled of density 0.7;
+    tests/golden/batch48_righting.json): the righting moment averaged over
+    the last 1000 of 3000 steps agrees within 1% (measured: 3e-7, 6e-7,
+    8e-4).  The smallest instance (a 16 x 8 section at 29.6 deg) has its low
+    deck edge 0.47 cells under the water: the thin film over it converts on
+    round-off, and the oracle's own m_s spreads by 4% over initial noise of
+    1e-7 (the golden holds those realisations).  There the GPU is compared as
+    an ensemble over the same seeded perturbations (the batch's run and the
+    instance alone from each noisy start): means within 3% (measured: 1.3%
+    FP32, 1.1% FP16), and every run within the oracle's range widened by its
+    width."""
     import json
 
     with open(os.path.join(os.path.dirname(__file__), "golden", "batch48_righting.json")) as f:
         gold = json.load(f)
     insts = W.config4(storage=storage)["instances"]
+
+    def window_mean(L, ks):
+        samples = {k: [] for k in ks}
+        done = 0
+        while done < gold["steps"]:
+            L.step(gold["every"])
+            done += gold["every"]
+            if done > gold["steps"] - gold["window"]:
+                for k in ks:
+                    samples[k].append(-L.body_forces(0, inst=ks[k])[1][0])
+        return {k: float(np.mean(v)) for k, v in samples.items()}
+
     L = lbm.Lattice([dict(i["lattice"], max_bodies=1) for i in insts])
     for k, i in enumerate(insts):
         L.set_body(0, i["bodies"][0], inst=k)
     L.set_tuning(batched=1)
-    samples = {r["instance"]: [] for r in gold["runs"]}
-    done = 0
-    while done < gold["steps"]:
-        L.step(gold["every"])
-        done += gold["every"]
-        if done > gold["steps"] - gold["window"]:
-            for k in samples:
-                samples[k].append(-L.body_forces(0, inst=k)[1][0])
+    got = window_mean(L, {r["instance"]: r["instance"] for r in gold["runs"]})
     L.sync()
     L.close()
-    errs = {}
+    fails = []
     for r in gold["runs"]:
-        ms = float(np.mean(samples[r["instance"]]))
-        errs[r["instance"]] = err = abs(ms - r["m_s"]) / abs(r["m_s"])
+        k, ms = r["instance"], got[r["instance"]]
+        err = abs(ms - r["m_s"]) / abs(r["m_s"])
         say("  %s instance %d %s heel %.1f rho_s %.1f: m_s %.6e oracle %.6e rel err %.2e" % (
-            storage, r["instance"], "x".join(map(str, r["shape"])), r["heel_deg"], r["density"], ms, r["m_s"], err))
-    for k, err in errs.items():
-        assert err <= 1e-2, (k, err)
+            storage, k, "x".join(map(str, r["shape"])), r["heel_deg"], r["density"], ms, r["m_s"], err))
+        if "m_s_noise_1e-7" not in r:
+            if err > 1e-2:
+                fails.append((k, err))
+            continue
+        ens = [ms]
+        for seed in range(1, len(r["m_s_noise_1e-7"]) + 1):
+            A = lbm.Lattice(dict(insts[k]["lattice"], max_bodies=1, seed=seed, noise_amp=1e-7))
+            A.set_body(0, insts[k]["bodies"][0])
+            ens.append(window_mean(A, {k: 0})[k])
+            A.close()
+        ora = [r["m_s"]] + r["m_s_noise_1e-7"]
+        lo, hi = min(ora), max(ora)
+        dm = abs(np.mean(ens) - np.mean(ora)) / np.mean(ora)
+        say("    thin film: GPU %s, oracle %s, means differ by %.2e" % (
+            ["%.4e" % v for v in ens], ["%.4e" % v for v in ora], dm))
+        if dm > 0.03 or min(ens) < lo - (hi - lo) or max(ens) > hi + (hi - lo):
+            fails.append((k, dm, min(ens), max(ens)))
+    assert not fails, fails
 
 
 def _cubes_trace(lbm, dof, steps, every, heel0=2.86):
