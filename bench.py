@@ -305,8 +305,14 @@ def batch_righting(storage):
     out = []
     for r in gold["runs"]:
         ms = sum(samples[r["instance"]]) / len(samples[r["instance"]])
-        out.append(dict(instance=r["instance"], shape=r["shape"], heel_deg=round(r["heel_deg"], 2), density=r["density"],
-                        m_s=ms, m_s_oracle=r["m_s"], rel_err=abs(ms - r["m_s"]) / abs(r["m_s"])))
+        row = dict(instance=r["instance"], shape=r["shape"], heel_deg=round(r["heel_deg"], 2), density=r["density"],
+                   m_s=ms, m_s_oracle=r["m_s"], rel_err=abs(ms - r["m_s"]) / abs(r["m_s"]))
+        if "m_s_noise_1e-7" in r:
+            # the low deck edge just under the water: the oracle's own m_s
+            # spreads over round-off-level noise (its runs from noisy starts)
+            ens = [r["m_s"]] + r["m_s_noise_1e-7"]
+            row.update(thin_film=True, oracle_range=[min(ens), max(ens)])
+        out.append(row)
     return out
 
 
@@ -391,8 +397,10 @@ def other_configs(steps, warmup):
         rt = batch_righting(st)
         if rt is not None:
             out["batch48_heel_sweep"][st]["righting_moment"] = dict(
-                runs=rt, max_rel_err=round(max(r["rel_err"] for r in rt), 5),
-                reference="FP64 oracle runs of four instances alone, tests/golden/batch48_righting.json")
+                runs=rt, max_rel_err=round(max(r["rel_err"] for r in rt if not r.get("thin_film")), 5),
+                reference="FP64 oracle runs of four instances alone, tests/golden/batch48_righting.json",
+                note="max_rel_err over the instances without a thin film over the deck edge; a thin-film "
+                     "instance lists the range of the oracle's runs from starts with 1e-7 noise")
     out["batch48_heel_sweep"]["fp32_one_launch_per_instance"] = run_batch("fp32", steps, warmup, batched=False)
     out["batch48_heel_sweep"]["fp32_graph"] = run_batch("fp32", steps, warmup, graph=True)
     return out

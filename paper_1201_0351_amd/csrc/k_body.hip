@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void k_init(Inst I, InitParams P) {
 
 // Highest layer with a liquid or interface cell or a mark: each workgroup
 // scans a contiguous chunk of cells and adds one atomicMax.
-constexpr int ZTOP_CHUNK = 1 << 16;
+constexpr int ZTOP_CHUNK = 1 << 12;
 __global__ __launch_bounds__(256) void k_ztop(Inst I) {
     const size_t c0 = (size_t)blockIdx.x * ZTOP_CHUNK;
     const size_t c1 = c0 + ZTOP_CHUNK < (size_t)I.N ? c0 + ZTOP_CHUNK : (size_t)I.N;
