@@ -14,10 +14,6 @@
 //           bitmap, so every new cell is listed once.  A stranded interface
 //           cell (no liquid neighbour, and no interface neighbour that has
 //           one) empties as well, unless a neighbour fills.
-//           The last workgroup of the grid instead sums the boundary sweep's
-//           per-workgroup momentum-exchange records per body in slot order
-//           (fixed-order FP64 reduction), retires the step's body moves and
-//           gives free bodies the rigid-body update.
 //   middle  (one group per new cell from gas) f = f_eq(mean rho, mean u) over
 //           its neighbours that are liquid or interface and not emptying,
 //           m = 0; (one thread per new cell from liquid) m = rho, phi = 1;
@@ -25,7 +21,10 @@
 //           interface after the conversion (a function of the flags, marks
 //           and claims), divide the excess among them and note this cell in
 //           each receiver's link mask; with none the excess leaves the fluid
-//           (ledger).
+//           (ledger).  The last workgroup of the grid instead sums the
+//           boundary sweep's momentum-exchange records per body (fixed-point
+//           integer sums), retires the step's body moves and gives free
+//           bodies the rigid-body update; no conversion reads the bodies.
 //   commit  converted and new cells take their new types; receivers add the
 //           shares of their converted neighbours in link order i = 1..18 and
 //           recompute phi = m / rho.  Converted cells keep their mark until
@@ -343,17 +342,12 @@ __device__ __forceinline__ void forces_and_bodies(const Inst& I, int parity, boo
 // instance's grid
 // ---------------------------------------------------------------------------
 template <typename S>
-__device__ __forceinline__ void conv_claim(const Inst& I, int parity, int blk, int nblk, bool retire_moves,
-                                           bool integrate) {
-    if (blk == nblk - 1) {
-        forces_and_bodies(I, parity, true, retire_moves, integrate);
-        return;
-    }
+__device__ __forceinline__ void conv_claim(const Inst& I, int parity, int blk, int nblk) {
     StepCounters& C = I.ctl->cnt[parity];
     const int n = list_len(&C.n_cand, I.list_cap);
     const int ns = list_len(&C.n_strd, I.list_cap);
     const int i = g_lane();
-    const int ng = (nblk - 1) * CG;
+    const int ng = nblk * CG;
     for (int k = blk * CG + (int)(threadIdx.x >> 5); k < n + ns; k += ng) {
         if (k >= n) {
             // a stranded candidate (no liquid neighbour, no mark): it empties
@@ -402,8 +396,17 @@ __device__ __forceinline__ void conv_claim(const Inst& I, int parity, int blk, i
     }
 }
 
+// The last workgroup of the middle launch sums the boundary sweep's force
+// records and updates the bodies (nothing in this launch or the next reads
+// them); the others share the conversions.
 template <typename S>
-__device__ __forceinline__ void conv_middle(const Inst& I, int parity, int blk, int nblk) {
+__device__ __forceinline__ void conv_middle(const Inst& I, int parity, int blk, int nblk_all, bool retire_moves,
+                                            bool integrate) {
+    if (blk == nblk_all - 1) {
+        forces_and_bodies(I, parity, true, retire_moves, integrate);
+        return;
+    }
+    const int nblk = nblk_all - 1;
     StepCounters& C = I.ctl->cnt[parity];
     S* pop = (S*)pop_of(I, parity ^ 1);
     float* phi = phi_of(I, parity ^ 1);
@@ -564,12 +567,12 @@ __device__ __forceinline__ void conv_commit(const Inst& I, int parity, int blk, 
 
 // one instance
 template <typename S>
-__global__ __launch_bounds__(CT) void k_conv_claim(Inst I, int parity, int retire_moves, int integrate) {
-    conv_claim<S>(I, parity, blockIdx.x, gridDim.x, retire_moves != 0, integrate != 0);
+__global__ __launch_bounds__(CT) void k_conv_claim(Inst I, int parity) {
+    conv_claim<S>(I, parity, blockIdx.x, gridDim.x);
 }
 template <typename S>
-__global__ __launch_bounds__(CT) void k_conv_middle(Inst I, int parity) {
-    conv_middle<S>(I, parity, blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(CT) void k_conv_middle(Inst I, int parity, int retire_moves, int integrate) {
+    conv_middle<S>(I, parity, blockIdx.x, gridDim.x, retire_moves != 0, integrate != 0);
 }
 template <typename S>
 __global__ __launch_bounds__(CT) void k_conv_commit(Inst I, int parity) {
@@ -580,20 +583,20 @@ __global__ __launch_bounds__(CT) void k_conv_commit(Inst I, int parity) {
 // masks), blockIdx.x the workgroup of its grid (grids of other sizes: the
 // extra workgroups return)
 template <typename S>
-__global__ __launch_bounds__(CT) void kb_conv_claim(const Inst* __restrict__ tab, int parity,
-                                                    unsigned long long retire_mask, unsigned long long integrate_mask) {
+__global__ __launch_bounds__(CT) void kb_conv_claim(const Inst* __restrict__ tab, int parity) {
+    const Inst I = tab[blockIdx.y];
+    const int nb = conv_blocks(I);
+    if ((int)blockIdx.x >= nb) return;
+    conv_claim<S>(I, parity, blockIdx.x, nb);
+}
+template <typename S>
+__global__ __launch_bounds__(CT) void kb_conv_middle(const Inst* __restrict__ tab, int parity,
+                                                     unsigned long long retire_mask, unsigned long long integrate_mask) {
     const int k = blockIdx.y;
     const Inst I = tab[k];
     const int nb = conv_blocks(I);
     if ((int)blockIdx.x >= nb) return;
-    conv_claim<S>(I, parity, blockIdx.x, nb, (retire_mask >> k) & 1ull, (integrate_mask >> k) & 1ull);
-}
-template <typename S>
-__global__ __launch_bounds__(CT) void kb_conv_middle(const Inst* __restrict__ tab, int parity) {
-    const Inst I = tab[blockIdx.y];
-    const int nb = conv_blocks(I);
-    if ((int)blockIdx.x >= nb) return;
-    conv_middle<S>(I, parity, blockIdx.x, nb);
+    conv_middle<S>(I, parity, blockIdx.x, nb, (retire_mask >> k) & 1ull, (integrate_mask >> k) & 1ull);
 }
 template <typename S>
 __global__ __launch_bounds__(CT) void kb_conv_commit(const Inst* __restrict__ tab, int parity) {
@@ -613,16 +616,16 @@ namespace {
 template <typename S>
 void convert_one(const Inst& I, int parity, int r, int n, hipStream_t s) {
     const dim3 g(conv_blocks(I)), b(CT);
-    hipLaunchKernelGGL(k_conv_claim<S>, g, b, 0, s, I, parity, r, n);
-    hipLaunchKernelGGL(k_conv_middle<S>, g, b, 0, s, I, parity);
+    hipLaunchKernelGGL(k_conv_claim<S>, g, b, 0, s, I, parity);
+    hipLaunchKernelGGL(k_conv_middle<S>, g, b, 0, s, I, parity, r, n);
     hipLaunchKernelGGL(k_conv_commit<S>, g, b, 0, s, I, parity);
 }
 template <typename S>
 void convert_batch(const Inst* tab, int n, int blocks, int parity, unsigned long long rm, unsigned long long im,
                    hipStream_t s) {
     const dim3 g(blocks, n), b(CT);
-    hipLaunchKernelGGL(kb_conv_claim<S>, g, b, 0, s, tab, parity, rm, im);
-    hipLaunchKernelGGL(kb_conv_middle<S>, g, b, 0, s, tab, parity);
+    hipLaunchKernelGGL(kb_conv_claim<S>, g, b, 0, s, tab, parity);
+    hipLaunchKernelGGL(kb_conv_middle<S>, g, b, 0, s, tab, parity, rm, im);
     hipLaunchKernelGGL(kb_conv_commit<S>, g, b, 0, s, tab, parity);
 }
 }  // namespace
