@@ -414,54 +414,33 @@ __device__ __forceinline__ bool active_workgroup(StepCounters& C, int wg, int nw
 }
 
 // Momentum exchange per boundary workgroup and body, in fixed point
-// (fx_split): each pass's lane terms are summed per body over the wavefront
-// into the wavefront's slot in LDS, and at the end the slots into the
-// workgroup's record of each body it met.  Every sum is an integer sum.
+// (fx_split): every lane whose cell met a body adds its terms to the
+// workgroup's slot of that body in LDS with integer atomics, and at the end
+// the slots go to the workgroup's records.  Integer sums do not depend on the
+// order of the additions.
 struct ForceLDS {
-    long long v[4][MAXB][FXW];
-    uint32_t mask[4];
+    unsigned long long v[MAXB][FXW];
+    uint32_t mask;
 };
 
-__device__ __forceinline__ long long wave_sum_i(long long v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
-// every wavefront clears its own slot
+// clear the slots (every thread calls it; a barrier follows before use)
 __device__ __forceinline__ void force_begin(ForceLDS& F) {
-    const int w = threadIdx.x >> 6, l = lane_id();
-    long long* v = &F.v[w][0][0];
-    for (int k = l; k < MAXB * FXW; k += 64) v[k] = 0;
-    if (l == 0) F.mask[w] = 0u;
+    unsigned long long* v = &F.v[0][0];
+    for (int k = threadIdx.x; k < MAXB * FXW; k += blockDim.x) v[k] = 0ull;
+    if (threadIdx.x == 0) F.mask = 0u;
 }
 
-// one pass: lane terms cv (force, torque) on body `body` (-1: none); every
-// lane of the wavefront calls it
+// one pass: this lane's terms cv (force, torque) on body `body` (-1: none)
 __device__ __forceinline__ void force_flush(ForceLDS& F, int body, const float (&cv)[6]) {
-    const int w = threadIdx.x >> 6;
-    unsigned long long m = __ballot(body >= 0);
-    if (!m) return;
-    long long h[6], l[6];
+    if (body < 0) return;
 #pragma unroll
-    for (int q = 0; q < 6; ++q) fx_split(cv[q], h[q], l[q]);
-    while (m) {
-        const int leader = __ffsll((long long)m) - 1;
-        const int b = __shfl(body, leader);
-        const bool mine = body == b;
-        long long v[FXW];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            v[q] = wave_sum_i(mine ? h[q] : 0);
-            v[6 + q] = wave_sum_i(mine ? l[q] : 0);
-        }
-        if (lane_id() == 0) {
-#pragma unroll
-            for (int q = 0; q < FXW; ++q) F.v[w][b][q] += v[q];
-            F.mask[w] |= 1u << b;
-        }
-        m &= ~__ballot(mine);
+    for (int q = 0; q < 6; ++q) {
+        long long h, l;
+        fx_split(cv[q], h, l);
+        atomicAdd(&F.v[body][q], (unsigned long long)h);
+        atomicAdd(&F.v[body][6 + q], (unsigned long long)l);
     }
+    atomicOr(&F.mask, 1u << body);
 }
 
 // a term on a second body of one cell: integer atomics on the step's sums
@@ -479,12 +458,11 @@ __device__ __forceinline__ void force_atomic(StepCounters& C, int b, const float
 // the workgroup's records (every thread calls it)
 __device__ __forceinline__ void force_record(const Inst& I, int wg, ForceLDS& F) {
     __syncthreads();
-    const uint32_t mask = F.mask[0] | F.mask[1] | F.mask[2] | F.mask[3];
+    const uint32_t mask = F.mask;
     const int t = threadIdx.x;
     if (t < MAXB * FXW) {
         const int b = t / FXW, q = t % FXW;
-        if ((mask >> b) & 1u)
-            I.frec_v[(b * FXW + q) * BND_BLOCKS_MAX + wg] = F.v[0][b][q] + F.v[1][b][q] + F.v[2][b][q] + F.v[3][b][q];
+        if ((mask >> b) & 1u) I.frec_v[(b * FXW + q) * BND_BLOCKS_MAX + wg] = (long long)F.v[b][q];
     }
     if (t == 0) I.frec_mask[wg] = mask;
 }
