@@ -684,7 +684,7 @@ def main():
         print(json.dumps(free_advection(steps=args.steps, window=max(100, args.steps // 4))))
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the workload is a single-GPU lattice); "
+        print("bench.py: the benchmark runs on one GPU (its workload is one lattice on one device); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
     from paper_1201_0351_amd import workloads as W
