@@ -1063,6 +1063,42 @@ def test_batched_instances_match_single(lbm):
             assert np.array_equal(Fb, Fs) and np.array_equal(Tb, Ts), (k, Fb - Fs, Tb - Ts)
 
 
+def test_long_boundary_list_takes_second_passes(lbm):
+    """A free surface of 576 x 576 cells lists some 330,000 cells for the
+    boundary sweep, more than one pass of the one-thread layout's grid (1024
+    workgroups of 256 threads): workgroups take a second pass and add both to
+    their force record.  A held box heeled 10 deg meets the surface.  One-
+    thread layout against the oracle over 3 steps (populations 1e-5, flags
+    exact, force and torque 1e-3), and the same lattice inside a batch (the
+    persistent grid walks the same slots and passes) bit-identical to it."""
+    cfg = W.basin((576, 576, 16), 8.3, 0.6, 1e-5, seed=5, noise_amp=1e-4)
+    body = W.box((40, 16, 4), (288.0, 288.0, 8.3), 10.0, 0.5)  # reaches z 4.9 .. 11.7
+    L1 = with_layout(lbm, 1)
+    L, o = pair(L1, cfg, bodies=[body])
+    B = L1.Lattice([dict(cfg, max_bodies=1), dict(W.basin((48, 40, 36), 18.0, 0.6, 1e-5), max_bodies=1)])
+    B.set_body(0, body, inst=0)
+    B.set_tuning(batched=1)
+    say("long boundary list: 576x576x16, held box")
+    for n in (1, 2):
+        L.step(n)
+        o.step(n)
+        B.step(n)
+        nb = L.boundary_cells()
+        say("  listed cells %d (one pass holds %d)" % (nb, 1024 * 256))
+        assert nb > 1024 * 256
+        compare_pop(L, o, 1e-5, label="long list +%d" % n)
+        assert np.array_equal(L.flags(), o.get_flags())
+        F, T = L.body_forces(0)
+        Fo, To = o.body_forces(0)
+        assert_force_close(F, Fo, 1e-3)
+        assert_force_close(T, To, 1e-3)
+        assert np.array_equal(B.pop(0), L.pop(0)) and np.array_equal(B.flags(0), L.flags(0))
+        Fb, Tb = B.body_forces(0, inst=0)
+        assert np.array_equal(Fb, F) and np.array_equal(Tb, T)
+    L.close()
+    B.close()
+
+
 def _graph_pair(lbm):
     cfgs = [W.basin((48, 40, 36), 18.0, 0.6, 1e-5, seed=31, noise_amp=1e-4),
             W.basin((40, 48, 40), 20.0, 0.6, 1e-5, seed=32, noise_amp=1e-4)]
