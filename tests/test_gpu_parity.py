@@ -1099,6 +1099,34 @@ def test_long_boundary_list_takes_second_passes(lbm):
     B.close()
 
 
+@pytest.mark.parametrize("layout", [0, 1])
+def test_sixteen_bodies_in_one_lattice(lbm, layout):
+    """The most bodies a lattice takes (16): held boxes on a 4 x 4 grid in one
+    basin, heeled 0-15 deg, every third spinning about x (rotating wall
+    velocity per body), so that every bit of the force records' body mask and
+    every body's fixed-point slot is used.  5 steps against the oracle:
+    flags exact, populations 1e-5, each body's force and torque 1e-3."""
+    cfg = W.basin((96, 96, 24), 12.0, 0.6, 1e-5, seed=9, noise_amp=1e-4)
+    bodies = []
+    for k in range(16):
+        b = W.box((8, 8, 4), (15.0 + 22.0 * (k % 4), 15.0 + 22.0 * (k // 4), 12.0), 5.0 * (k % 4), 0.5)
+        if k % 3 == 0:
+            b["omega"] = (0.002, 0.0, 0.0)
+        bodies.append(b)
+    L, o = pair(with_layout(lbm, layout), cfg, bodies=bodies)
+    say("16 held bodies, layout %d" % layout)
+    L.step(5)
+    o.step(5)
+    compare_pop(L, o, 1e-5, label="16 bodies")
+    assert np.array_equal(L.flags(), o.get_flags())
+    for k in range(16):
+        F, T = L.body_forces(k)
+        Fo, To = o.body_forces(k)
+        assert_force_close(F, Fo, 1e-3)
+        assert_force_close(T, To, 1e-3)
+    L.close()
+
+
 def _graph_pair(lbm):
     cfgs = [W.basin((48, 40, 36), 18.0, 0.6, 1e-5, seed=31, noise_amp=1e-4),
             W.basin((40, 48, 40), 20.0, 0.6, 1e-5, seed=32, noise_amp=1e-4)]
