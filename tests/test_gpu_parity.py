@@ -1127,6 +1127,33 @@ def test_sixteen_bodies_in_one_lattice(lbm, layout):
     L.close()
 
 
+def test_bodies_closer_than_three_cells_rejected(lbm):
+    """Bodies must be at least three cells apart along some axis (their
+    half-extents plus 3), so that no fluid cell has links into two bodies:
+    the per-lane momentum-exchange term carries one body (the integer atomics
+    for a second body are a guard that this rule leaves unused).  Boxes 8
+    wide: centres 10 cells apart are refused, 11 accepted, and the accepted
+    pair steps as the oracle does (each body's force and torque 1e-3)."""
+    cfg = W.basin((48, 32, 24), 12.0, 0.6, 1e-5, seed=13, noise_amp=1e-4)
+    b0 = W.box((8, 8, 6), (19.0, 16.0, 12.0), 0.0, 0.5)
+    L = lbm.Lattice(dict(cfg, max_bodies=2))
+    L.set_body(0, b0)
+    with pytest.raises(lbm.LBMError, match="three cells apart"):
+        L.set_body(1, W.box((8, 8, 6), (29.0, 16.0, 12.0), 0.0, 0.5))
+    L.close()
+    b1 = dict(W.box((8, 8, 6), (30.0, 16.0, 12.0), 0.0, 0.5), omega=(0.0, 0.0, 0.002))
+    L, o = pair(lbm, cfg, bodies=[b0, b1])
+    L.step(5)
+    o.step(5)
+    assert np.array_equal(L.flags(), o.get_flags())
+    for k in range(2):
+        F, T = L.body_forces(k)
+        Fo, To = o.body_forces(k)
+        assert_force_close(F, Fo, 1e-3)
+        assert_force_close(T, To, 1e-3)
+    L.close()
+
+
 def _graph_pair(lbm):
     cfgs = [W.basin((48, 40, 36), 18.0, 0.6, 1e-5, seed=31, noise_amp=1e-4),
             W.basin((40, 48, 40), 20.0, 0.6, 1e-5, seed=32, noise_amp=1e-4)]
