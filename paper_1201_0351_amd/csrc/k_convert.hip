@@ -342,7 +342,11 @@ __device__ __forceinline__ void forces_and_bodies(const Inst& I, int parity, boo
 // instance's grid
 // ---------------------------------------------------------------------------
 template <typename S>
-__device__ __forceinline__ void conv_claim(const Inst& I, int parity, int blk, int nblk) {
+__device__ __forceinline__ void conv_claim(const Inst& I, int parity, int blk, int nblk, int bulk_layers = 0) {
+    // a bulk grid cut to bulk_layers layers must have covered every layer up
+    // to ztop (the sweeps raise no layer; the remap before them already did)
+    if (blk == 0 && threadIdx.x == 0 && bulk_layers > 0 && I.ctl->ztop >= bulk_layers)
+        atomicOr(&I.ctl->nonfinite, NONFINITE_LAYERS);
     StepCounters& C = I.ctl->cnt[parity];
     const int n = list_len(&C.n_cand, I.list_cap);
     const int ns = list_len(&C.n_strd, I.list_cap);
@@ -494,7 +498,7 @@ __device__ __forceinline__ void conv_middle(const Inst& I, int parity, int blk, 
 }
 
 template <typename S>
-__device__ __forceinline__ void conv_commit(const Inst& I, int parity, int blk, int nblk) {
+__device__ __forceinline__ void conv_commit(const Inst& I, int parity, int blk, int nblk, unsigned step_tag) {
     StepCounters& C = I.ctl->cnt[parity];
     const int nc = cand_len(C, I.list_cap), ng = list_len(&C.n_newg, I.list_cap);
     const int nl = list_len(&C.n_newl, I.list_cap), nr = list_len(&C.n_recv, I.list_cap);
@@ -561,22 +565,29 @@ __device__ __forceinline__ void conv_commit(const Inst& I, int parity, int blk, 
         I.cmask[id] = 0u;
     }
     if (blk == 0) clear_other(I, parity, threadIdx.x, CT);
+    // report the layer bound with the step's index (one 64-bit store to the
+    // pinned host word; read in this launch, the bound may miss this launch's
+    // own raises, which later steps' bounds allow for)
+    if (blk == 0 && threadIdx.x == 0 && step_tag != NO_STEP_TAG && I.zpin) {
+        const unsigned zt = (unsigned)__atomic_load_n(&I.ctl->ztop, __ATOMIC_RELAXED);
+        *(volatile unsigned long long*)I.zpin = ((unsigned long long)step_tag << 32) | zt;
+    }
 }
 
 }  // namespace
 
 // one instance
 template <typename S>
-__global__ __launch_bounds__(CT) void k_conv_claim(Inst I, int parity) {
-    conv_claim<S>(I, parity, blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(CT) void k_conv_claim(Inst I, int parity, int bulk_layers) {
+    conv_claim<S>(I, parity, blockIdx.x, gridDim.x, bulk_layers);
 }
 template <typename S>
 __global__ __launch_bounds__(CT) void k_conv_middle(Inst I, int parity, int retire_moves, int integrate) {
     conv_middle<S>(I, parity, blockIdx.x, gridDim.x, retire_moves != 0, integrate != 0);
 }
 template <typename S>
-__global__ __launch_bounds__(CT) void k_conv_commit(Inst I, int parity) {
-    conv_commit<S>(I, parity, blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(CT) void k_conv_commit(Inst I, int parity, unsigned step_tag) {
+    conv_commit<S>(I, parity, blockIdx.x, gridDim.x, step_tag);
 }
 
 // a batch of at most 64 instances: blockIdx.y is the instance (bit y of the
@@ -603,7 +614,7 @@ __global__ __launch_bounds__(CT) void kb_conv_commit(const Inst* __restrict__ ta
     const Inst I = tab[blockIdx.y];
     const int nb = conv_blocks(I);
     if ((int)blockIdx.x >= nb) return;
-    conv_commit<S>(I, parity, blockIdx.x, nb);
+    conv_commit<S>(I, parity, blockIdx.x, nb, NO_STEP_TAG);
 }
 
 // End of a step without conversions (phase-isolated calls).
@@ -614,11 +625,11 @@ __global__ __launch_bounds__(CT) void k_finish(Inst I, int parity, int reduce, i
 
 namespace {
 template <typename S>
-void convert_one(const Inst& I, int parity, int r, int n, hipStream_t s) {
+void convert_one(const Inst& I, int parity, int r, int n, hipStream_t s, unsigned step_tag, int bulk_layers) {
     const dim3 g(conv_blocks(I)), b(CT);
-    hipLaunchKernelGGL(k_conv_claim<S>, g, b, 0, s, I, parity);
+    hipLaunchKernelGGL(k_conv_claim<S>, g, b, 0, s, I, parity, bulk_layers);
     hipLaunchKernelGGL(k_conv_middle<S>, g, b, 0, s, I, parity, r, n);
-    hipLaunchKernelGGL(k_conv_commit<S>, g, b, 0, s, I, parity);
+    hipLaunchKernelGGL(k_conv_commit<S>, g, b, 0, s, I, parity, step_tag);
 }
 template <typename S>
 void convert_batch(const Inst* tab, int n, int blocks, int parity, unsigned long long rm, unsigned long long im,
@@ -639,12 +650,13 @@ void launch_convert_batch(const Inst* tab, int n, int blocks, int storage, int p
     }
 }
 
-void launch_convert(const Inst& I, int parity, bool retire_moves, bool integrate, hipStream_t s) {
+void launch_convert(const Inst& I, int parity, bool retire_moves, bool integrate, hipStream_t s, unsigned step_tag,
+                    int bulk_layers) {
     const int r = (int)retire_moves, n = (int)integrate;
     switch (I.storage) {
-    case LBM_FP16_DEV: convert_one<__half>(I, parity, r, n, s); break;
-    case LBM_BF16_DEV: convert_one<__hip_bfloat16>(I, parity, r, n, s); break;
-    default: convert_one<float>(I, parity, r, n, s); break;
+    case LBM_FP16_DEV: convert_one<__half>(I, parity, r, n, s, step_tag, bulk_layers); break;
+    case LBM_BF16_DEV: convert_one<__hip_bfloat16>(I, parity, r, n, s, step_tag, bulk_layers); break;
+    default: convert_one<float>(I, parity, r, n, s, step_tag, bulk_layers); break;
     }
 }
 

@@ -1170,21 +1170,22 @@ int device_cus() {
     return ncu;
 }
 
-int bulk_blocks(const Inst& I, int tile_x) {
+int bulk_blocks(const Inst& I, int tile_x, int layers) {
+    const int nz = layers > 0 && layers < I.nz ? layers : I.nz;
     int n;
     if (tile_x == 0) {
-        n = ((I.nx * I.ny + 255) / 256) * I.nz;
+        n = ((I.nx * I.ny + 255) / 256) * nz;
     } else {
         const int ty = 256 / tile_x;
-        n = ((I.nx + tile_x - 1) / tile_x) * ((I.ny + ty - 1) / ty) * I.nz;
+        n = ((I.nx + tile_x - 1) / tile_x) * ((I.ny + ty - 1) / ty) * nz;
     }
     return (n + 7) / 8 * 8;
 }
 
 namespace {
 template <typename S, int TX, bool NT>
-void bulk_one(const Inst& I, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    const dim3 g(bulk_blocks(I, TX)), b(256);
+void bulk_one(const Inst& I, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1, int layers) {
+    const dim3 g(bulk_blocks(I, TX, layers)), b(256);
     const bool px = I.periodic & 1;
     if (I.wall_moving && px)
         hipExtLaunchKernelGGL((k_sweep_bulk<S, TX, true, NT, true>), g, b, 0, s, e0, e1, 0, I, parity);
@@ -1200,42 +1201,44 @@ void bulk_batch(const BatchGrid& G, int parity, hipStream_t s, hipEvent_t e0, hi
                           parity);
 }
 template <typename S, int TX, bool NT>
-void bulk_go(const Inst* I, const BatchGrid* G, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    if (I) bulk_one<S, TX, NT>(*I, parity, s, e0, e1);
+void bulk_go(const Inst* I, const BatchGrid* G, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1, int layers) {
+    if (I) bulk_one<S, TX, NT>(*I, parity, s, e0, e1, layers);
     else bulk_batch<S, TX, NT>(*G, parity, s, e0, e1);
 }
 template <typename S, bool NT>
-void bulk_tx(int tile_x, const Inst* I, const BatchGrid* G, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+void bulk_tx(int tile_x, const Inst* I, const BatchGrid* G, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+             int layers) {
     switch (tile_x) {
-    case 32: bulk_go<S, 32, NT>(I, G, parity, s, e0, e1); break;
-    case 128: bulk_go<S, 128, NT>(I, G, parity, s, e0, e1); break;
-    case 0: bulk_go<S, 0, NT>(I, G, parity, s, e0, e1); break;
-    default: bulk_go<S, 64, NT>(I, G, parity, s, e0, e1); break;
+    case 32: bulk_go<S, 32, NT>(I, G, parity, s, e0, e1, layers); break;
+    case 128: bulk_go<S, 128, NT>(I, G, parity, s, e0, e1, layers); break;
+    case 0: bulk_go<S, 0, NT>(I, G, parity, s, e0, e1, layers); break;
+    default: bulk_go<S, 64, NT>(I, G, parity, s, e0, e1, layers); break;
     }
 }
 template <typename S>
 void bulk_nt(int tile_x, bool nt, const Inst* I, const BatchGrid* G, int parity, hipStream_t s, hipEvent_t e0,
-             hipEvent_t e1) {
-    if (nt) bulk_tx<S, true>(tile_x, I, G, parity, s, e0, e1);
-    else bulk_tx<S, false>(tile_x, I, G, parity, s, e0, e1);
+             hipEvent_t e1, int layers) {
+    if (nt) bulk_tx<S, true>(tile_x, I, G, parity, s, e0, e1, layers);
+    else bulk_tx<S, false>(tile_x, I, G, parity, s, e0, e1, layers);
 }
 void bulk_dispatch(int storage, int tile_x, bool nt, const Inst* I, const BatchGrid* G, int parity, hipStream_t s,
-                   hipEvent_t e0, hipEvent_t e1) {
+                   hipEvent_t e0, hipEvent_t e1, int layers) {
     switch (storage) {
-    case LBM_FP16_DEV: bulk_nt<__half>(tile_x, nt, I, G, parity, s, e0, e1); break;
-    case LBM_BF16_DEV: bulk_nt<__hip_bfloat16>(tile_x, nt, I, G, parity, s, e0, e1); break;
-    default: bulk_nt<float>(tile_x, nt, I, G, parity, s, e0, e1); break;
+    case LBM_FP16_DEV: bulk_nt<__half>(tile_x, nt, I, G, parity, s, e0, e1, layers); break;
+    case LBM_BF16_DEV: bulk_nt<__hip_bfloat16>(tile_x, nt, I, G, parity, s, e0, e1, layers); break;
+    default: bulk_nt<float>(tile_x, nt, I, G, parity, s, e0, e1, layers); break;
     }
 }
 }  // namespace
 
-void launch_sweep_bulk(const Inst& I, int parity, int tile_x, bool nt, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    bulk_dispatch(I.storage, tile_x, nt, &I, nullptr, parity, s, e0, e1);
+void launch_sweep_bulk(const Inst& I, int parity, int tile_x, bool nt, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                       int layers) {
+    bulk_dispatch(I.storage, tile_x, nt, &I, nullptr, parity, s, e0, e1, layers);
 }
 
 void launch_sweep_bulk_batch(const BatchGrid& G, int storage, int tile_x, bool nt, int parity, hipStream_t s,
                              hipEvent_t e0, hipEvent_t e1) {
-    bulk_dispatch(storage, tile_x, nt, nullptr, &G, parity, s, e0, e1);
+    bulk_dispatch(storage, tile_x, nt, nullptr, &G, parity, s, e0, e1, 0);
 }
 
 namespace {

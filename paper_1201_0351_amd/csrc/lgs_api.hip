@@ -13,6 +13,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "lgs_internal.h"
@@ -118,6 +119,15 @@ struct InstHost {
     bool any_free;         // some body is integrated on the device
     int remap_blocks;      // workgroups per body of the remap kernels
     size_t offset, bytes;
+    // The bulk sweep's layer bound.  The commit launch of full step m
+    // reports (m << 32) | v into zpin_host, with v at least the highest layer
+    // that may hold fluid after step m - 1.  A step raises that layer by at
+    // most two (its remap refills cells next to fluid, its conversions give
+    // gas cells next to filling cells interface), so the bulk sweep of step
+    // s needs layers 0 .. v + 2 (s - m) + 1 only.  steps counts every step
+    // that advanced the instance.
+    unsigned long long* zpin_host;
+    long long steps;
 };
 
 // Byte layout of one instance inside the workspace.
@@ -250,7 +260,28 @@ struct lbm_ctx {
     hipGraphExec_t gexec = nullptr;
     int gparity = 0;
     std::vector<unsigned char> gremap;  // need_remap of every instance at the start of the graph
+    bool capturing = false;             // run_step launches into a graph capture
 };
+
+// Reports a step may lag behind the host before the host waits for the GPU
+// (the bound then spans at most 2 (LAYER_LAG + 1) + 1 layers over the fluid).
+constexpr unsigned LAYER_LAG = 8;
+
+// Layers the bulk sweep of the instance's next step must cover (0: all).
+static int layer_bound(lbm_ctx* c, const InstHost& h) {
+    if (!h.zpin_host) return 0;
+    for (;;) {
+        const unsigned long long w = *(volatile unsigned long long*)h.zpin_host;
+        const unsigned lag = (unsigned)h.steps - (unsigned)(w >> 32);
+        if (lag <= LAYER_LAG) {
+            const long long top = (long long)(unsigned)w + 2ll * lag + 1;
+            return top + 1 >= h.dev.nz ? 0 : (int)(top + 1);
+        }
+        // the host is ahead: wait for a newer report, unless nothing is queued
+        if (hipStreamQuery(c->stream) == hipSuccess) return 0;
+        std::this_thread::yield();
+    }
+}
 
 // Workspace head of a context: the instance table and two offset arrays.
 size_t ctx_head_bytes(int n) { return align256(sizeof(Inst) * n) + 2 * align256(sizeof(int) * (n + 1)); }
@@ -407,6 +438,24 @@ int32_t lbm_create(const lbm_config* cfgs, int32_t n_inst, void* d_workspace, si
     c->batched = n_inst > 1;
     for (int k = 1; k < n_inst; ++k)
         if (c->inst[k].cfg.storage != c->inst[0].cfg.storage) c->batched = false;
+    // the layer bounds' pinned words, starting from the scanned ztop
+    HIP_OK(hipStreamSynchronize(c->stream));
+    for (int k = 0; k < n_inst; ++k) {
+        InstHost& h = c->inst[k];
+        void* hp = nullptr;
+        void* dp = nullptr;
+        if (hipHostMalloc(&hp, sizeof(unsigned long long), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+            hipHostGetDevicePointer(&dp, hp, 0) != hipSuccess) {
+            if (hp) (void)hipHostFree(hp);
+            (void)hipGetLastError();
+            continue;  // no bound: the bulk sweep covers all layers
+        }
+        int zt = 0;
+        HIP_OK(hipMemcpy(&zt, &h.dev.ctl->ztop, sizeof(int), hipMemcpyDeviceToHost));
+        h.zpin_host = (unsigned long long*)hp;
+        *(volatile unsigned long long*)h.zpin_host = (unsigned long long)(unsigned)zt;
+        h.dev.zpin = (unsigned long long*)dp;
+    }
     rc = upload_batch(c);
     if (rc) return rc;
     *out = c;
@@ -418,6 +467,8 @@ int32_t lbm_destroy(lbm_ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
     if (c->own_ws) (void)hipFree(c->ws);
+    for (InstHost& h : c->inst)
+        if (h.zpin_host) (void)hipHostFree(h.zpin_host);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -688,6 +739,7 @@ static int run_step_batched(lbm_ctx* c) {
     c->last_parity = p;
     c->have_forces = true;
     c->parity ^= 1;
+    for (InstHost& h : c->inst) ++h.steps;
     for (int k = 0; k < n; ++k) {
         InstHost& h = c->inst[k];
         if (!h.any_free || h.cfg.host_body_update == 0) continue;
@@ -704,6 +756,7 @@ static int run_step(lbm_ctx* c, int mask) {
     for (int k = 0; k < c->n_inst; ++k) {
         InstHost& h = c->inst[k];
         bool remapped = false;
+        int layers = 0;  // of the bulk grid (0: all)
         if ((mask & LBM_PHASE_REMAP) && h.need_remap) {
             launch_remap(h.dev, p, h.remap_blocks, c->stream);
             h.need_remap = false;
@@ -713,7 +766,9 @@ static int run_step(lbm_ctx* c, int mask) {
             hipEvent_t e[4];
             int rc = timing_events(c, e);
             if (rc) return rc;
-            launch_sweep_bulk(h.dev, p, c->tile_x, c->nt_store, c->stream, e[0], e[1]);
+            // a full step outside a capture launches the layers its bound needs
+            layers = mask == LBM_PHASE_ALL && !c->capturing ? layer_bound(c, h) : 0;
+            launch_sweep_bulk(h.dev, p, c->tile_x, c->nt_store, c->stream, e[0], e[1], layers);
             if (h.dev.lap != 0.f) launch_curvature(h.dev, p, c->stream);
             launch_sweep_boundary(h.dev, p, c->bnd_layout, c->stream, e[2], e[3]);
         } else if (mask & LBM_PHASE_CONVERT) {
@@ -721,7 +776,9 @@ static int run_step(lbm_ctx* c, int mask) {
             launch_mark(h.dev, p, c->stream);
         }
         const bool integrate = mask == LBM_PHASE_ALL && h.any_free && h.cfg.host_body_update == 0;
-        if (mask & LBM_PHASE_CONVERT) launch_convert(h.dev, p, remapped, integrate, c->stream);
+        if (mask & LBM_PHASE_CONVERT)
+            launch_convert(h.dev, p, remapped, integrate, c->stream,
+                           mask == LBM_PHASE_ALL && !c->capturing ? (unsigned)h.steps : NO_STEP_TAG, layers);
         else if (advances || remapped)
             launch_finish(h.dev, p, (mask & LBM_PHASE_SWEEP) != 0, advances, remapped, c->stream);
         // free bodies moved on the device: the next step maps them
@@ -732,6 +789,7 @@ static int run_step(lbm_ctx* c, int mask) {
         c->last_parity = p;
         c->have_forces = (mask & LBM_PHASE_SWEEP) != 0;
         c->parity ^= 1;
+        for (InstHost& h : c->inst) ++h.steps;
     }
     if (mask == LBM_PHASE_ALL)
         for (int k = 0; k < c->n_inst; ++k) {
@@ -769,8 +827,10 @@ static int graph_two_steps(lbm_ctx* c) {
         c->stream = c->cap_stream;
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+        c->capturing = true;  // all layers, no bound reports: the graph replays with any state
         int rc = e == hipSuccess ? run_step(c, LBM_PHASE_ALL) : LBM_OK;
         if (e == hipSuccess && rc == LBM_OK) rc = run_step(c, LBM_PHASE_ALL);
+        c->capturing = false;
         hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(c->cap_stream, &g) : e;
         c->stream = user;
         if (e != hipSuccess || e2 != hipSuccess)
@@ -791,6 +851,7 @@ static int graph_two_steps(lbm_ctx* c) {
         // replay: the host-side state after two steps
         c->last_parity = c->parity ^ 1;
         c->have_forces = true;
+        for (InstHost& h : c->inst) h.steps += 2;
     }
     HIP_OK(hipGraphLaunch(c->gexec, c->stream));
     return LBM_OK;
@@ -1029,6 +1090,8 @@ static int sync_and_check(lbm_ctx* c) {
         HIP_OK(hipMemcpy(&ov[1], &ctl->cnt[1].overflow, sizeof(int), hipMemcpyDeviceToHost));
         int berr = 0;
         HIP_OK(hipMemcpy(&berr, &ctl->body_err, sizeof(int), hipMemcpyDeviceToHost));
+        if (flags[0] & NONFINITE_LAYERS)
+            return fail(LBM_ERR_DEVICE, "bulk sweep: a launch's layer bound missed a layer holding fluid");
         if (flags[0]) return fail(LBM_ERR_UNSTABLE, "non-finite or non-positive density detected");
         if (berr) {
             std::string why;
@@ -1338,6 +1401,7 @@ int32_t lbm_write_fields(lbm_ctx* c, int32_t inst, int32_t field, int32_t dtype,
         for (size_t k = 0; k < N; ++k)
             if ((a[k] & TYPE_MASK) == LIQ || (a[k] & TYPE_MASK) == IFC) ztop = (int)(k / ((size_t)I.nx * I.ny));
         HIP_OK(hipMemcpy(&I.ctl->ztop, &ztop, sizeof(int), hipMemcpyHostToDevice));
+        if (h.zpin_host) *(volatile unsigned long long*)h.zpin_host = ((unsigned long long)(unsigned)h.steps << 32) | (unsigned)ztop;
         const std::vector<uint8_t> nm = near_marks(I, a);
         HIP_OK(hipMemcpy(I.nearo, nm.data(), N, hipMemcpyHostToDevice));
         // the written obstacle cells are the bodies' mappings at their poses

@@ -129,7 +129,7 @@ struct Ctl {
     double ledger;
     double mass_total;
     unsigned long long contacts;
-    int nonfinite;
+    int nonfinite;  // 1: a non-finite or non-positive density; NONFINITE_LAYERS: a bulk grid missed a fluid layer
     int body_err;  // BODY_ERR_* bits of a rejected free-body update
     // Highest z-layer that may hold a liquid or interface cell or a
     // conversion mark: scanned after init, computed on the host when flags
@@ -141,6 +141,7 @@ struct Ctl {
 
 // Reasons the device update of a free body was rejected (the body keeps its
 // pose; the next synchronising call reports the error).
+constexpr int NONFINITE_LAYERS = 2;
 enum : int { BODY_ERR_WALL = 1, BODY_ERR_SPEED = 2, BODY_ERR_CLOSE = 4, BODY_ERR_JUMP = 8 };
 
 struct DevBody {
@@ -219,6 +220,10 @@ struct Inst {
     // so none does.)
     uint32_t* frec_mask;
     long long* frec_v;
+    // A word of pinned host memory (device-visible) where the conversions'
+    // commit launch of step s reports (s << 32) | ctl->ztop, the layer bound
+    // the host sizes later bulk grids with (nullptr: no report)
+    unsigned long long* zpin;
     // FP64 partial sums of the liquid-mass total, one per chunk of
     // MASS_CHUNK cells (mass_parts(N) of them)
     double* mass_part;
@@ -725,12 +730,14 @@ struct BatchGrid {
 // workgroups of one instance's bulk grid for a tile width (32, 64 or 128
 // cells along x, 256 / width rows; 0: 256 consecutive cells of a layer),
 // padded to a multiple of 8
-int bulk_blocks(const Inst& I, int tile_x);
+int bulk_blocks(const Inst& I, int tile_x, int layers = 0);
 
 // e0 / e1: optional events recorded at the start / end of the kernel itself;
-// nt: non-temporal population stores
+// nt: non-temporal population stores; layers > 0: launch the tiles of layers
+// 0 .. layers-1 only (a bound the host holds on ctl->ztop; the step's claim
+// launch flags a bound that was too low), else all
 void launch_sweep_bulk(const Inst& I, int parity, int tile_x, bool nt, hipStream_t s, hipEvent_t e0 = nullptr,
-                       hipEvent_t e1 = nullptr);
+                       hipEvent_t e1 = nullptr, int layers = 0);
 // Mean curvature of the cells of this step's boundary list (surface tension
 // only; after the bulk sweep, before the boundary sweep).
 void launch_curvature(const Inst& I, int parity, hipStream_t s);
@@ -743,7 +750,12 @@ void launch_sweep_bulk_batch(const BatchGrid& G, int storage, int tile_x, bool n
 void launch_sweep_boundary_batch(const BatchGrid& G, int storage, int parity, int layout, hipStream_t s,
                                  hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void launch_mark(const Inst& I, int parity, hipStream_t s);
-void launch_convert(const Inst& I, int parity, bool retire_moves, bool integrate, hipStream_t s);
+// step_tag: the step's index, reported with ctl->ztop through I.zpin
+// (NO_STEP_TAG: no report); bulk_layers > 0: the step's bulk grid covered
+// layers 0 .. bulk_layers-1 only (checked against ctl->ztop)
+constexpr unsigned NO_STEP_TAG = 0xFFFFFFFFu;
+void launch_convert(const Inst& I, int parity, bool retire_moves, bool integrate, hipStream_t s,
+                    unsigned step_tag = NO_STEP_TAG, int bulk_layers = 0);
 void launch_finish(const Inst& I, int parity, bool reduce, bool zero_other, bool retire_moves, hipStream_t s);
 void launch_remap(const Inst& I, int parity, int blocks_per_body, hipStream_t s);
 // batches of at most 64 instances (bit k of a mask belongs to instance k)

@@ -96,6 +96,7 @@ def fluid_mask(t):
 
 
 def compare_pop(L, o, tol, inst=0, label=""):
+    L.sync()  # raises on the device's error flags (density, lists, the bulk sweep's layer bound)
     tg, to = L.types(inst), o.types()
     agree = (tg == to) & fluid_mask(to)
     fg, fo = L.pop(inst), o.get_f()
