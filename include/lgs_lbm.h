@@ -161,7 +161,10 @@ int32_t lbm_workspace_size(const lbm_config* cfgs, int32_t n_inst, size_t* bytes
  * lifetime), or NULL to let the library allocate and own it.  hip_stream: the
  * hipStream_t all work is ordered on (NULL = null stream).  Checks: tau > 0.5,
  * max_k n_k |a_k| < 0.1 c_s^2 (the incompressibility bound of Sec. 2.1),
- * storage, sizes, eps >= 0, rho_gas > 0. */
+ * storage, sizes, eps >= 0, rho_gas > 0.  Besides the workspace the library
+ * allocates one 8-byte word of pinned host memory per instance, where the
+ * steps report the highest layer that may hold fluid (the bulk sweep's
+ * grid bound); without it the bulk sweep launches every layer. */
 int32_t lbm_create(const lbm_config* cfgs, int32_t n_inst, void* d_workspace, size_t ws_bytes, void* hip_stream,
                    lbm_ctx** out);
 int32_t lbm_destroy(lbm_ctx* ctx);
@@ -185,7 +188,9 @@ int32_t lbm_get_body(lbm_ctx* ctx, int32_t inst, int32_t body, lbm_body* b);
  * unless an instance updates its free bodies on the host.  A free-body update
  * that breaks the lbm_set_body checks is rejected (the body keeps its pose):
  * on the device the next lbm_sync returns LBM_ERR_UNSTABLE naming the reason,
- * on the host lbm_step returns it. */
+ * on the host lbm_step returns it.  Each step's bulk sweep covers the layers
+ * up to a bound the host derives from the reports of earlier steps; the host
+ * waits for the GPU when it runs more than 8 steps ahead of them. */
 int32_t lbm_step(lbm_ctx* ctx, int32_t nsteps);
 
 /* One step restricted to the phases in phase_mask (LBM_PHASE_*), for tests.
@@ -236,7 +241,10 @@ int32_t lbm_conversion_counts(lbm_ctx* ctx, int32_t inst, int64_t counts[4]);
  * layer, Sec. 2.2).  Synchronises. */
 int32_t lbm_liq_gas_contacts(lbm_ctx* ctx, int32_t inst, int64_t* contacts);
 
-/* Wait for all work of the context. */
+/* Wait for all work of the context, then report what the device flagged:
+ * LBM_ERR_UNSTABLE for a non-finite or non-positive density, a rejected
+ * free-body update or a list overflow; LBM_ERR_DEVICE if a bulk sweep's
+ * layer bound missed a layer holding fluid (an internal error). */
 int32_t lbm_sync(lbm_ctx* ctx);
 
 /* Kernel timing: while enabled, HIP start / stop events are attached to the
