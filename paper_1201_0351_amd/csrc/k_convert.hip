@@ -594,11 +594,11 @@ __global__ __launch_bounds__(CT) void k_conv_commit(Inst I, int parity, unsigned
 // masks), blockIdx.x the workgroup of its grid (grids of other sizes: the
 // extra workgroups return)
 template <typename S>
-__global__ __launch_bounds__(CT) void kb_conv_claim(const Inst* __restrict__ tab, int parity) {
+__global__ __launch_bounds__(CT) void kb_conv_claim(const Inst* __restrict__ tab, int parity, const GroupLayers L) {
     const Inst I = tab[blockIdx.y];
     const int nb = conv_blocks(I);
     if ((int)blockIdx.x >= nb) return;
-    conv_claim<S>(I, parity, blockIdx.x, nb);
+    conv_claim<S>(I, parity, blockIdx.x, nb, L.v[blockIdx.y]);
 }
 template <typename S>
 __global__ __launch_bounds__(CT) void kb_conv_middle(const Inst* __restrict__ tab, int parity,
@@ -610,11 +610,11 @@ __global__ __launch_bounds__(CT) void kb_conv_middle(const Inst* __restrict__ ta
     conv_middle<S>(I, parity, blockIdx.x, nb, (retire_mask >> k) & 1ull, (integrate_mask >> k) & 1ull);
 }
 template <typename S>
-__global__ __launch_bounds__(CT) void kb_conv_commit(const Inst* __restrict__ tab, int parity) {
+__global__ __launch_bounds__(CT) void kb_conv_commit(const Inst* __restrict__ tab, int parity, unsigned step_tag) {
     const Inst I = tab[blockIdx.y];
     const int nb = conv_blocks(I);
     if ((int)blockIdx.x >= nb) return;
-    conv_commit<S>(I, parity, blockIdx.x, nb, NO_STEP_TAG);
+    conv_commit<S>(I, parity, blockIdx.x, nb, step_tag);
 }
 
 // End of a step without conversions (phase-isolated calls).
@@ -633,20 +633,24 @@ void convert_one(const Inst& I, int parity, int r, int n, hipStream_t s, unsigne
 }
 template <typename S>
 void convert_batch(const Inst* tab, int n, int blocks, int parity, unsigned long long rm, unsigned long long im,
-                   hipStream_t s) {
+                   hipStream_t s, unsigned step_tag, const GroupLayers& L) {
     const dim3 g(blocks, n), b(CT);
-    hipLaunchKernelGGL(kb_conv_claim<S>, g, b, 0, s, tab, parity);
+    hipLaunchKernelGGL(kb_conv_claim<S>, g, b, 0, s, tab, parity, L);
     hipLaunchKernelGGL(kb_conv_middle<S>, g, b, 0, s, tab, parity, rm, im);
-    hipLaunchKernelGGL(kb_conv_commit<S>, g, b, 0, s, tab, parity);
+    hipLaunchKernelGGL(kb_conv_commit<S>, g, b, 0, s, tab, parity, step_tag);
 }
 }  // namespace
 
 void launch_convert_batch(const Inst* tab, int n, int blocks, int storage, int parity, unsigned long long retire_mask,
-                          unsigned long long integrate_mask, hipStream_t s) {
+                          unsigned long long integrate_mask, hipStream_t s, unsigned step_tag, const int* bulk_layers) {
+    GroupLayers L{};
+    for (int k = 0; k < n && k < 64; ++k) L.v[k] = bulk_layers ? bulk_layers[k] : 0;
     switch (storage) {
-    case LBM_FP16_DEV: convert_batch<__half>(tab, n, blocks, parity, retire_mask, integrate_mask, s); break;
-    case LBM_BF16_DEV: convert_batch<__hip_bfloat16>(tab, n, blocks, parity, retire_mask, integrate_mask, s); break;
-    default: convert_batch<float>(tab, n, blocks, parity, retire_mask, integrate_mask, s); break;
+    case LBM_FP16_DEV: convert_batch<__half>(tab, n, blocks, parity, retire_mask, integrate_mask, s, step_tag, L); break;
+    case LBM_BF16_DEV:
+        convert_batch<__hip_bfloat16>(tab, n, blocks, parity, retire_mask, integrate_mask, s, step_tag, L);
+        break;
+    default: convert_batch<float>(tab, n, blocks, parity, retire_mask, integrate_mask, s, step_tag, L); break;
     }
 }
 

@@ -373,13 +373,23 @@ __global__ __launch_bounds__(256, 8) void k_sweep_bulk(Inst I, int parity) {
 // the copied descriptor needs registers of its own, so no 64-VGPR bound; the
 // collision constants are read from the table where they are used)
 template <typename S, int TX, bool NT>
-__global__ __launch_bounds__(256) void kb_sweep_bulk(const Inst* __restrict__ tab, const int* __restrict__ off, int n,
-                                                     int parity) {
+__device__ __forceinline__ void batch_bulk(const Inst* __restrict__ tab, const int* off, int n, int parity) {
     const int k = batch_instance(off, n, blockIdx.x);
     const Inst I = tab[k];
     const CollideConst& K = tab[k].cc;
     if (I.periodic & 1) sweep_bulk<S, TX, true, NT, true>(I, K, parity, blockIdx.x - off[k], off[k + 1] - off[k]);
     else sweep_bulk<S, TX, true, NT, false>(I, K, parity, blockIdx.x - off[k], off[k + 1] - off[k]);
+}
+template <typename S, int TX, bool NT>
+__global__ __launch_bounds__(256) void kb_sweep_bulk(const Inst* __restrict__ tab, const int* __restrict__ off, int n,
+                                                     int parity) {
+    batch_bulk<S, TX, NT>(tab, off, n, parity);
+}
+// the same with the offsets of a grid cut per instance to its layer bound
+template <typename S, int TX, bool NT>
+__global__ __launch_bounds__(256) void kb_sweep_bulk_cut(const Inst* __restrict__ tab, const BatchOff o, int n,
+                                                         int parity) {
+    batch_bulk<S, TX, NT>(tab, o.off, n, parity);
 }
 
 // ---------------------------------------------------------------------------
@@ -1197,8 +1207,12 @@ void bulk_one(const Inst& I, int parity, hipStream_t s, hipEvent_t e0, hipEvent_
 }
 template <typename S, int TX, bool NT>
 void bulk_batch(const BatchGrid& G, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    hipExtLaunchKernelGGL((kb_sweep_bulk<S, TX, NT>), dim3(G.blocks), dim3(256), 0, s, e0, e1, 0, G.tab, G.off, G.n,
-                          parity);
+    if (G.hoff)
+        hipExtLaunchKernelGGL((kb_sweep_bulk_cut<S, TX, NT>), dim3(G.hoff->off[G.n]), dim3(256), 0, s, e0, e1, 0, G.tab,
+                              *G.hoff, G.n, parity);
+    else
+        hipExtLaunchKernelGGL((kb_sweep_bulk<S, TX, NT>), dim3(G.blocks), dim3(256), 0, s, e0, e1, 0, G.tab, G.off, G.n,
+                              parity);
 }
 template <typename S, int TX, bool NT>
 void bulk_go(const Inst* I, const BatchGrid* G, int parity, hipStream_t s, hipEvent_t e0, hipEvent_t e1, int layers) {

@@ -713,8 +713,22 @@ static int run_step_batched(lbm_ctx* c) {
     hipEvent_t e[4];
     int rc = timing_events(c, e);
     if (rc) return rc;
-    launch_sweep_bulk_batch(BatchGrid{c->d_tab, c->d_bulk_off, n, c->bulk_total}, storage, c->tile_x, c->nt_store, p,
-                            c->stream, e[0], e[1]);
+    // each instance's bulk grid cut to its layer bound (offsets passed by
+    // value); in a capture, or beyond BATCH_OFF_MAX instances, all layers
+    bool cut = !c->capturing && n <= BATCH_OFF_MAX;
+    for (int k = 1; k < n && cut; ++k) cut = c->inst[k].steps == c->inst[0].steps;
+    std::vector<int> layers(n, 0);
+    BatchOff hoff;
+    if (cut) {
+        hoff.off[0] = 0;
+        for (int k = 0; k < n; ++k) {
+            layers[k] = layer_bound(c, c->inst[k]);
+            hoff.off[k + 1] = hoff.off[k] + bulk_blocks(c->inst[k].dev, c->tile_x, layers[k]);
+        }
+    }
+    BatchGrid bulk{c->d_tab, c->d_bulk_off, n, c->bulk_total};
+    if (cut) bulk.hoff = &hoff;
+    launch_sweep_bulk_batch(bulk, storage, c->tile_x, c->nt_store, p, c->stream, e[0], e[1]);
     bool tension = false;
     for (int k = 0; k < n; ++k) tension |= c->inst[k].dev.lap != 0.f;
     if (tension) launch_curvature_batch(BatchGrid{c->d_tab, c->d_bnd_off, n, c->bnd_total}, p, c->stream);
@@ -731,7 +745,8 @@ static int run_step_batched(lbm_ctx* c) {
             if (integrate[k]) im |= 1ull << (k - g);
             blocks = std::max(blocks, conv_blocks(h.dev));
         }
-        launch_convert_batch(c->d_tab + g, ng, blocks, storage, p, rm, im, c->stream);
+        launch_convert_batch(c->d_tab + g, ng, blocks, storage, p, rm, im, c->stream,
+                             cut ? (unsigned)c->inst[0].steps : NO_STEP_TAG, cut ? layers.data() + g : nullptr);
     }
     for (int k = 0; k < n; ++k)
         if (integrate[k]) c->inst[k].need_remap = true;  // the device moved free bodies

@@ -719,12 +719,21 @@ __host__ __device__ inline bool bnd_buf_fits(const Inst& I, size_t elem) {
     return (size_t)Q * I.ps * elem <= 0xFFFFFFFFull && (size_t)I.N * 4 <= 0xFFFFFFFFull;
 }
 
+// A batch's per-instance workgroup offsets passed by value (a bulk grid cut
+// per instance to its layer bound): batches of at most BATCH_OFF_MAX
+// instances.
+constexpr int BATCH_OFF_MAX = 256;
+struct BatchOff {
+    int off[BATCH_OFF_MAX + 1];
+};
+
 struct BatchGrid {
     const Inst* tab;
     const int* off;
     int n;
     int blocks;             // off[n]
     bool buf_fits = false;  // every instance's arrays addressable with 32-bit offsets (boundary sweep)
+    const BatchOff* hoff = nullptr;  // host offsets of a cut bulk grid (blocks = hoff->off[n]), else off
 };
 
 // workgroups of one instance's bulk grid for a tile width (32, 64 or 128
@@ -768,9 +777,15 @@ __host__ __device__ inline int conv_blocks(const Inst& I) {
     const int b = (int)(((long long)I.nx * I.ny + 511) / 512);
     return b < 8 ? 8 : (b > 256 ? 256 : b);
 }
-// blocks: the largest conv_blocks of the batch's instances
+// blocks: the largest conv_blocks of the batch's instances (at most 64);
+// step_tag: as for launch_convert; bulk_layers: each instance's bulk layer
+// count of the step (nullptr or 0: all layers)
+struct GroupLayers {
+    int v[64];
+};
 void launch_convert_batch(const Inst* tab, int n, int blocks, int storage, int parity, unsigned long long retire_mask,
-                          unsigned long long integrate_mask, hipStream_t s);
+                          unsigned long long integrate_mask, hipStream_t s, unsigned step_tag = NO_STEP_TAG,
+                          const int* bulk_layers = nullptr);
 void launch_set_body(const Inst& I, int slot, const DevBody& b, hipStream_t s);
 // Liquid-mass total sum_LIQ rho + sum_IF m in two fixed-order passes: one
 // FP64 partial per chunk of MASS_CHUNK cells into part[0 .. mass_parts(N)),
