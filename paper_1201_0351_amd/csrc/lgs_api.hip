@@ -688,6 +688,22 @@ static int timing_events(lbm_ctx* c, hipEvent_t e[4]) {
     return LBM_OK;
 }
 
+// Each instance's bulk grid cut to its layer bound: the offsets to pass by
+// value and the layer counts.  False (all layers) in a capture, beyond
+// BATCH_OFF_MAX instances, or if the instances' step counts differ.
+static bool batch_cut(lbm_ctx* c, BatchOff& hoff, std::vector<int>& layers) {
+    const int n = c->n_inst;
+    bool cut = !c->capturing && n <= BATCH_OFF_MAX;
+    for (int k = 1; k < n && cut; ++k) cut = c->inst[k].steps == c->inst[0].steps;
+    if (!cut) return false;
+    hoff.off[0] = 0;
+    for (int k = 0; k < n; ++k) {
+        layers[k] = layer_bound(c, c->inst[k]);
+        hoff.off[k + 1] = hoff.off[k] + bulk_blocks(c->inst[k].dev, c->tile_x, layers[k]);
+    }
+    return true;
+}
+
 // A full step of a batched context: every kernel runs once for all
 // instances (remap and conversions in groups of 64 instances).
 static int run_step_batched(lbm_ctx* c) {
@@ -713,19 +729,9 @@ static int run_step_batched(lbm_ctx* c) {
     hipEvent_t e[4];
     int rc = timing_events(c, e);
     if (rc) return rc;
-    // each instance's bulk grid cut to its layer bound (offsets passed by
-    // value); in a capture, or beyond BATCH_OFF_MAX instances, all layers
-    bool cut = !c->capturing && n <= BATCH_OFF_MAX;
-    for (int k = 1; k < n && cut; ++k) cut = c->inst[k].steps == c->inst[0].steps;
     std::vector<int> layers(n, 0);
     BatchOff hoff;
-    if (cut) {
-        hoff.off[0] = 0;
-        for (int k = 0; k < n; ++k) {
-            layers[k] = layer_bound(c, c->inst[k]);
-            hoff.off[k + 1] = hoff.off[k] + bulk_blocks(c->inst[k].dev, c->tile_x, layers[k]);
-        }
-    }
+    const bool cut = batch_cut(c, hoff, layers);
     BatchGrid bulk{c->d_tab, c->d_bulk_off, n, c->bulk_total};
     if (cut) bulk.hoff = &hoff;
     launch_sweep_bulk_batch(bulk, storage, c->tile_x, c->nt_store, p, c->stream, e[0], e[1]);
@@ -1038,12 +1044,18 @@ int32_t lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* tile_x, int32_t* stream_
     auto reset = [&]() {
         for (InstHost& h : c->inst) hipLaunchKernelGGL(k_reset_bnd, dim3(1), dim3(64), 0, c->stream, h.dev.ctl, p);
     };
+    // the candidates sweep the grids the steps launch (cut to the layer bounds)
     auto sweep = [&]() {
-        if (c->batched)
-            launch_sweep_bulk_batch(BatchGrid{c->d_tab, c->d_bulk_off, c->n_inst, c->bulk_total},
-                                    c->inst[0].cfg.storage, c->tile_x, c->nt_store, p, c->stream);
-        else
-            for (InstHost& h : c->inst) launch_sweep_bulk(h.dev, p, c->tile_x, c->nt_store, c->stream);
+        if (c->batched) {
+            std::vector<int> layers(c->n_inst, 0);
+            BatchOff hoff;
+            BatchGrid bulk{c->d_tab, c->d_bulk_off, c->n_inst, c->bulk_total};
+            if (batch_cut(c, hoff, layers)) bulk.hoff = &hoff;
+            launch_sweep_bulk_batch(bulk, c->inst[0].cfg.storage, c->tile_x, c->nt_store, p, c->stream);
+        } else {
+            for (InstHost& h : c->inst)
+                launch_sweep_bulk(h.dev, p, c->tile_x, c->nt_store, c->stream, nullptr, nullptr, layer_bound(c, h));
+        }
     };
     for (int cand = 0; cand < 8 && rc == LBM_OK; ++cand) {
         c->tile_x = widths[cand % 4];
