@@ -278,7 +278,8 @@ static int layer_bound(lbm_ctx* c, const InstHost& h) {
             return top + 1 >= h.dev.nz ? 0 : (int)(top + 1);
         }
         // the host is ahead: wait for a newer report, unless nothing is queued
-        if (hipStreamQuery(c->stream) == hipSuccess) return 0;
+        // (or the stream failed, which the next sync reports)
+        if (hipStreamQuery(c->stream) != hipErrorNotReady) return 0;
         std::this_thread::yield();
     }
 }
