@@ -75,6 +75,7 @@ SWEEP_SOURCES = ("paper_1201_0351_amd/csrc/k_sweep.hip", "paper_1201_0351_amd/cs
 PREP_STEPS = 200
 WINDOWS = 5
 EVENT_STEPS = 500
+TUNE_REPS = 16  # autotuner launches per candidate (candidates lie within a few percent)
 STORAGE_BYTES = {"fp32": 4, "fp16": 2, "bf16": 2}
 KERNEL_NAMES = {"fp32": "float", "fp16": "__half", "bf16": "__hip_bfloat16"}
 
@@ -157,7 +158,7 @@ def run_case(workload, storage, steps, warmup, free=True, host_update=0, prep=0,
         L = _lattice(workload, storage, free, host_update)
         if prep:
             L.step(prep)
-        t = L.autotune(4)
+        t = L.autotune(TUNE_REPS)
         tuned = dict(tile_x=t["tile_x"], stream_store=t["stream_store"], boundary_layout=t["boundary_layout"])
         L.close()
 
@@ -339,7 +340,7 @@ def run_batch(storage, steps, warmup, batched=True, graph=False):
         L.set_body(0, i["bodies"][0], inst=k)
     L.set_tuning(batched=int(batched), use_graph=int(graph))
     L.step(2)
-    tuned = L.autotune(4)
+    tuned = L.autotune(TUNE_REPS)
     dt = _timed(L, steps, warmup)
     cells = sum(L.ncells(k) for k in range(len(insts)))
     res = dict(instances=len(insts), cells=cells, steps=steps, ms_per_step=round(1e3 * dt / steps, 4),

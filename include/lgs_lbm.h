@@ -270,7 +270,8 @@ int32_t lbm_kernel_time(lbm_ctx* ctx, int32_t kernel, double* total_ms, int64_t*
  * when the step parity or the set of instances that remap changes.
  * stream_store: 1 = the bulk sweep writes the populations with
  * non-temporal (streaming) stores that pass the caches: faster once the
- * populations of a step exceed the 256 MiB cache in front of HBM, slower
+ * populations a step moves (both lattices over the layers up to the bulk
+ * sweep's layer bound) exceed the 256 MiB cache in front of HBM, slower
  * below it (the default follows that size).
  * boundary_layout: work layout of the boundary sweep (interface cells and
  * liquid cells next to gas or a body): 0 = 8 lanes per cell, the links
@@ -285,7 +286,9 @@ int32_t lbm_get_tuning(lbm_ctx* ctx, int32_t* tile_x, int32_t* batched, int32_t*
 
 /* Autotuner.  First the bulk sweep: reps launches on the current state for
  * every tile width (32, 64, 128, and 0: packed rows) and store policy
- * (cached, streaming), the fastest of the eight kept.  Then the boundary sweep: reps launches with each
+ * (cached, and streaming where a step's populations exceed the 256 MiB
+ * cache; below it the trials, which sweep one cached source, would favour
+ * streaming stores), the fastest kept.  Then the boundary sweep: reps launches with each
  * work layout, the faster kept (skipped, layout unchanged and boundary_ms
  * -1, when the device has no room for a copy of the interface cells' mass,
  * flags and counters, 9 bytes per cell).  The state does not change: the

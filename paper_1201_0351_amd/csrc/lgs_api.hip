@@ -284,6 +284,21 @@ static int layer_bound(lbm_ctx* c, const InstHost& h) {
     }
 }
 
+// Population bytes the bulk sweeps of a step move: 2 Q values per cell of
+// the layers up to each instance's bound.  Streaming stores pass the caches,
+// which is faster once these exceed the 256 MiB cache in front of HBM and
+// slower below it (the next step's source then stays cached).
+constexpr double CACHE_BYTES = 256.0 * (1 << 20);
+static double moved_bytes(lbm_ctx* c) {
+    double b = 0.0;
+    for (const InstHost& h : c->inst) {
+        const int L = layer_bound(c, h);
+        const double layers = L > 0 ? L : h.dev.nz;
+        b += 2.0 * Q * (double)h.dev.nx * (double)h.dev.ny * layers * (double)storage_bytes(h.cfg.storage);
+    }
+    return b;
+}
+
 // Workspace head of a context: the instance table and two offset arrays.
 size_t ctx_head_bytes(int n) { return align256(sizeof(Inst) * n) + 2 * align256(sizeof(int) * (n + 1)); }
 
@@ -430,12 +445,7 @@ int32_t lbm_create(const lbm_config* cfgs, int32_t n_inst, void* d_workspace, si
     // lattice's (measured at least as fast as the rectangular tiles on every
     // workload here, 9-21% faster on the batch of uneven lattices).
     c->tile_x = 0;
-    // Streaming stores pass the caches: faster once the populations a step
-    // moves exceed the 256 MiB cache in front of HBM, slower below it.
-    double pop_bytes = 0.0;
-    for (int k = 0; k < n_inst; ++k)
-        pop_bytes += 2.0 * Q * (double)c->inst[k].dev.N * (double)storage_bytes(c->inst[k].cfg.storage);
-    c->nt_store = pop_bytes > 256.0 * (1 << 20);
+    c->nt_store = false;  // set from the layer bounds below
     c->batched = n_inst > 1;
     for (int k = 1; k < n_inst; ++k)
         if (c->inst[k].cfg.storage != c->inst[0].cfg.storage) c->batched = false;
@@ -457,6 +467,7 @@ int32_t lbm_create(const lbm_config* cfgs, int32_t n_inst, void* d_workspace, si
         *(volatile unsigned long long*)h.zpin_host = (unsigned long long)(unsigned)zt;
         h.dev.zpin = (unsigned long long*)dp;
     }
+    c->nt_store = moved_bytes(c) > CACHE_BYTES;
     rc = upload_batch(c);
     if (rc) return rc;
     *out = c;
@@ -1058,7 +1069,13 @@ int32_t lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* tile_x, int32_t* stream_
                 launch_sweep_bulk(h.dev, p, c->tile_x, c->nt_store, c->stream, nullptr, nullptr, layer_bound(c, h));
         }
     };
+    // Streaming-store candidates only where a step's populations exceed the
+    // cache: below it, repeated sweeps of one source favour them (their
+    // writes leave that source cached, while a step's next source, written
+    // with streaming stores, is not).
+    const bool try_nt = moved_bytes(c) > CACHE_BYTES;
     for (int cand = 0; cand < 8 && rc == LBM_OK; ++cand) {
+        if (cand >= 4 && !try_nt) break;
         c->tile_x = widths[cand % 4];
         c->nt_store = cand >= 4;
         rc = upload_batch(c);

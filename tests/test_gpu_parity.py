@@ -1216,10 +1216,11 @@ def test_graph_replay_with_surface_tension(lbm):
 
 
 def test_autotune_keeps_state(lbm):
-    """The autotuner sweeps the current state for every tile width, store
-    policy and boundary-sweep layout without changing it: afterwards the
-    context advances exactly like an untouched one on the same layout (held
-    bodies, bit for bit), also with streaming stores."""
+    """The autotuner sweeps the current state for every tile width and
+    boundary-sweep layout without changing it: afterwards the context
+    advances exactly like an untouched one on the same layout (held bodies,
+    bit for bit), also with streaming stores.  These lattices move far less
+    than the 256 MiB cache per step, so only cached stores are tried."""
     cfgs = [W.basin((64, 40, 36), 18.0, 0.6, 1e-5, seed=41, noise_amp=1e-4),
             W.basin((96, 32, 30), 15.0, 0.6, 1e-5, seed=42, noise_amp=1e-4)]
     A = lbm.Lattice([dict(c, max_bodies=1) for c in cfgs])
@@ -1229,7 +1230,7 @@ def test_autotune_keeps_state(lbm):
         L.step(7)
     t = A.autotune(reps=3)
     say("autotune: %s" % t)
-    assert t["tile_x"] in (0, 32, 64, 128) and t["stream_store"] in (0, 1) and t["bulk_ms"] > 0
+    assert t["tile_x"] in (0, 32, 64, 128) and t["stream_store"] == 0 and t["bulk_ms"] > 0
     assert t["boundary_layout"] in (0, 1) and t["boundary_ms"] > 0
     got = A.get_tuning()
     assert (got["tile_x"], got["stream_store"], got["boundary_layout"]) == (t["tile_x"], t["stream_store"],
