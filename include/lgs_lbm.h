@@ -190,7 +190,8 @@ int32_t lbm_get_body(lbm_ctx* ctx, int32_t inst, int32_t body, lbm_body* b);
  * on the device the next lbm_sync returns LBM_ERR_UNSTABLE naming the reason,
  * on the host lbm_step returns it.  Each step's bulk sweep covers the layers
  * up to a bound the host derives from the reports of earlier steps; the host
- * waits for the GPU when it runs more than 8 steps ahead of them. */
+ * waits for the GPU when it runs further ahead of them than about 4 GB of
+ * queued bulk-sweep traffic (2 to 8 steps). */
 int32_t lbm_step(lbm_ctx* ctx, int32_t nsteps);
 
 /* One step restricted to the phases in phase_mask (LBM_PHASE_*), for tests.

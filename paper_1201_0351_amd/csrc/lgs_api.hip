@@ -261,11 +261,20 @@ struct lbm_ctx {
     int gparity = 0;
     std::vector<unsigned char> gremap;  // need_remap of every instance at the start of the graph
     bool capturing = false;             // run_step launches into a graph capture
+    unsigned max_lag = 8;               // steps the host may run ahead of the layer reports
 };
 
-// Reports a step may lag behind the host before the host waits for the GPU
-// (the bound then spans at most 2 (LAYER_LAG + 1) + 1 layers over the fluid).
+// Steps a report may lag behind the host before the host waits for the GPU:
+// enough to keep about LAG_BYTES of bulk-sweep traffic queued, 2 to
+// LAYER_LAG.  Each step of lag widens the bound by two layers, which cost
+// their early-exit tiles (a third of the liquid tiles of a batch of small
+// lattices at 8 steps).
 constexpr unsigned LAYER_LAG = 8;
+constexpr double LAG_BYTES = 4e9;
+static unsigned lag_limit(double moved_bytes) {
+    const double n = moved_bytes > 0.0 ? std::ceil(LAG_BYTES / moved_bytes) : (double)LAYER_LAG;
+    return (unsigned)std::min((double)LAYER_LAG, std::max(2.0, n));
+}
 
 // Layers the bulk sweep of the instance's next step must cover (0: all).
 static int layer_bound(lbm_ctx* c, const InstHost& h) {
@@ -273,7 +282,7 @@ static int layer_bound(lbm_ctx* c, const InstHost& h) {
     for (;;) {
         const unsigned long long w = *(volatile unsigned long long*)h.zpin_host;
         const unsigned lag = (unsigned)h.steps - (unsigned)(w >> 32);
-        if (lag <= LAYER_LAG) {
+        if (lag <= c->max_lag) {
             const long long top = (long long)(unsigned)w + 2ll * lag + 1;
             return top + 1 >= h.dev.nz ? 0 : (int)(top + 1);
         }
@@ -467,7 +476,9 @@ int32_t lbm_create(const lbm_config* cfgs, int32_t n_inst, void* d_workspace, si
         *(volatile unsigned long long*)h.zpin_host = (unsigned long long)(unsigned)zt;
         h.dev.zpin = (unsigned long long*)dp;
     }
-    c->nt_store = moved_bytes(c) > CACHE_BYTES;
+    const double moved = moved_bytes(c);
+    c->nt_store = moved > CACHE_BYTES;
+    c->max_lag = lag_limit(moved);
     rc = upload_batch(c);
     if (rc) return rc;
     *out = c;
@@ -1073,7 +1084,9 @@ int32_t lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* tile_x, int32_t* stream_
     // cache: below it, repeated sweeps of one source favour them (their
     // writes leave that source cached, while a step's next source, written
     // with streaming stores, is not).
-    const bool try_nt = moved_bytes(c) > CACHE_BYTES;
+    const double moved = moved_bytes(c);
+    const bool try_nt = moved > CACHE_BYTES;
+    c->max_lag = lag_limit(moved);
     for (int cand = 0; cand < 8 && rc == LBM_OK; ++cand) {
         if (cand >= 4 && !try_nt) break;
         c->tile_x = widths[cand % 4];
