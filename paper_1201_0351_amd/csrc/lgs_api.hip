@@ -282,7 +282,10 @@ static int layer_bound(lbm_ctx* c, const InstHost& h) {
     for (;;) {
         const unsigned long long w = *(volatile unsigned long long*)h.zpin_host;
         const unsigned lag = (unsigned)h.steps - (unsigned)(w >> 32);
-        if (lag <= c->max_lag) {
+        // one launch per instance of a batch: the host's launches bound the
+        // step, so it keeps the deepest queue
+        const unsigned lim = c->n_inst > 1 && !c->batched ? LAYER_LAG : c->max_lag;
+        if (lag <= lim) {
             const long long top = (long long)(unsigned)w + 2ll * lag + 1;
             return top + 1 >= h.dev.nz ? 0 : (int)(top + 1);
         }
