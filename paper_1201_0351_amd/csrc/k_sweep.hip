@@ -306,13 +306,14 @@ struct BulkTiles {
 template <typename S, int TX, bool W, bool NT, bool PX>
 __device__ __forceinline__ void bulk_tile(const Inst& I, const CollideConst& K, int parity, const BulkTiles<TX>& T,
                                           int z, int c) {
-    const int tx = c % T.tiles_x, ty = c / T.tiles_x;
     int x, y;
     if constexpr (TX == 0) {
-        const int off = tx * 256 + (int)threadIdx.x;
-        y = off / I.nx;
-        x = off - y * I.nx;
+        // one row of tiles per layer: tile c starts at cell 256 c of it
+        const unsigned off = (unsigned)c * 256u + threadIdx.x;
+        y = (int)(off / (unsigned)I.nx);
+        x = (int)off - y * I.nx;
     } else {
+        const int tx = c % T.tiles_x, ty = c / T.tiles_x;
         x = tx * TX + (threadIdx.x % TX);
         y = ty * BulkTiles<TX>::TY + (threadIdx.x / TX);
     }
@@ -348,17 +349,18 @@ __device__ __forceinline__ void bulk_tile(const Inst& I, const CollideConst& K, 
 template <typename S, int TX, bool W, bool NT, bool PX>
 __device__ __forceinline__ void sweep_bulk(const Inst& I, const CollideConst& K, int parity, int b, int nb) {
     const BulkTiles<TX> T(I);
-    const int CH = T.per_layer;
-    const int full = nb / (8 * CH) * (8 * CH);
-    int t = b;
-    if (b < full) {
-        const int xcd = b & 7, kk = b >> 3;
-        t = ((kk / CH) * 8 + xcd) * CH + kk % CH;
+    // unsigned: the divisions by the tile count need no sign fix-ups
+    const unsigned CH = (unsigned)T.per_layer;
+    const unsigned full = (unsigned)nb / (8u * CH) * (8u * CH);
+    unsigned t = (unsigned)b;
+    if (t < full) {
+        const unsigned xcd = t & 7u, kk = t >> 3;
+        t = ((kk / CH) * 8u + xcd) * CH + kk % CH;
     }
-    if (t >= CH * I.nz) return;  // padding of the grid to a multiple of 8
-    const int z = t / CH;
+    if (t >= CH * (unsigned)I.nz) return;  // padding of the grid to a multiple of 8
+    const int z = (int)(t / CH);
     if (z > I.ctl->ztop) return;  // gas (and bodies) only
-    bulk_tile<S, TX, W, NT, PX>(I, K, parity, T, z, t - z * CH);
+    bulk_tile<S, TX, W, NT, PX>(I, K, parity, T, z, (int)(t - (unsigned)z * CH));
 }
 
 // At most 64 VGPRs, so that eight wavefronts fit per SIMD.  W: the lattice
