@@ -200,6 +200,36 @@ def test_run_ahead_matches_stepwise_on_a_large_rising_slab(lbm):
     B.close()
 
 
+def test_batch_run_ahead_matches_single_stepwise(lbm):
+    """Each instance of a batch has its own layer report and its own cut of
+    the bulk grid, passed to the launch by value.  Three rising slabs of
+    different sizes (about 3.5 GB per step together, so the host runs two
+    steps ahead) are stepped 100 times in one call as a batch, and each
+    alone with a sync after every step; every instance must end
+    bit-identical to its single run."""
+    cfgs = [W.basin((1024, 512, 40), 30.0, 0.6, -4e-4, periodic=4),
+            W.basin((512, 512, 40), 20.0, 0.6, -4e-4, periodic=4),
+            W.basin((256, 256, 40), 10.0, 0.6, -4e-4, periodic=4)]
+    say("batch run-ahead rising slabs")
+    A = lbm.Lattice([dict(c, max_bodies=1) for c in cfgs])
+    assert A.get_tuning()["batched"] == 1
+    A.step(100)
+    A.sync()
+    for k, c in enumerate(cfgs):
+        B = lbm.Lattice(dict(c, max_bodies=1))
+        top0 = int(np.where(fluid_mask(B.types()).any(axis=(1, 2)))[0].max())
+        for _ in range(100):
+            B.step(1)
+            B.sync()
+        assert np.array_equal(A.flags(k), B.flags()), k
+        assert np.array_equal(A.pop(k), B.pop()), k
+        top = int(np.where(fluid_mask(B.types()).any(axis=(1, 2)))[0].max())
+        say("  instance %d: top fluid layer %d -> %d" % (k, top0, top))
+        assert top > top0
+        B.close()
+    A.close()
+
+
 @pytest.mark.parametrize("n,periodic,storage", [((130, 20, 18), 0, "fp16"), ((64, 24, 20), 1, "bf16"),
                                                    ((96, 22, 20), 3, "fp16"), ((4, 10, 12), 0, "bf16")])
 def test_bulk_sweep_16bit_shapes(lbm, n, periodic, storage):
