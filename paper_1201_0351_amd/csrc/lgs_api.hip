@@ -128,7 +128,11 @@ struct InstHost {
     // that advanced the instance.
     unsigned long long* zpin_host;
     long long steps;
+    // pinned landing place of a step's force sums and body records for the
+    // host body update (null: pageable copies)
+    unsigned char* cpl_host;
 };
+constexpr size_t CPL_BYTES = sizeof(double) * MAXB * 6 + sizeof(DevBody) * MAXB;
 
 // Byte layout of one instance inside the workspace.
 size_t layout(const lbm_config& c, Inst* I, char* base) {
@@ -465,6 +469,11 @@ int32_t lbm_create(const lbm_config* cfgs, int32_t n_inst, void* d_workspace, si
     HIP_OK(hipStreamSynchronize(c->stream));
     for (int k = 0; k < n_inst; ++k) {
         InstHost& h = c->inst[k];
+        if (h.cfg.host_body_update) {
+            void* cp = nullptr;
+            if (hipHostMalloc(&cp, CPL_BYTES, hipHostMallocDefault) == hipSuccess) h.cpl_host = (unsigned char*)cp;
+            else (void)hipGetLastError();  // pageable copies instead
+        }
         void* hp = nullptr;
         void* dp = nullptr;
         if (hipHostMalloc(&hp, sizeof(unsigned long long), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
@@ -493,8 +502,10 @@ int32_t lbm_destroy(lbm_ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
     if (c->own_ws) (void)hipFree(c->ws);
-    for (InstHost& h : c->inst)
+    for (InstHost& h : c->inst) {
         if (h.zpin_host) (void)hipHostFree(h.zpin_host);
+        if (h.cpl_host) (void)hipHostFree(h.cpl_host);
+    }
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -659,10 +670,22 @@ __global__ void k_copy_state(Inst I, int from);
 // and upload it; the next step maps it.
 static int couple_on_host(lbm_ctx* c, InstHost& h, int p) {
     double acc[MAXB][6];
-    HIP_OK(hipStreamSynchronize(c->stream));
-    HIP_OK(hipMemcpy(acc, &h.dev.ctl->cnt[p].acc[0][0], sizeof acc, hipMemcpyDeviceToHost));
-    int rc = pull_bodies(c, h);
-    if (rc) return rc;
+    int rc = LBM_OK;
+    if (h.cpl_host) {
+        // both copies queued behind the step, one wait for the stream
+        unsigned char* pa = h.cpl_host;
+        unsigned char* pb = h.cpl_host + sizeof acc;
+        HIP_OK(hipMemcpyAsync(pa, &h.dev.ctl->cnt[p].acc[0][0], sizeof acc, hipMemcpyDeviceToHost, c->stream));
+        HIP_OK(hipMemcpyAsync(pb, h.dev.bodies, sizeof(DevBody) * MAXB, hipMemcpyDeviceToHost, c->stream));
+        HIP_OK(hipStreamSynchronize(c->stream));
+        std::memcpy(acc, pa, sizeof acc);
+        std::memcpy(h.bodies, pb, sizeof(DevBody) * MAXB);
+    } else {
+        HIP_OK(hipStreamSynchronize(c->stream));
+        HIP_OK(hipMemcpy(acc, &h.dev.ctl->cnt[p].acc[0][0], sizeof acc, hipMemcpyDeviceToHost));
+        rc = pull_bodies(c, h);
+        if (rc) return rc;
+    }
     for (int b = 0; b < h.dev.nbodies; ++b) {
         DevBody d = h.bodies[b];
         if (!d.active || !d.free_body || !d.dof) continue;
